@@ -1,0 +1,228 @@
+"""The paper's k-space field of a charge streaming along x1 on the grid
+(TEST INFRASTRUCTURE ONLY).
+
+Sec. 2 expresses the on-axis axial field of a point charge q moving at beta
+along x1 on a 2D grid as a k-space integral (Eq. 13; general beta through
+Eqs. 8-9 and the aliased density of App. A):
+
+  E1(i1', i2=0) = -(q/(2 pi)^2) int dk1 (i/[k]_B1) sum_nu S1(k1 + nu k_g1)
+                   * I_nu(k1) exp(i k1 dx1 (i1' + 1/2)),
+  I_nu(k1) = int_{-k_g2/2}^{k_g2/2} dk2 T(k2) X / (X - [k]_E2 [k]_B2),
+  X = [beta (k1 + nu k_g1)]_t^2 - [k]_E1 [k]_B1,
+
+with i1' the E1 index relative to the particle (E1 sits at i1 + 1/2), the
+particle on a node, and T the transverse density factor of the deposit
+(T = 1 for the paper's linear transverse shape, whose aliases sum to 1; the
+quadratic spline sampled at a node gives T = 1 - sin^2(k2 dx2/2)/2).
+
+In normalized variables khat = k1 dx1/2, theta = k2 dx2/2, r = dx2/dx1,
+kappa = dx1/dt this becomes
+
+  E1 dx1 / q = -(1/(2 pi^2 r)) int_{-pi/2}^{pi/2} dkhat (i/sigma1(khat))
+               sum_nu Shat(khat + nu pi) Ihat_nu(khat) exp(i khat (2 i1' + 1))
+
+with sigma1 = [k]_1 dx1/2, Ihat = int dtheta T A/(A - sigma2(theta)^2),
+A = r^2 (tau^2 - sigma1^2), tau = kappa sin(beta (khat + nu pi)/kappa).
+
+The k2 integral is done in closed form (App. D, with the typo 1-A^2 read as
+1-A).  Poles (0 < A < 1 for the Yee transverse operator, 0 < A < pi^2/4 for
+the spectral one) take the causal prescription omega -> omega + i0, i.e.
+A -> A + i0 s with s = sign(sin(beta k1' dt)) (App. D states it for nu = 0:
+k1 > 0 gives -i pi sqrt(A/(1-A))).  The k1 integral is adaptive quadrature
+with breakpoints at every region boundary.
+"""
+import math
+
+import numpy as np
+from scipy import integrate, optimize
+
+from .fit import sym_custom, sym_spectral, sym_yee
+
+
+def shape_hat(khat, order):
+    """Fourier transform of the order-p B-spline: sinc(khat)^(p+1)."""
+    khat = np.asarray(khat, dtype=np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        s = np.where(khat == 0.0, 1.0, np.sin(khat) / np.where(khat == 0.0, 1.0, khat))
+    return s ** (order + 1)
+
+
+def axial_symbol(solver, C=None, kappa=None):
+    if solver == "yee":
+        return sym_yee
+    if solver == "spectral":
+        return sym_spectral
+    if solver == "custom":
+        Cc = np.asarray(C, dtype=np.float64)
+        return lambda k: sym_custom(k, Cc)
+    if solver == "exact":  # [k]_1 = [k1]_t exactly (Sec. 3)
+        return lambda k: kappa * np.sin(np.asarray(k, dtype=np.float64) / kappa)
+    raise ValueError(solver)
+
+
+def transverse_kind(solver):
+    return "spectral" if solver == "spectral" else "yee"
+
+
+def k2_integral(A, s, kind="yee", tpow=0):
+    """Ihat(A) = int_{-pi/2}^{pi/2} dtheta T^tpow A / (A + i0 s - sigma2^2)."""
+    if A == 0.0:
+        return 0.0 + 0.0j
+    if kind == "yee":
+        if A < 0.0 or A > 1.0:
+            base = math.pi * math.sqrt(-A / (1.0 - A)) + 0.0j
+        else:
+            base = -1j * s * math.pi * math.sqrt(A / (1.0 - A))
+        if tpow == 0:
+            return base
+        h = 1.0 - 0.5 * A
+        if tpow == 1:
+            return h * base + 0.5 * math.pi * A
+        if tpow == 2:
+            return h * h * base + h * math.pi * A + 0.25 * A * (math.pi * A - 0.5 * math.pi)
+        raise ValueError(tpow)
+    if kind == "spectral":
+        if tpow != 0:
+            raise ValueError("spectral transverse operator: only T = 1")
+        if A < 0.0:
+            a = -A
+            return 2.0 * math.sqrt(a) * math.atan(math.pi / (2.0 * math.sqrt(a))) + 0.0j
+        rA = math.sqrt(A)
+        if A > math.pi ** 2 / 4.0:
+            return 2.0 * rA * math.atanh(math.pi / (2.0 * rA)) + 0.0j
+        return 2.0 * rA * math.atanh(2.0 * rA / math.pi) - 1j * s * math.pi * rA
+    raise ValueError(kind)
+
+
+class KSpace:
+    """On-axis E1 and self-force of a streaming point charge (2D)."""
+
+    def __init__(self, solver="yee", kappa=4.0, r=1.0, order=2, beta=1.0, C=None, tpow=0, nus=(-1, 0, 1)):
+        self.solver = solver
+        self.kappa = float(kappa)
+        self.r = float(r)
+        self.order = order
+        self.beta = float(beta)
+        self.sigma1 = axial_symbol(solver, C, kappa)
+        self.kind = transverse_kind(solver)
+        self.tpow = tpow
+        self.nus = tuple(nus)
+
+    # X dx1^2/4 on zone nu
+    def xhat(self, kh, nu):
+        tau = self.kappa * np.sin(self.beta * (kh + nu * np.pi) / self.kappa)
+        return tau * tau - self.sigma1(kh) ** 2
+
+    def A(self, kh, nu):
+        return self.r ** 2 * self.xhat(kh, nu)
+
+    def sgn(self, kh, nu):
+        v = math.sin(2.0 * self.beta * (kh + nu * math.pi) / self.kappa)
+        return 1.0 if v > 0 else (-1.0 if v < 0 else 0.0)
+
+    def ihat(self, kh, nu):
+        return k2_integral(float(self.A(kh, nu)), self.sgn(kh, nu), self.kind, self.tpow)
+
+    def breakpoints(self, nu, ngrid=4001):
+        """khat where A = 0, A = 1 (Yee) or A = pi^2/4 (spectral), sin(beta k1' dt) = 0, and 0."""
+        kh = np.linspace(-np.pi / 2, np.pi / 2, ngrid)
+        pts = {0.0}
+        levels = [0.0, 1.0] if self.kind == "yee" else [0.0, np.pi ** 2 / 4.0]
+        for lev in levels:
+            f = lambda k, lev=lev: float(self.A(k, nu)) - lev
+            v = np.array([f(k) for k in kh])
+            for i in range(len(kh) - 1):
+                if v[i] == 0.0:
+                    pts.add(float(kh[i]))
+                elif v[i] * v[i + 1] < 0.0:
+                    pts.add(float(optimize.brentq(f, kh[i], kh[i + 1], xtol=1e-15)))
+        g = lambda k: math.sin(2.0 * self.beta * (k + nu * math.pi) / self.kappa)
+        v = np.array([g(k) for k in kh])
+        for i in range(len(kh) - 1):
+            if v[i] * v[i + 1] < 0.0:
+                pts.add(float(optimize.brentq(g, kh[i], kh[i + 1], xtol=1e-15)))
+        pts = sorted(p for p in pts if -np.pi / 2 < p < np.pi / 2)
+        return [-np.pi / 2] + pts + [np.pi / 2]
+
+    def _integrate(self, fn, nu):
+        bp = self.breakpoints(nu)
+        total = 0.0
+        for a, b in zip(bp[:-1], bp[1:]):
+            if b - a < 1e-14:
+                continue
+            v, _ = integrate.quad(fn, a, b, limit=400, epsabs=1e-14, epsrel=1e-11)
+            total += v
+        return total
+
+    def e1(self, i1rel):
+        """E1 dx1 / q at E1 index i1' relative to the particle (on axis)."""
+        out = []
+        for ip in np.atleast_1d(i1rel):
+            ph = 2.0 * float(ip) + 1.0
+            tot = 0.0
+            for nu in self.nus:
+                def fn(kh, nu=nu):
+                    s1 = float(self.sigma1(kh))
+                    if s1 == 0.0:
+                        return 0.0
+                    val = (1j / s1) * float(shape_hat(kh + nu * np.pi, self.order)) * self.ihat(kh, nu)
+                    return (val * complex(math.cos(ph * kh), math.sin(ph * kh))).real
+                tot += self._integrate(fn, nu)
+            out.append(-tot / (2.0 * np.pi ** 2 * self.r))
+        return np.array(out)
+
+    def self_force(self, gather_order=None):
+        """F1 dx1 / q^2 in the paper's convention (Eqs. 19, 25): the k1-space
+        field weighted by the unaliased gather shape S(k1), no staggering phase."""
+        go = self.order if gather_order is None else gather_order
+        tot = 0.0
+        for nu in self.nus:
+            def fn(kh, nu=nu):
+                s1 = float(self.sigma1(kh))
+                if s1 == 0.0:
+                    return 0.0
+                val = (1j / s1) * float(shape_hat(kh, go)) * float(shape_hat(kh + nu * np.pi, self.order)) * self.ihat(kh, nu)
+                return val.real
+            tot += self._integrate(fn, nu)
+        return -tot / (2.0 * np.pi ** 2 * self.r)
+
+
+# ---- regime thresholds (Sec. 2.2, 2.3, 3) ----------------------------------
+
+def r_crit():
+    """Yee, nu = 0: above this r a space-charge zone can appear (Sec. 2.2)."""
+    return 2.0 / math.sqrt(math.pi ** 2 - 4.0)
+
+
+def kappa_r_yee(r):
+    """kappa_r^2 sin^2(pi / (2 kappa_r)) = 1 + r^-2 (Sec. 2.2)."""
+    f = lambda k: k * k * math.sin(math.pi / (2.0 * k)) ** 2 - (1.0 + r ** -2)
+    return optimize.brentq(f, 1.0 + 1e-12, 100.0, xtol=1e-15)
+
+
+def kappa_r_spectral():
+    """kappa_r^2 sin^2(3 pi / (2 kappa_r)) = pi^2 / 2, r = 1 (Sec. 2.3)."""
+    f = lambda k: k * k * math.sin(1.5 * math.pi / k) ** 2 - math.pi ** 2 / 2.0
+    return optimize.brentq(f, 1.6, 10.0, xtol=1e-15)
+
+
+def kappa_r_custom():
+    """sin^2(3 pi / (2 kappa_r)) - sin^2(pi / (2 kappa_r)) = 1 / kappa_r^2 (Sec. 3)."""
+    f = lambda k: math.sin(1.5 * math.pi / k) ** 2 - math.sin(0.5 * math.pi / k) ** 2 - 1.0 / k ** 2
+    return optimize.brentq(f, 1.6, 10.0, xtol=1e-15)
+
+
+def regime_nu0(ks, ngrid=20001):
+    """Classify zone nu = 0 from the symbols alone: 'cerenkov' if 0 < A < 1
+    for every khat in (0, pi/2], 'space-charge' if never, else 'mixed'."""
+    kh = np.linspace(1e-6, np.pi / 2, ngrid)
+    A = ks.A(kh, 0)
+    if ks.kind == "yee":
+        pole = (A > 0.0) & (A < 1.0)
+    else:
+        pole = (A > 0.0) & (A < np.pi ** 2 / 4.0)
+    if pole.all():
+        return "cerenkov"
+    if not pole.any():
+        return "space-charge"
+    return "mixed"
