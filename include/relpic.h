@@ -1,0 +1,214 @@
+/*
+ * relpic.h -- C ABI of the MI355X (gfx950) electromagnetic PIC step for
+ * relativistic beams.
+ *
+ * Method: Xu et al., "On numerical errors to the fields surrounding a
+ * relativistically moving particle in PIC codes".  One step is the PIC cycle
+ * of Sec. 1: charge-conserving current deposit with the quadratic B-spline
+ * shape, Maxwell field advance (Eq. 1) with the Yee operators (Eq. 14) or the
+ * customized axial operator of Sec. 3 / App. C, field gather, and the
+ * relativistic Boris push.
+ *
+ * Conventions
+ *   Units: c = 1, d_t E = curl B - J, div E = rho (Eqs. 1, 5).
+ *   Lattice (node = integer index): E1 (i1+1/2,i2,i3), E2 (i1,i2+1/2,i3),
+ *     E3 (i1,i2,i3+1/2), B1 (i1,i2+1/2,i3+1/2), B2 (i1+1/2,i2,i3+1/2),
+ *     B3 (i1+1/2,i2+1/2,i3); J like E; rho at nodes.  In 2D i3 is absent.
+ *   Field arrays exchanged with the caller are dense, x1 fastest:
+ *     index = i1 + n1 * (i2 + n2 * i3), with i1 counted from the first cell
+ *     of the (possibly moving) window.
+ *   Particle positions are (cell, offset): cell = nearest node (x1 global,
+ *     i.e. counted from the window's starting position at t = 0), offset in
+ *     [-1/2, 1/2) in cell units; momenta u = gamma * beta.
+ *   Axial operators (App. C):
+ *     d+ f_i = (1/dx1) sum_{l=1..M} C_l (f_{i+l} - f_{i-l+1})   (E -> B)
+ *     d- f_i = (1/dx1) sum_{l=1..M} C_l (f_{i+l-1} - f_{i-l})   (B -> E)
+ *     M = 1, C_1 = 1 is Yee.  x2 and x3 always use the Yee difference.
+ *
+ * Ownership: every pointer argument is caller-owned; the library copies what
+ * it needs before returning.  Host pointers are host memory unless a name
+ * says "device".  Handles are not thread-safe: one handle per host thread and
+ * stream.  No C++ exception or abort crosses this boundary; every call
+ * returns a relpic_status and relpic_last_error() describes the last failure
+ * on the calling thread.
+ */
+#ifndef RELPIC_H
+#define RELPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RELPIC_OK = 0,
+  RELPIC_EINVAL = 1,    /* malformed argument or descriptor */
+  RELPIC_EUNSTABLE = 2, /* time step violates the operators' Courant limit */
+  RELPIC_ERANGE = 3,    /* particle or index outside the grid / capacity */
+  RELPIC_ENOMEM = 4,    /* device allocation failed */
+  RELPIC_EDEVICE = 5,   /* HIP runtime error, or a kernel raised the error word */
+  RELPIC_ESTATE = 6     /* call not valid in the object's current state */
+} relpic_status;
+
+typedef enum { RELPIC_FP32 = 0, RELPIC_FP64 = 1 } relpic_precision;
+
+typedef enum { RELPIC_BC_PERIODIC = 0, RELPIC_BC_WINDOW = 1 } relpic_bc;
+
+typedef enum {
+  RELPIC_E1 = 0, RELPIC_E2, RELPIC_E3,
+  RELPIC_B1, RELPIC_B2, RELPIC_B3,
+  RELPIC_J1, RELPIC_J2, RELPIC_J3
+} relpic_field;
+
+/* Grid.  ndim 2 or 3; n[d], dx[d] for d < ndim (others ignored); dt the time
+ * step.  bc1 is the x1 boundary: periodic, or a window moving along +x1 at
+ * window_speed (units of c) that advances one cell each time
+ * floor(steps * window_speed * dt / dx1) grows; fields outside the window are
+ * zero and particles whose cell leaves [2, n1 - 3] of the window are dropped.
+ * x2 and x3 are periodic. */
+typedef struct {
+  int ndim;
+  int64_t n[3];
+  double dx[3];
+  double dt;
+  int bc1;
+  double window_speed;
+} relpic_grid;
+
+/* Axial operator: M coefficients C[0..M-1] (C_1..C_M of App. C).  M = 1 with
+ * C = NULL or C[0] = 1 is the Yee solver.  For M > 1 the library also applies
+ * the current correction J1 <- G * J1 (G the inverse of the telescoped
+ * stencil) so that the discrete Gauss law holds with the customized
+ * divergence (Sec. 3). */
+typedef struct {
+  int M;
+  const double *C;
+} relpic_solver;
+
+typedef void *(*relpic_alloc_fn)(size_t bytes, void *user);
+typedef void (*relpic_free_fn)(void *device_ptr, void *user);
+
+/* Device binding.  stream is a hipStream_t (NULL = the null stream).  If alloc
+ * is non-NULL all device memory comes from alloc/free (e.g. PyTorch's caching
+ * allocator); otherwise hipMalloc/hipFree. */
+typedef struct {
+  int device;
+  void *stream;
+  relpic_alloc_fn alloc;
+  relpic_free_fn free;
+  void *user;
+} relpic_device;
+
+typedef struct relpic_sim relpic_sim;
+
+/* FP64 diagnostics (a7), computed on the GPU in FP64 in either precision.
+ * w_field = 1/2 sum (E^2 + B^2) dV; w_kin = sum over alive macro-particles of
+ * (Q / (q/m)) (gamma - 1); gauss_max = max |d- . E - rho - rho_bg| over the
+ * interior nodes (customized divergence for M > 1; the window's 2M + 2 edge
+ * cells are excluded); rho_max = max |rho| of the particles (the scale for
+ * gauss_max); charge = sum rho dV of the particles. */
+typedef struct {
+  int64_t step;
+  int64_t window_start;
+  int64_t n_alive;
+  double time;
+  double w_field;
+  double w_kin;
+  double gauss_max;
+  double rho_max;
+  double charge;
+  int32_t error_word; /* bit 0: a particle moved more than one cell; bit 1: NaN momentum */
+} relpic_diag;
+
+/* App. C: constrained least-squares fit of M axial coefficients to the
+ * leapfrog operator [k1]_t = sin(k1 dt/2)/(dt/2) at kappa = dx1/dt, with
+ * consistency order p (even), super-Gaussian weight FWHM wk1 (in units of
+ * k_g1) and exponent nsg.  C_out: caller-owned, length M.  max_rel_err_out
+ * (nullable): max relative symbol error for k1 dx1/2 <= 1. */
+relpic_status relpic_fit_coefficients(double kappa, int M, int p, double wk1, double nsg, double *C_out,
+                                      double *max_rel_err_out);
+
+/* Create a simulation.  Returns RELPIC_EUNSTABLE if
+ * (dt/2)^2 * max_k sum_d [k]_d^2 >= 1 for the chosen operators. */
+relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver, relpic_precision prec,
+                            const relpic_device *dev, relpic_sim **out);
+
+relpic_status relpic_destroy(relpic_sim *sim);
+
+/* Add a particle species with charge-to-mass ratio q_over_m (electrons: -1),
+ * charge Q of one macro-particle and room for `capacity` particles. */
+relpic_status relpic_add_species(relpic_sim *sim, double q_over_m, double Q, int64_t capacity, int *species_id);
+
+/* Append n particles (host arrays): cell [n][ndim] int32, offset [n][ndim]
+ * in [-1/2, 1/2), u [n][3].  Rounded to FP32 in FP32 mode.  RELPIC_ERANGE if
+ * a cell lies outside the grid (window: outside [2, n1 - 3] of the current
+ * window) or the capacity is exceeded. */
+relpic_status relpic_load_particles(relpic_sim *sim, int species, int64_t n, const int32_t *cell,
+                                    const double *offset, const double *u);
+
+/* Plasma injection at every window shift into the slab at window cell n1 - 3:
+ * ppc[d] particles per cell per dimension on a regular sub-lattice
+ * (offsets (a + 1/2)/ppc - 1/2), momenta uth * N(0,1) per component drawn
+ * from splitmix64 stream `seed` (counter = running injected-particle index *
+ * 3 + component, Box-Muller on consecutive uniforms). */
+relpic_status relpic_set_injection(relpic_sim *sim, int species, const int *ppc, double uth, uint64_t seed);
+
+/* Immobile background charge density (node-centred, dense layout above,
+ * window-relative), added to rho in the Gauss diagnostic. */
+relpic_status relpic_set_background_rho(relpic_sim *sim, const double *rho, int64_t count);
+
+/* Enqueue nsteps PIC steps on the bound stream (asynchronous). */
+relpic_status relpic_step(relpic_sim *sim, int64_t nsteps);
+
+/* Wait for the bound stream; returns RELPIC_EDEVICE if a kernel set the error word. */
+relpic_status relpic_sync(relpic_sim *sim);
+
+/* Copy a field to host FP64 (synchronizing); count must equal n1*n2*n3. */
+relpic_status relpic_read_field(relpic_sim *sim, relpic_field f, double *host, int64_t count);
+
+/* Overwrite a field from host FP64 (synchronizing). */
+relpic_status relpic_write_field(relpic_sim *sim, relpic_field f, const double *host, int64_t count);
+
+/* Device address and element size (4 or 8) of a field array in storage
+ * order; with the moving window the x1 index of storage is (global mod n1). */
+relpic_status relpic_field_device_ptr(relpic_sim *sim, relpic_field f, void **device_ptr, int *elem_bytes);
+
+/* Copy particles of a species to host (synchronizing).  cell [cap][ndim]
+ * (x1 global), offset [cap][ndim], u [cap][3], alive [cap]; *n_out = number
+ * of particle slots (alive or dropped). */
+relpic_status relpic_read_particles(relpic_sim *sim, int species, int64_t cap, int32_t *cell, double *offset,
+                                    double *u, uint8_t *alive, int64_t *n_out);
+
+/* FP64 diagnostics (synchronizing). */
+relpic_status relpic_diagnostics(relpic_sim *sim, relpic_diag *out);
+
+/* Current step count and window start (host-side bookkeeping, no sync). */
+relpic_status relpic_get_step(relpic_sim *sim, int64_t *step, int64_t *window_start);
+
+/* Half-width of the FIR J1 correction along x1 (0 for Yee). */
+relpic_status relpic_correction_halfwidth(relpic_sim *sim, int *halfwidth);
+
+/* Per-kernel timing with HIP events recorded on the bound stream around every
+ * launch (adds a small gap between launches; off by default).  Kernel classes:
+ * 0 push+deposit, 1 J1 correction, 2 B half step, 3 E step, 4 window shift
+ * and injection. */
+#define RELPIC_NUM_KERNEL_CLASSES 5
+typedef struct {
+  int64_t launches[RELPIC_NUM_KERNEL_CLASSES];
+  double total_ms[RELPIC_NUM_KERNEL_CLASSES];
+} relpic_profile;
+
+/* Enable (1) or disable (0) per-kernel timing; enabling clears the totals. */
+relpic_status relpic_profile_enable(relpic_sim *sim, int on);
+
+/* Synchronize and return the totals accumulated since enabling. */
+relpic_status relpic_profile_read(relpic_sim *sim, relpic_profile *out);
+
+const char *relpic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RELPIC_H */

@@ -1,0 +1,738 @@
+// C ABI and host engine of relpic: owns the device arrays of one simulation,
+// validates descriptors, and enqueues the per-step kernel sequence on the
+// caller's stream:
+//   push+deposit (per species) -> [J1 correction] -> B half -> E -> B half
+//   -> [window shift: zero the new leading slab, inject plasma]
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/relpic.h"
+#include "kernels.h"
+#include "solver_setup.h"
+
+using namespace relpic;
+
+namespace relpic_host {
+
+struct Species {
+  double qm = -1.0, Q = -1.0;
+  long long cap = 0, n = 0;
+  int *cell = nullptr;
+  void *o[3] = {nullptr, nullptr, nullptr};
+  void *u[3] = {nullptr, nullptr, nullptr};
+  bool inject = false;
+  int ppc[3] = {1, 1, 1};
+  double uth = 0.0;
+  unsigned long long seed = 0, inj_count = 0;
+};
+
+}  // namespace relpic_host
+
+namespace {
+
+thread_local std::string g_last_error;
+
+relpic_status fail(relpic_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+}  // namespace
+
+using relpic_host::Species;
+
+struct relpic_sim {
+  relpic_grid grid{};
+  int ndim = 2;
+  int n[3] = {1, 1, 1};
+  double dx[3] = {1, 1, 1};
+  relpic_precision prec = RELPIC_FP64;
+  size_t esz = 8;
+  int M = 1;
+  double C[kMaxM] = {1.0};
+  relpic_device dev{};
+  hipStream_t st = nullptr;
+  long long N = 0;
+  void *F[10] = {};  // E1 E2 E3 B1 B2 B3 J1 J2 J3 J1c
+  void *taps = nullptr;
+  int ng = 0;
+  std::vector<Species> sp;
+  long long step = 0, ws = 0;
+  int *err = nullptr;
+  double *dbuf = nullptr;      // diagnostics accumulators (8 doubles)
+  double *rho = nullptr;       // FP64 scratch for the Gauss diagnostic
+  double *rho_bg = nullptr;    // background charge, storage layout
+  std::vector<void *> owned;
+  // per-kernel event timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (class, index of the start event)
+};
+
+namespace {
+
+#define HIP_OK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return fail(RELPIC_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+void *dev_alloc(relpic_sim *s, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  void *p = nullptr;
+  if (s->dev.alloc) {
+    p = s->dev.alloc(bytes, s->dev.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) s->owned.push_back(p);
+  return p;
+}
+
+void dev_free_all(relpic_sim *s) {
+  for (void *p : s->owned) {
+    if (s->dev.free)
+      s->dev.free(p, s->dev.user);
+    else if (!s->dev.alloc)
+      (void)hipFree(p);
+  }
+  s->owned.clear();
+}
+
+Geo make_geo(const relpic_sim *s) {
+  Geo g{};
+  g.n1 = s->n[0];
+  g.n2 = s->n[1];
+  g.n3 = s->n[2];
+  g.window = s->grid.bc1 == RELPIC_BC_WINDOW ? 1 : 0;
+  g.ws_mod = (int)(((s->ws % s->n[0]) + s->n[0]) % s->n[0]);
+  g.N = s->N;
+  return g;
+}
+
+template <typename Real>
+Fields<Real> fields(const relpic_sim *s) {
+  Fields<Real> f;
+  f.E1 = (Real *)s->F[0];
+  f.E2 = (Real *)s->F[1];
+  f.E3 = (Real *)s->F[2];
+  f.B1 = (Real *)s->F[3];
+  f.B2 = (Real *)s->F[4];
+  f.B3 = (Real *)s->F[5];
+  f.J1 = (Real *)s->F[6];
+  f.J2 = (Real *)s->F[7];
+  f.J3 = (Real *)s->F[8];
+  f.J1c = (Real *)s->F[9];
+  return f;
+}
+
+template <typename Real>
+Particles<Real> parts(const Species &sp) {
+  Particles<Real> p;
+  p.cell = sp.cell;
+  p.o1 = (Real *)sp.o[0];
+  p.o2 = (Real *)sp.o[1];
+  p.o3 = (Real *)sp.o[2];
+  p.u1 = (Real *)sp.u[0];
+  p.u2 = (Real *)sp.u[1];
+  p.u3 = (Real *)sp.u[2];
+  p.n = sp.n;
+  return p;
+}
+
+// Bracket one launch with events when profiling is on.
+struct ProfScope {
+  relpic_sim *s;
+  int cls;
+  size_t idx = 0;
+  bool on = false;
+  ProfScope(relpic_sim *s_, int c) : s(s_), cls(c) {
+    if (!s->prof) return;
+    while (s->ev_pool.size() < s->ev_used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      s->ev_pool.push_back(e);
+    }
+    idx = s->ev_used;
+    s->ev_used += 2;
+    on = hipEventRecord(s->ev_pool[idx], s->st) == hipSuccess;
+  }
+  ~ProfScope() {
+    if (!on) return;
+    if (hipEventRecord(s->ev_pool[idx + 1], s->st) == hipSuccess) s->ev_marks.emplace_back(cls, idx);
+  }
+};
+
+long long window_target(const relpic_sim *s, long long steps_done) {
+  return (long long)std::floor((double)steps_done * s->grid.window_speed * s->grid.dt / s->dx[0] + 1e-9);
+}
+
+double cell_volume(const relpic_sim *s) {
+  double v = 1.0;
+  for (int d = 0; d < s->ndim; ++d) v *= s->dx[d];
+  return v;
+}
+
+template <typename Real>
+relpic_status do_steps(relpic_sim *s, long long nsteps) {
+  const double dt = s->grid.dt;
+  const double dV = cell_volume(s);
+  Fields<Real> f = fields<Real>(s);
+  Axial<Real> axB{}, axE{};
+  axB.M = axE.M = s->M;
+  for (int l = 0; l < s->M; ++l) {
+    axB.c[l] = (Real)(s->C[l] * 0.5 * dt / s->dx[0]);
+    axE.c[l] = (Real)(s->C[l] * dt / s->dx[0]);
+  }
+  const Real h2 = (Real)(0.5 * dt / s->dx[1]), h3 = (Real)(s->ndim == 3 ? 0.5 * dt / s->dx[2] : 0.0);
+  const Real e2 = (Real)(dt / s->dx[1]), e3 = (Real)(s->ndim == 3 ? dt / s->dx[2] : 0.0);
+  const bool window = s->grid.bc1 == RELPIC_BC_WINDOW;
+  for (long long it = 0; it < nsteps; ++it) {
+    int shift = 0;
+    if (window) {
+      const long long tgt = window_target(s, s->step + 1);
+      if (tgt - s->ws > 1) return fail(RELPIC_EUNSTABLE, "window moves more than one cell per step");
+      shift = tgt > s->ws ? 1 : 0;
+    }
+    const Geo g = make_geo(s);
+    for (auto &sp : s->sp) {
+      PushParams<Real> q{};
+      q.half_qmdt = (Real)(0.5 * sp.qm * dt);
+      for (int d = 0; d < 3; ++d) q.dtdx[d] = (Real)(d < s->ndim ? dt / s->dx[d] : 0.0);
+      q.f1 = (Real)(-sp.Q * s->dx[0] / (dV * dt));
+      q.f2 = (Real)(-sp.Q * s->dx[1] / (dV * dt));
+      q.f3 = (Real)(s->ndim == 3 ? -sp.Q * s->dx[2] / (dV * dt) : 0.0);
+      q.fv = (Real)(sp.Q / dV);
+      q.shift = shift;
+      ProfScope ps(s, 0);
+      launch_push_deposit<Real>(s->ndim, g, f, parts<Real>(sp), q, s->err, s->st);
+    }
+    const Real *J1src = f.J1;
+    if (s->M > 1) {
+      ProfScope ps(s, 1);
+      launch_jcorr<Real>(g, f.J1, f.J1c, (const Real *)s->taps, s->ng, s->st);
+      J1src = f.J1c;
+    }
+    {
+      ProfScope ps(s, 2);
+      launch_bhalf<Real>(s->ndim, g, f, axB, h2, h3, s->st);
+    }
+    {
+      ProfScope ps(s, 3);
+      launch_efull<Real>(s->ndim, g, f, J1src, axE, e2, e3, (Real)dt, s->st);
+    }
+    {
+      ProfScope ps(s, 2);
+      launch_bhalf<Real>(s->ndim, g, f, axB, h2, h3, s->st);
+    }
+    s->step += 1;
+    if (shift) {
+      ProfScope ps(s, 4);
+      launch_zero_column<Real>(g, f, g.ws_mod, s->st);
+      s->ws += 1;
+      const Geo g2 = make_geo(s);
+      for (auto &sp : s->sp) {
+        if (!sp.inject) continue;
+        const long long nnew = (long long)sp.ppc[0] * sp.ppc[1] * sp.ppc[2] * s->n[1] * s->n[2];
+        if (sp.n + nnew > sp.cap) return fail(RELPIC_ERANGE, "injection exceeds species capacity");
+        launch_inject_slab<Real>(s->ndim, g2, parts<Real>(sp), sp.n, s->n[0] - 3, sp.ppc[0], sp.ppc[1], sp.ppc[2],
+                                 sp.uth, sp.seed, sp.inj_count, s->st);
+        sp.n += nnew;
+        sp.inj_count += (unsigned long long)nnew;
+      }
+    }
+  }
+  HIP_OK(hipGetLastError());
+  return RELPIC_OK;
+}
+
+template <typename Real>
+relpic_status do_diag(relpic_sim *s, relpic_diag *out) {
+  const Geo g = make_geo(s);
+  Fields<Real> f = fields<Real>(s);
+  HIP_OK(hipMemsetAsync(s->dbuf, 0, 8 * sizeof(double), s->st));
+  HIP_OK(hipMemsetAsync(s->rho, 0, sizeof(double) * s->N, s->st));
+  launch_diag_field_energy<Real>(g, f, s->dbuf + 0, s->st);
+  const double dV = cell_volume(s);
+  for (auto &sp : s->sp) {
+    launch_diag_kinetic<Real>(parts<Real>(sp), sp.Q / sp.qm, s->dbuf + 1, (unsigned long long *)(s->dbuf + 5), s->st);
+    launch_diag_rho<Real>(s->ndim, g, parts<Real>(sp), sp.Q / dV, s->rho, s->st);
+  }
+  Axial<double> c1{};
+  c1.M = s->M;
+  for (int l = 0; l < s->M; ++l) c1.c[l] = s->C[l] / s->dx[0];
+  launch_diag_gauss<Real>(s->ndim, g, f, c1, 1.0 / s->dx[1], s->ndim == 3 ? 1.0 / s->dx[2] : 0.0, s->rho, s->rho_bg,
+                          2 * s->M + 2, s->dbuf + 2, s->st);
+  double h[8];
+  int err = 0;
+  HIP_OK(hipMemcpyAsync(h, s->dbuf, sizeof(h), hipMemcpyDeviceToHost, s->st));
+  HIP_OK(hipMemcpyAsync(&err, s->err, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
+  unsigned long long cnt;
+  std::memcpy(&cnt, &h[5], sizeof(cnt));
+  out->step = s->step;
+  out->window_start = s->ws;
+  out->n_alive = (int64_t)cnt;
+  out->time = s->step * s->grid.dt;
+  out->w_field = h[0] * cell_volume(s);
+  out->w_kin = h[1];
+  out->gauss_max = h[2];
+  out->rho_max = h[3];
+  out->charge = h[4] * cell_volume(s);
+  out->error_word = err;
+  return RELPIC_OK;
+}
+
+relpic_status check_sim(relpic_sim *s) {
+  if (!s) return fail(RELPIC_EINVAL, "null simulation handle");
+  return RELPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *relpic_last_error(void) { return g_last_error.c_str(); }
+
+relpic_status relpic_fit_coefficients(double kappa, int M, int p, double wk1, double nsg, double *C_out,
+                                      double *max_rel_err_out) {
+  if (!C_out || M < 1 || M > kMaxM) return fail(RELPIC_EINVAL, "fit: bad M or output pointer");
+  std::vector<double> C;
+  if (!fit_axial_coefficients(kappa, M, p, wk1, nsg, 2048, C)) return fail(RELPIC_EINVAL, "fit: singular or bad parameters");
+  std::copy(C.begin(), C.end(), C_out);
+  if (max_rel_err_out) {
+    double worst = 0.0;
+    for (int q = 1; q <= 2000; ++q) {
+      const double kh = 1.0 * q / 2000;
+      double v = 0.0;
+      for (int l = 1; l <= M; ++l) v += C[l - 1] * std::sin((2 * l - 1) * kh);
+      const double t = kappa * std::sin(kh / kappa);
+      worst = std::max(worst, std::fabs(v - t) / t);
+    }
+    *max_rel_err_out = worst;
+  }
+  return RELPIC_OK;
+}
+
+relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver, relpic_precision prec,
+                            const relpic_device *dev, relpic_sim **out) {
+  if (!grid || !out) return fail(RELPIC_EINVAL, "create: null descriptor");
+  *out = nullptr;
+  if (grid->ndim != 2 && grid->ndim != 3) return fail(RELPIC_EINVAL, "create: ndim must be 2 or 3");
+  if (prec != RELPIC_FP32 && prec != RELPIC_FP64) return fail(RELPIC_EINVAL, "create: bad precision");
+  if (grid->bc1 != RELPIC_BC_PERIODIC && grid->bc1 != RELPIC_BC_WINDOW) return fail(RELPIC_EINVAL, "create: bad bc1");
+  if (!(grid->dt > 0.0)) return fail(RELPIC_EINVAL, "create: dt must be positive");
+  long long N = 1;
+  for (int d = 0; d < grid->ndim; ++d) {
+    if (grid->n[d] < 1 || grid->n[d] > (1 << 24) || !(grid->dx[d] > 0.0))
+      return fail(RELPIC_EINVAL, "create: bad n or dx");
+    N *= grid->n[d];
+  }
+  if (N >= (1LL << 31)) return fail(RELPIC_EINVAL, "create: grid exceeds 2^31 cells");
+  if (grid->n[0] < 8 || grid->n[1] < 2 || (grid->ndim == 3 && grid->n[2] < 2))
+    return fail(RELPIC_EINVAL, "create: grid too small (n1 >= 8, n2, n3 >= 2)");
+  if (grid->n[1] > 65535 || (grid->ndim == 3 && grid->n[2] > 65535))
+    return fail(RELPIC_EINVAL, "create: n2 and n3 are limited to 65535 (launch grid rows)");
+  int M = 1;
+  double C[kMaxM] = {1.0};
+  if (solver && solver->M > 1) {
+    if (solver->M > kMaxM || !solver->C) return fail(RELPIC_EINVAL, "create: bad solver coefficients");
+    M = solver->M;
+    for (int l = 0; l < M; ++l) C[l] = solver->C[l];
+    if (2 * M > grid->n[0]) return fail(RELPIC_EINVAL, "create: stencil wider than the grid");
+  } else if (solver && solver->M == 1 && solver->C) {
+    C[0] = solver->C[0];
+  }
+  if (grid->bc1 == RELPIC_BC_WINDOW) {
+    if (!(grid->window_speed > 0.0) || grid->window_speed * grid->dt >= grid->dx[0])
+      return fail(RELPIC_EINVAL, "create: window must advance less than one cell per step");
+  }
+  const double cn = courant_number(grid->ndim, grid->dx, grid->dt, C, M);
+  if (!(cn < 1.0)) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "create: Courant number %.6f >= 1", cn);
+    return fail(RELPIC_EUNSTABLE, buf);
+  }
+  // every particle moves less than one cell per step only if dt < dx_d
+  for (int d = 0; d < grid->ndim; ++d)
+    if (!(grid->dt < grid->dx[d])) return fail(RELPIC_EUNSTABLE, "create: dt must be below every dx");
+
+  relpic_sim *s = new (std::nothrow) relpic_sim();
+  if (!s) return fail(RELPIC_ENOMEM, "create: host allocation failed");
+  s->grid = *grid;
+  s->ndim = grid->ndim;
+  for (int d = 0; d < 3; ++d) {
+    s->n[d] = d < grid->ndim ? (int)grid->n[d] : 1;
+    s->dx[d] = d < grid->ndim ? grid->dx[d] : 1.0;
+  }
+  s->N = N;
+  s->prec = prec;
+  s->esz = prec == RELPIC_FP32 ? 4 : 8;
+  s->M = M;
+  for (int l = 0; l < M; ++l) s->C[l] = C[l];
+  if (dev) s->dev = *dev;
+  s->st = (hipStream_t)s->dev.stream;
+  if (hipSetDevice(s->dev.device) != hipSuccess) {
+    delete s;
+    return fail(RELPIC_EDEVICE, "create: hipSetDevice failed");
+  }
+  std::vector<double> taps;
+  if (M > 1) {
+    const double tol = prec == RELPIC_FP64 ? 1e-16 : 1e-9;
+    if (!correction_taps(C, M, tol, kMaxTaps, taps)) {
+      delete s;
+      return fail(RELPIC_EINVAL, "create: J1 correction does not converge within the tap limit");
+    }
+    s->ng = (int)taps.size() - 1;
+  }
+  for (int k = 0; k < 10; ++k) {
+    if (k == 9 && M == 1) continue;
+    s->F[k] = dev_alloc(s, s->esz * N);
+    if (!s->F[k]) {
+      dev_free_all(s);
+      delete s;
+      return fail(RELPIC_ENOMEM, "create: field allocation failed");
+    }
+  }
+  s->err = (int *)dev_alloc(s, 64);
+  s->dbuf = (double *)dev_alloc(s, 8 * sizeof(double));
+  s->rho = (double *)dev_alloc(s, sizeof(double) * N);
+  s->taps = dev_alloc(s, s->esz * (kMaxTaps + 1));
+  if (!s->err || !s->dbuf || !s->rho || !s->taps) {
+    dev_free_all(s);
+    delete s;
+    return fail(RELPIC_ENOMEM, "create: allocation failed");
+  }
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 10 && e == hipSuccess; ++k)
+    if (s->F[k]) e = hipMemsetAsync(s->F[k], 0, s->esz * N, s->st);
+  if (e == hipSuccess) e = hipMemsetAsync(s->err, 0, 64, s->st);
+  if (e == hipSuccess && M > 1) {
+    std::vector<unsigned char> host(s->esz * taps.size());
+    for (size_t i = 0; i < taps.size(); ++i) {
+      if (prec == RELPIC_FP32) {
+        float v = (float)taps[i];
+        std::memcpy(&host[i * 4], &v, 4);
+      } else {
+        std::memcpy(&host[i * 8], &taps[i], 8);
+      }
+    }
+    e = hipMemcpyAsync(s->taps, host.data(), host.size(), hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) {
+    dev_free_all(s);
+    delete s;
+    return fail(RELPIC_EDEVICE, std::string("create: ") + hipGetErrorString(e));
+  }
+  *out = s;
+  return RELPIC_OK;
+}
+
+relpic_status relpic_destroy(relpic_sim *sim) {
+  if (!sim) return RELPIC_OK;
+  (void)hipStreamSynchronize(sim->st);
+  for (hipEvent_t e : sim->ev_pool) (void)hipEventDestroy(e);
+  dev_free_all(sim);
+  delete sim;
+  return RELPIC_OK;
+}
+
+relpic_status relpic_add_species(relpic_sim *s, double q_over_m, double Q, int64_t capacity, int *species_id) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (!(q_over_m != 0.0) || !std::isfinite(q_over_m) || !std::isfinite(Q) || capacity < 0 || capacity > (1LL << 31))
+    return fail(RELPIC_EINVAL, "add_species: bad q/m, charge or capacity");
+  Species sp;
+  sp.qm = q_over_m;
+  sp.Q = Q;
+  sp.cap = capacity;
+  const size_t cap = (size_t)std::max<int64_t>(capacity, 1);
+  sp.cell = (int *)dev_alloc(s, sizeof(int) * cap);
+  bool ok = sp.cell != nullptr;
+  for (int d = 0; d < 3 && ok; ++d) {
+    sp.o[d] = (d < s->ndim) ? dev_alloc(s, s->esz * cap) : nullptr;
+    sp.u[d] = dev_alloc(s, s->esz * cap);
+    ok = (d >= s->ndim || sp.o[d]) && sp.u[d];
+  }
+  if (!ok) return fail(RELPIC_ENOMEM, "add_species: allocation failed");
+  s->sp.push_back(sp);
+  if (species_id) *species_id = (int)s->sp.size() - 1;
+  return RELPIC_OK;
+}
+
+relpic_status relpic_load_particles(relpic_sim *s, int species, int64_t n, const int32_t *cell, const double *offset,
+                                    const double *u) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "load: bad species");
+  if (n < 0 || (n > 0 && (!cell || !offset || !u))) return fail(RELPIC_EINVAL, "load: bad arrays");
+  Species &sp = s->sp[species];
+  if (sp.n + n > sp.cap) return fail(RELPIC_ERANGE, "load: capacity exceeded");
+  if (n == 0) return RELPIC_OK;
+  const Geo g = make_geo(s);
+  const int nd = s->ndim;
+  std::vector<int> packed(n);
+  std::vector<double> o64[3], u64[3];
+  for (int d = 0; d < 3; ++d) {
+    o64[d].resize(d < nd ? n : 0);
+    u64[d].resize(n);
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    long long l1 = cell[i * nd + 0];
+    if (g.window) {
+      l1 -= s->ws;
+      if (l1 < 2 || l1 > s->n[0] - 3) return fail(RELPIC_ERANGE, "load: particle outside the window interior");
+    } else if (l1 < 0 || l1 >= s->n[0]) {
+      return fail(RELPIC_ERANGE, "load: x1 cell outside the grid");
+    }
+    const int c2 = cell[i * nd + 1];
+    const int c3 = nd == 3 ? cell[i * nd + 2] : 0;
+    if (c2 < 0 || c2 >= s->n[1] || c3 < 0 || c3 >= s->n[2]) return fail(RELPIC_ERANGE, "load: cell outside the grid");
+    for (int d = 0; d < nd; ++d) {
+      const double o = offset[i * nd + d];
+      if (!(o >= -0.5 && o < 0.5)) return fail(RELPIC_EINVAL, "load: offset outside [-1/2, 1/2)");
+      o64[d][i] = o;
+    }
+    for (int d = 0; d < 3; ++d) {
+      if (!std::isfinite(u[i * 3 + d])) return fail(RELPIC_EINVAL, "load: non-finite momentum");
+      u64[d][i] = u[i * 3 + d];
+    }
+    const int col = (int)((l1 + g.ws_mod) % s->n[0]);
+    packed[i] = col + s->n[0] * (c2 + s->n[1] * c3);
+  }
+  HIP_OK(hipMemcpyAsync(sp.cell + sp.n, packed.data(), sizeof(int) * n, hipMemcpyHostToDevice, s->st));
+  std::vector<float> tmp(s->prec == RELPIC_FP32 ? n : 0);
+  auto put = [&](void *dst, const std::vector<double> &src) -> relpic_status {
+    char *d = (char *)dst + s->esz * sp.n;
+    if (s->prec == RELPIC_FP32) {
+      for (int64_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
+      HIP_OK(hipMemcpyAsync(d, tmp.data(), 4 * n, hipMemcpyHostToDevice, s->st));
+      HIP_OK(hipStreamSynchronize(s->st));
+    } else {
+      HIP_OK(hipMemcpyAsync(d, src.data(), 8 * n, hipMemcpyHostToDevice, s->st));
+      HIP_OK(hipStreamSynchronize(s->st));
+    }
+    return RELPIC_OK;
+  };
+  for (int d = 0; d < nd; ++d)
+    if (relpic_status r = put(sp.o[d], o64[d])) return r;
+  for (int d = 0; d < 3; ++d)
+    if (relpic_status r = put(sp.u[d], u64[d])) return r;
+  sp.n += n;
+  return RELPIC_OK;
+}
+
+relpic_status relpic_set_injection(relpic_sim *s, int species, const int *ppc, double uth, uint64_t seed) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (species < 0 || species >= (int)s->sp.size() || !ppc) return fail(RELPIC_EINVAL, "injection: bad species");
+  if (s->grid.bc1 != RELPIC_BC_WINDOW) return fail(RELPIC_ESTATE, "injection needs the moving window");
+  Species &sp = s->sp[species];
+  for (int d = 0; d < 3; ++d) {
+    sp.ppc[d] = d < s->ndim ? ppc[d] : 1;
+    if (sp.ppc[d] < 1 || sp.ppc[d] > 16) return fail(RELPIC_EINVAL, "injection: ppc must be in 1..16");
+  }
+  sp.inject = true;
+  sp.uth = uth;
+  sp.seed = seed;
+  sp.inj_count = 0;
+  return RELPIC_OK;
+}
+
+relpic_status relpic_set_background_rho(relpic_sim *s, const double *rho, int64_t count) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (!rho || count != s->N) return fail(RELPIC_EINVAL, "background: count must equal the number of cells");
+  if (!s->rho_bg) {
+    s->rho_bg = (double *)dev_alloc(s, sizeof(double) * s->N);
+    if (!s->rho_bg) return fail(RELPIC_ENOMEM, "background: allocation failed");
+  }
+  // window-relative -> storage layout
+  std::vector<double> st((size_t)s->N);
+  const int n1 = s->n[0];
+  const int wsm = make_geo(s).ws_mod;
+  for (long long r = 0; r < s->N / n1; ++r)
+    for (int l = 0; l < n1; ++l) st[r * n1 + (l + wsm) % n1] = rho[r * n1 + l];
+  HIP_OK(hipMemcpyAsync(s->rho_bg, st.data(), sizeof(double) * s->N, hipMemcpyHostToDevice, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
+  return RELPIC_OK;
+}
+
+relpic_status relpic_step(relpic_sim *s, int64_t nsteps) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (nsteps < 0) return fail(RELPIC_EINVAL, "step: negative count");
+  if (s->prec == RELPIC_FP32) return do_steps<float>(s, nsteps);
+  return do_steps<double>(s, nsteps);
+}
+
+relpic_status relpic_sync(relpic_sim *s) {
+  if (relpic_status r = check_sim(s)) return r;
+  int err = 0;
+  HIP_OK(hipMemcpyAsync(&err, s->err, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
+  if (err) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "kernel error word 0x%x (1: moved > 1 cell, 2: NaN momentum)", err);
+    return fail(RELPIC_EDEVICE, buf);
+  }
+  return RELPIC_OK;
+}
+
+relpic_status relpic_read_field(relpic_sim *s, relpic_field f, double *host, int64_t count) {
+  if (relpic_status r = check_sim(s)) return r;
+  if ((int)f < 0 || (int)f > 8 || !host || count != s->N) return fail(RELPIC_EINVAL, "read_field: bad field or count");
+  std::vector<unsigned char> raw(s->esz * s->N);
+  HIP_OK(hipMemcpyAsync(raw.data(), s->F[(int)f], raw.size(), hipMemcpyDeviceToHost, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
+  const int n1 = s->n[0];
+  const int wsm = make_geo(s).ws_mod;
+  for (long long r = 0; r < s->N / n1; ++r)
+    for (int l = 0; l < n1; ++l) {
+      const long long src = r * n1 + (l + wsm) % n1;
+      double v;
+      if (s->esz == 4) {
+        float x;
+        std::memcpy(&x, &raw[src * 4], 4);
+        v = x;
+      } else {
+        std::memcpy(&v, &raw[src * 8], 8);
+      }
+      host[r * n1 + l] = v;
+    }
+  return RELPIC_OK;
+}
+
+relpic_status relpic_write_field(relpic_sim *s, relpic_field f, const double *host, int64_t count) {
+  if (relpic_status r = check_sim(s)) return r;
+  if ((int)f < 0 || (int)f > 8 || !host || count != s->N) return fail(RELPIC_EINVAL, "write_field: bad field or count");
+  std::vector<unsigned char> raw(s->esz * s->N);
+  const int n1 = s->n[0];
+  const int wsm = make_geo(s).ws_mod;
+  for (long long r = 0; r < s->N / n1; ++r)
+    for (int l = 0; l < n1; ++l) {
+      const long long dst = r * n1 + (l + wsm) % n1;
+      const double v = host[r * n1 + l];
+      if (s->esz == 4) {
+        const float x = (float)v;
+        std::memcpy(&raw[dst * 4], &x, 4);
+      } else {
+        std::memcpy(&raw[dst * 8], &v, 8);
+      }
+    }
+  HIP_OK(hipMemcpyAsync(s->F[(int)f], raw.data(), raw.size(), hipMemcpyHostToDevice, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
+  return RELPIC_OK;
+}
+
+relpic_status relpic_field_device_ptr(relpic_sim *s, relpic_field f, void **ptr, int *elem_bytes) {
+  if (relpic_status r = check_sim(s)) return r;
+  if ((int)f < 0 || (int)f > 8 || !ptr) return fail(RELPIC_EINVAL, "field_device_ptr: bad field");
+  *ptr = s->F[(int)f];
+  if (elem_bytes) *elem_bytes = (int)s->esz;
+  return RELPIC_OK;
+}
+
+relpic_status relpic_read_particles(relpic_sim *s, int species, int64_t cap, int32_t *cell, double *offset, double *u,
+                                    uint8_t *alive, int64_t *n_out) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "read_particles: bad species");
+  Species &sp = s->sp[species];
+  if (n_out) *n_out = sp.n;
+  if (cap < sp.n || !cell || !offset || !u || !alive) return fail(RELPIC_ERANGE, "read_particles: buffers too small");
+  const long long n = sp.n;
+  const int nd = s->ndim;
+  std::vector<int> packed(n);
+  HIP_OK(hipMemcpyAsync(packed.data(), sp.cell, sizeof(int) * n, hipMemcpyDeviceToHost, s->st));
+  std::vector<unsigned char> raw(s->esz * std::max<long long>(n, 1));
+  auto get = [&](const void *src, int stride_idx, int stride, double *dst) -> relpic_status {
+    HIP_OK(hipMemcpyAsync(raw.data(), src, s->esz * n, hipMemcpyDeviceToHost, s->st));
+    HIP_OK(hipStreamSynchronize(s->st));
+    for (long long i = 0; i < n; ++i) {
+      double v;
+      if (s->esz == 4) {
+        float x;
+        std::memcpy(&x, &raw[i * 4], 4);
+        v = x;
+      } else {
+        std::memcpy(&v, &raw[i * 8], 8);
+      }
+      dst[i * stride + stride_idx] = v;
+    }
+    return RELPIC_OK;
+  };
+  for (int d = 0; d < nd; ++d)
+    if (relpic_status r = get(sp.o[d], d, nd, offset)) return r;
+  for (int d = 0; d < 3; ++d)
+    if (relpic_status r = get(sp.u[d], d, 3, u)) return r;
+  const int n1 = s->n[0];
+  const int wsm = make_geo(s).ws_mod;
+  for (long long i = 0; i < n; ++i) {
+    const int pk = packed[i];
+    alive[i] = pk >= 0 ? 1 : 0;
+    if (pk < 0) {
+      for (int d = 0; d < nd; ++d) cell[i * nd + d] = 0;
+      continue;
+    }
+    const int s1 = pk % n1;
+    const int rest = pk / n1;
+    const int l1 = ((s1 - wsm) % n1 + n1) % n1;
+    cell[i * nd + 0] = (int32_t)(l1 + (s->grid.bc1 == RELPIC_BC_WINDOW ? s->ws : 0));
+    cell[i * nd + 1] = rest % s->n[1];
+    if (nd == 3) cell[i * nd + 2] = rest / s->n[1];
+  }
+  return RELPIC_OK;
+}
+
+relpic_status relpic_diagnostics(relpic_sim *s, relpic_diag *out) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (!out) return fail(RELPIC_EINVAL, "diagnostics: null output");
+  if (s->prec == RELPIC_FP32) return do_diag<float>(s, out);
+  return do_diag<double>(s, out);
+}
+
+relpic_status relpic_get_step(relpic_sim *s, int64_t *step, int64_t *window_start) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (step) *step = s->step;
+  if (window_start) *window_start = s->ws;
+  return RELPIC_OK;
+}
+
+relpic_status relpic_profile_enable(relpic_sim *s, int on) {
+  if (relpic_status r = check_sim(s)) return r;
+  HIP_OK(hipStreamSynchronize(s->st));
+  s->prof = on != 0;
+  s->ev_used = 0;
+  s->ev_marks.clear();
+  return RELPIC_OK;
+}
+
+relpic_status relpic_profile_read(relpic_sim *s, relpic_profile *out) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (!out) return fail(RELPIC_EINVAL, "profile_read: null output");
+  HIP_OK(hipStreamSynchronize(s->st));
+  for (int k = 0; k < RELPIC_NUM_KERNEL_CLASSES; ++k) {
+    out->launches[k] = 0;
+    out->total_ms[k] = 0.0;
+  }
+  for (auto &m : s->ev_marks) {
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, s->ev_pool[m.second], s->ev_pool[m.second + 1]));
+    out->launches[m.first] += 1;
+    out->total_ms[m.first] += ms;
+  }
+  return RELPIC_OK;
+}
+
+relpic_status relpic_correction_halfwidth(relpic_sim *s, int *hw) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (hw) *hw = s->ng;
+  return RELPIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// Launch entry points of the relpic HIP kernels (internal to the library).
+#pragma once
+
+#include "relpic_internal.h"
+
+namespace relpic {
+
+template <typename Real>
+struct PushParams {
+  Real half_qmdt;  // (q/m) dt / 2
+  Real dtdx[3];    // dt / dx_d
+  Real f1, f2, f3; // -Q dx_d / (dV dt): Esirkepov current factors
+  Real fv;         // Q / dV: out-of-plane current factor (2D)
+  int shift;       // 1 if the window advances after this step
+};
+
+template <typename Real>
+void launch_bhalf(int ndim, const Geo &g, const Fields<Real> &f, const Axial<Real> &ax, Real h2, Real h3,
+                  hipStream_t st);
+template <typename Real>
+void launch_efull(int ndim, const Geo &g, const Fields<Real> &f, const Real *J1src, const Axial<Real> &ax, Real e2,
+                  Real e3, Real dt, hipStream_t st);
+template <typename Real>
+void launch_jcorr(const Geo &g, const Real *J1, Real *J1c, const Real *taps, int ng, hipStream_t st);
+template <typename Real>
+void launch_zero_column(const Geo &g, const Fields<Real> &f, int col, hipStream_t st);
+template <typename Real>
+void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const Particles<Real> &p,
+                         const PushParams<Real> &q, int *err, hipStream_t st);
+
+// ---- FP64 diagnostics ----------------------------------------------------------
+// acc[0] += 1/2 sum (E^2 + B^2)
+template <typename Real>
+void launch_diag_field_energy(const Geo &g, const Fields<Real> &f, double *acc, hipStream_t st);
+// acc[0] += sum Q/(q/m) (gamma - 1); cnt[0] += alive particles
+template <typename Real>
+void launch_diag_kinetic(const Particles<Real> &p, double mass, double *acc, unsigned long long *cnt,
+                         hipStream_t st);
+// rho (FP64, storage layout) += Q S(x_p)/dV for every alive particle
+template <typename Real>
+void launch_diag_rho(int ndim, const Geo &g, const Particles<Real> &p, double qdv, double *rho, hipStream_t st);
+// max |d- . E - rho - rho_bg| over interior nodes, max |rho| of the particles, sum rho
+// (rho_bg window-relative, may be null); out[0..2] hold the FP64 results
+template <typename Real>
+void launch_diag_gauss(int ndim, const Geo &g, const Fields<Real> &f, const Axial<double> &c1dx, double idx2,
+                       double idx3, const double *rho, const double *rho_bg, int margin1, double *out,
+                       hipStream_t st);
+
+// ---- plasma injection ------------------------------------------------------------
+template <typename Real>
+void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, long long first, int win_cell, int ppc1, int ppc2,
+                        int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
+                        hipStream_t st);
+
+}  // namespace relpic

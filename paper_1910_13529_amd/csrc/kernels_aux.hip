@@ -1,0 +1,255 @@
+// FP64 diagnostics (energies, charge, discrete Gauss residual) and plasma
+// injection for the moving window.  Diagnostics accumulate in FP64 whatever
+// the field precision, so FP32 runs report energy and charge conservation at
+// FP64 resolution.
+#include "kernels.h"
+
+namespace relpic {
+
+constexpr int kRedBlock = 256;
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sh[kRedBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  return t;  // valid in thread 0
+}
+
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double sh[kRedBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, sh[w]);
+  return t;
+}
+
+// non-negative doubles order like their bit patterns
+__device__ __forceinline__ void atomic_max_nonneg(double *addr, double v) {
+  atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kRedBlock) void k_field_energy(Geo g, Fields<Real> f, double *acc) {
+  double s = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N; i += (long long)gridDim.x * blockDim.x) {
+    const double e1 = f.E1[i], e2 = f.E2[i], e3 = f.E3[i], b1 = f.B1[i], b2 = f.B2[i], b3 = f.B3[i];
+    s += e1 * e1 + e2 * e2 + e3 * e3 + b1 * b1 + b2 * b2 + b3 * b3;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) atomicAdd(acc, 0.5 * s);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kRedBlock) void k_kinetic(Particles<Real> p, double mass, double *acc,
+                                                       unsigned long long *cnt) {
+  double s = 0;
+  double c = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < p.n; i += (long long)gridDim.x * blockDim.x) {
+    if (p.cell[i] < 0) continue;
+    const double u1 = p.u1[i], u2 = p.u2[i], u3 = p.u3[i];
+    const double usq = u1 * u1 + u2 * u2 + u3 * u3;
+    // gamma - 1 without cancellation
+    s += mass * usq / (sqrt(1.0 + usq) + 1.0);
+    c += 1.0;
+  }
+  s = block_sum(s);
+  __syncthreads();
+  c = block_sum(c);
+  if (threadIdx.x == 0) {
+    atomicAdd(acc, s);
+    atomicAdd(cnt, (unsigned long long)c);
+  }
+}
+
+template <typename Real, int DIM>
+__global__ __launch_bounds__(kRedBlock) void k_rho(Geo g, Particles<Real> p, double qdv, double *rho) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const int packed = p.cell[i];
+  if (packed < 0) return;
+  const int s1 = packed % g.n1;
+  const int rest = packed / g.n1;
+  const int c2 = rest % g.n2;
+  const int c3 = DIM == 3 ? rest / g.n2 : 0;
+  int c1 = s1 - g.ws_mod;
+  if (c1 < 0) c1 += g.n1;
+  double w[3][3];
+  const double o[3] = {(double)p.o1[i], (double)p.o2[i], DIM == 3 ? (double)p.o3[i] : 0.0};
+  for (int d = 0; d < DIM; ++d) {
+    const double a = 0.5 - o[d], b = 0.5 + o[d];
+    w[d][0] = 0.5 * a * a;
+    w[d][1] = 0.75 - o[d] * o[d];
+    w[d][2] = 0.5 * b * b;
+  }
+  for (int cc = 0; cc < (DIM == 3 ? 3 : 1); ++cc) {
+    const int i3 = DIM == 3 ? wrap(c3 - 1 + cc, g.n3) : 0;
+    const double w3 = DIM == 3 ? w[2][cc] : 1.0;
+    for (int bb = 0; bb < 3; ++bb) {
+      const long long row = (long long)g.n1 * (wrap(c2 - 1 + bb, g.n2) + (long long)g.n2 * i3);
+      for (int aa = 0; aa < 3; ++aa) {
+        const int col = col_of(g, c1 - 1 + aa);
+        if (col < 0) continue;
+        atomicAdd(rho + row + col, qdv * w[0][aa] * w[1][bb] * w3);
+      }
+    }
+  }
+}
+
+template <typename Real, int DIM>
+__global__ __launch_bounds__(kRedBlock) void k_gauss(Geo g, Fields<Real> f, Axial<double> c1dx, double idx2,
+                                                     double idx3, const double *rho, const double *rho_bg,
+                                                     int margin1, double *out) {
+  double rmax = 0, qmax = 0, qsum = 0;
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < g.N;
+       id += (long long)gridDim.x * blockDim.x) {
+    // id enumerates window cells in logical order
+    const int l1 = (int)(id % g.n1);
+    const long long rest = id / g.n1;
+    const int i2 = (int)(rest % g.n2);
+    const int i3 = (int)(rest / g.n2);
+    const long long row = (long long)g.n1 * (i2 + (long long)g.n2 * i3);
+    const int s1 = col_of(g, l1);
+    const long long sid = row + s1;
+    double div = 0;
+    for (int l = 1; l <= c1dx.M; ++l) {
+      const int a = col_of(g, l1 + l - 1), b = col_of(g, l1 - l);
+      const double fa = a >= 0 ? (double)f.E1[row + a] : 0.0;
+      const double fb = b >= 0 ? (double)f.E1[row + b] : 0.0;
+      div += c1dx.c[l - 1] * (fa - fb);
+    }
+    const long long row2m = (long long)g.n1 * (wrap(i2 - 1, g.n2) + (long long)g.n2 * i3);
+    div += idx2 * ((double)f.E2[sid] - (double)f.E2[row2m + s1]);
+    if (DIM == 3) {
+      const long long row3m = (long long)g.n1 * (i2 + (long long)g.n2 * wrap(i3 - 1, g.n3));
+      div += idx3 * ((double)f.E3[sid] - (double)f.E3[row3m + s1]);
+    }
+    double r = rho[sid];
+    qsum += r;
+    qmax = fmax(qmax, fabs(r));
+    if (rho_bg) r += rho_bg[sid];
+    if (!g.window || (l1 >= margin1 && l1 < g.n1 - margin1)) rmax = fmax(rmax, fabs(div - r));
+  }
+  rmax = block_max(rmax);
+  __syncthreads();
+  qmax = block_max(qmax);
+  __syncthreads();
+  qsum = block_sum(qsum);
+  if (threadIdx.x == 0) {
+    atomic_max_nonneg(out + 0, rmax);
+    atomic_max_nonneg(out + 1, qmax);
+    atomicAdd(out + 2, qsum);
+  }
+}
+
+// ---- splitmix64 counter stream (Steele, Lea, Flood 2014) ------------------------
+__device__ __forceinline__ unsigned long long smix(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double uni53(unsigned long long seed, unsigned long long k) {
+  const unsigned long long z = smix(seed + (k + 1ULL) * 0x9e3779b97f4a7c15ULL);
+  return ((double)(z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+__device__ __forceinline__ double normal_k(unsigned long long seed, unsigned long long k) {
+  const double a = uni53(seed, 2ULL * k), b = uni53(seed, 2ULL * k + 1ULL);
+  return sqrt(-2.0 * log(a)) * cospi(2.0 * b);
+}
+
+template <typename Real>
+__global__ void k_inject(int ndim, Geo g, Particles<Real> p, long long first, int win_cell, int ppc1, int ppc2,
+                         int ppc3, double uth, unsigned long long seed, unsigned long long counter0) {
+  const long long per = (long long)ppc1 * ppc2 * ppc3;
+  const long long total = per * g.n2 * g.n3;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const long long q = t % per;
+  const long long rc = t / per;
+  const int i2 = (int)(rc % g.n2);
+  const int i3 = (int)(rc / g.n2);
+  const int a = (int)(q % ppc1), b = (int)((q / ppc1) % ppc2), c = (int)(q / ((long long)ppc1 * ppc2));
+  const long long k = first + t;
+  const int s1 = col_of(g, win_cell);
+  p.cell[k] = s1 + g.n1 * (i2 + g.n2 * i3);
+  p.o1[k] = (Real)((a + 0.5) / ppc1 - 0.5);
+  p.o2[k] = (Real)((b + 0.5) / ppc2 - 0.5);
+  if (ndim == 3) p.o3[k] = (Real)((c + 0.5) / ppc3 - 0.5);
+  const unsigned long long ctr = counter0 + (unsigned long long)t;
+  p.u1[k] = (Real)(uth * normal_k(seed, 3ULL * ctr + 0ULL));
+  p.u2[k] = (Real)(uth * normal_k(seed, 3ULL * ctr + 1ULL));
+  p.u3[k] = (Real)(uth * normal_k(seed, 3ULL * ctr + 2ULL));
+}
+
+// ---- launchers --------------------------------------------------------------------
+
+static unsigned red_blocks(long long n) {
+  long long b = (n + kRedBlock - 1) / kRedBlock;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+template <typename Real>
+void launch_diag_field_energy(const Geo &g, const Fields<Real> &f, double *acc, hipStream_t st) {
+  k_field_energy<Real><<<red_blocks(g.N), kRedBlock, 0, st>>>(g, f, acc);
+}
+
+template <typename Real>
+void launch_diag_kinetic(const Particles<Real> &p, double mass, double *acc, unsigned long long *cnt,
+                         hipStream_t st) {
+  if (p.n <= 0) return;
+  k_kinetic<Real><<<red_blocks(p.n), kRedBlock, 0, st>>>(p, mass, acc, cnt);
+}
+
+template <typename Real>
+void launch_diag_rho(int ndim, const Geo &g, const Particles<Real> &p, double qdv, double *rho, hipStream_t st) {
+  if (p.n <= 0) return;
+  const unsigned blocks = (unsigned)((p.n + kRedBlock - 1) / kRedBlock);
+  if (ndim == 3)
+    k_rho<Real, 3><<<blocks, kRedBlock, 0, st>>>(g, p, qdv, rho);
+  else
+    k_rho<Real, 2><<<blocks, kRedBlock, 0, st>>>(g, p, qdv, rho);
+}
+
+template <typename Real>
+void launch_diag_gauss(int ndim, const Geo &g, const Fields<Real> &f, const Axial<double> &c1dx, double idx2,
+                       double idx3, const double *rho, const double *rho_bg, int margin1, double *out,
+                       hipStream_t st) {
+  if (ndim == 3)
+    k_gauss<Real, 3><<<red_blocks(g.N), kRedBlock, 0, st>>>(g, f, c1dx, idx2, idx3, rho, rho_bg, margin1, out);
+  else
+    k_gauss<Real, 2><<<red_blocks(g.N), kRedBlock, 0, st>>>(g, f, c1dx, idx2, idx3, rho, rho_bg, margin1, out);
+}
+
+template <typename Real>
+void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, long long first, int win_cell, int ppc1, int ppc2,
+                        int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
+                        hipStream_t st) {
+  const long long total = (long long)ppc1 * ppc2 * ppc3 * g.n2 * g.n3;
+  k_inject<Real><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(ndim, g, p, first, win_cell, ppc1, ppc2, ppc3, uth,
+                                                                    seed, counter0);
+}
+
+#define RELPIC_INST_AUX(Real)                                                                                      \
+  template void launch_diag_field_energy<Real>(const Geo &, const Fields<Real> &, double *, hipStream_t);          \
+  template void launch_diag_kinetic<Real>(const Particles<Real> &, double, double *, unsigned long long *,         \
+                                          hipStream_t);                                                            \
+  template void launch_diag_rho<Real>(int, const Geo &, const Particles<Real> &, double, double *, hipStream_t);   \
+  template void launch_diag_gauss<Real>(int, const Geo &, const Fields<Real> &, const Axial<double> &, double,      \
+                                        double, const double *, const double *, int, double *, hipStream_t);       \
+  template void launch_inject_slab<Real>(int, const Geo &, Particles<Real>, long long, int, int, int, int, double, \
+                                         unsigned long long, unsigned long long, hipStream_t);
+
+RELPIC_INST_AUX(float)
+RELPIC_INST_AUX(double)
+
+}  // namespace relpic

@@ -1,0 +1,60 @@
+// Internal types shared by the HIP kernels and the host engine of relpic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace relpic {
+
+constexpr int kMaxM = 32;      // longest axial stencil (2M points)
+constexpr int kMaxTaps = 64;   // half-width bound of the J1 correction FIR
+
+// Grid geometry as the kernels see it.  x1 storage is a ring buffer: the
+// storage column of global cell g is g mod n1, window cell l lives at
+// (l + ws_mod) mod n1.
+struct Geo {
+  int n1, n2, n3;  // n3 = 1 in 2D
+  int ws_mod;      // window start mod n1 (0 when periodic)
+  int window;      // 1: values outside window cells [0, n1) read as zero
+  int pad_;
+  long long N;     // n1 * n2 * n3
+};
+
+template <typename Real>
+struct Fields {
+  Real *E1, *E2, *E3, *B1, *B2, *B3, *J1, *J2, *J3;
+  Real *J1c;  // corrected J1 (customized solver), scratch
+};
+
+// Axial stencil with the 1/dx1 and time-step factors folded in.
+template <typename Real>
+struct Axial {
+  int M;
+  Real c[kMaxM];
+};
+
+template <typename Real>
+struct Particles {
+  int *cell;  // packed storage index s1 + n1 * (s2 + n2 * s3); -1 = dropped
+  Real *o1, *o2, *o3;
+  Real *u1, *u2, *u3;
+  long long n;
+};
+
+// window-cell index -> storage column, or -1 outside the window
+__device__ __forceinline__ int col_of(const Geo &g, int l) {
+  if (g.window) {
+    if (l < 0 || l >= g.n1) return -1;
+    int s = l + g.ws_mod;
+    return s >= g.n1 ? s - g.n1 : s;
+  }
+  int s = (l + g.ws_mod) % g.n1;
+  return s < 0 ? s + g.n1 : s;
+}
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+}  // namespace relpic

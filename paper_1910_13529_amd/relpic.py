@@ -1,0 +1,313 @@
+"""Thin ctypes binding of librelpic.so (the C ABI in include/relpic.h).
+
+Argument marshalling only: every step of the PIC cycle runs in the HIP
+kernels of the library.  The functions keep the C names; `Sim` is a small
+convenience wrapper.  PyTorch provides the device memory (through the
+library's allocator callbacks) and the stream.  If the library is missing
+this module raises: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librelpic.so")
+
+RELPIC_OK, RELPIC_EINVAL, RELPIC_EUNSTABLE, RELPIC_ERANGE, RELPIC_ENOMEM, RELPIC_EDEVICE, RELPIC_ESTATE = range(7)
+RELPIC_FP32, RELPIC_FP64 = 0, 1
+RELPIC_BC_PERIODIC, RELPIC_BC_WINDOW = 0, 1
+FIELDS = ("E1", "E2", "E3", "B1", "B2", "B3", "J1", "J2", "J3")
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EUNSTABLE", 3: "ERANGE", 4: "ENOMEM", 5: "EDEVICE", 6: "ESTATE"}
+
+EXPORTS = (
+    "relpic_fit_coefficients", "relpic_create", "relpic_destroy", "relpic_add_species", "relpic_load_particles",
+    "relpic_set_injection", "relpic_set_background_rho", "relpic_step", "relpic_sync", "relpic_read_field",
+    "relpic_write_field", "relpic_field_device_ptr", "relpic_read_particles", "relpic_diagnostics",
+    "relpic_get_step", "relpic_correction_halfwidth", "relpic_profile_enable", "relpic_profile_read",
+    "relpic_last_error",
+)
+KERNEL_CLASSES = ("push_deposit", "jcorr", "bhalf", "efull", "window")
+
+
+class RelpicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3),
+                ("dt", ctypes.c_double), ("bc1", ctypes.c_int), ("window_speed", ctypes.c_double)]
+
+
+class Solver(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("C", ctypes.POINTER(ctypes.c_double))]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Device(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("user", ctypes.c_void_p)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("window_start", ctypes.c_int64), ("n_alive", ctypes.c_int64),
+                ("time", ctypes.c_double), ("w_field", ctypes.c_double), ("w_kin", ctypes.c_double),
+                ("gauss_max", ctypes.c_double), ("rho_max", ctypes.c_double), ("charge", ctypes.c_double),
+                ("error_word", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 5), ("total_ms", ctypes.c_double * 5)]
+
+
+_lib = None
+
+
+def load():
+    """Load librelpic.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("librelpic.so not built: run __graft_entry__.build() or python -m paper_1910_13529_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    D = ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    for name in EXPORTS:
+        getattr(L, name)  # every declared entry point must exist
+    L.relpic_fit_coefficients.argtypes = [D, ctypes.c_int, ctypes.c_int, D, D, dp, dp]
+    L.relpic_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Solver), ctypes.c_int, ctypes.POINTER(Device),
+                                ctypes.POINTER(P)]
+    L.relpic_destroy.argtypes = [P]
+    L.relpic_add_species.argtypes = [P, D, D, I64, ip]
+    L.relpic_load_particles.argtypes = [P, ctypes.c_int, I64, ctypes.POINTER(ctypes.c_int32), dp, dp]
+    L.relpic_set_injection.argtypes = [P, ctypes.c_int, ip, D, ctypes.c_uint64]
+    L.relpic_set_background_rho.argtypes = [P, dp, I64]
+    L.relpic_step.argtypes = [P, I64]
+    L.relpic_sync.argtypes = [P]
+    L.relpic_read_field.argtypes = [P, ctypes.c_int, dp, I64]
+    L.relpic_write_field.argtypes = [P, ctypes.c_int, dp, I64]
+    L.relpic_field_device_ptr.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ip]
+    L.relpic_read_particles.argtypes = [P, ctypes.c_int, I64, ctypes.POINTER(ctypes.c_int32), dp, dp,
+                                        ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(I64)]
+    L.relpic_diagnostics.argtypes = [P, ctypes.POINTER(Diag)]
+    L.relpic_get_step.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    L.relpic_correction_halfwidth.argtypes = [P, ip]
+    L.relpic_profile_enable.argtypes = [P, ctypes.c_int]
+    L.relpic_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
+    L.relpic_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "relpic_last_error":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != RELPIC_OK:
+        raise RelpicError(status, load().relpic_last_error().decode())
+    return status
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---- functions with the C names ------------------------------------------------------
+
+def relpic_fit_coefficients(kappa, M, p=2, wk1=0.6, nsg=10.0):
+    C = np.zeros(M)
+    err = ctypes.c_double()
+    check(load().relpic_fit_coefficients(kappa, M, p, wk1, nsg, _dp(C), ctypes.byref(err)))
+    return C, err.value
+
+
+class TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.live = {}
+        self._alloc = ALLOC_FN(self.alloc)
+        self._free = FREE_FN(self.free)
+
+    def alloc(self, nbytes, user):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device="cuda:%d" % self.device)
+        except Exception:
+            return None
+        ptr = t.data_ptr()
+        self.live[ptr] = t
+        return ptr
+
+    def free(self, ptr, user):
+        self.live.pop(ptr, None)
+
+
+def relpic_create(grid, solver_C=None, precision=RELPIC_FP64, device=0, stream=None, allocator=None):
+    L = load()
+    g = Grid()
+    g.ndim = grid["ndim"]
+    for d in range(3):
+        g.n[d] = int(grid["n"][d]) if d < g.ndim else 1
+        g.dx[d] = float(grid["dx"][d]) if d < g.ndim else 1.0
+    g.dt = float(grid["dt"])
+    g.bc1 = RELPIC_BC_WINDOW if grid.get("window") else RELPIC_BC_PERIODIC
+    g.window_speed = float(grid.get("window_speed", 1.0))
+    s = Solver()
+    Carr = None
+    if solver_C is not None and len(solver_C) > 1:
+        Carr = np.ascontiguousarray(solver_C, dtype=np.float64)
+        s.M = len(Carr)
+        s.C = _dp(Carr)
+    else:
+        s.M = 1
+        s.C = None
+    dev = Device()
+    dev.device = device
+    dev.stream = stream
+    if allocator is not None:
+        dev.alloc = allocator._alloc
+        dev.free = allocator._free
+    h = ctypes.c_void_p()
+    check(L.relpic_create(ctypes.byref(g), ctypes.byref(s), precision, ctypes.byref(dev), ctypes.byref(h)))
+    return h
+
+
+def relpic_destroy(h):
+    return check(load().relpic_destroy(h))
+
+
+def relpic_step(h, nsteps):
+    return check(load().relpic_step(h, int(nsteps)))
+
+
+def relpic_sync(h):
+    return check(load().relpic_sync(h))
+
+
+class Sim:
+    """One simulation on one GPU.  grid: dict(ndim, n, dx, dt, window, window_speed)."""
+
+    def __init__(self, grid, C=None, precision="fp64", device=0, use_torch=True):
+        self.ndim = grid["ndim"]
+        self.n = tuple(int(v) for v in grid["n"][: self.ndim])
+        self.N = int(np.prod(self.n))
+        self.shape = tuple(reversed(self.n))
+        self.prec = RELPIC_FP64 if precision in ("fp64", RELPIC_FP64) else RELPIC_FP32
+        self.allocator = None
+        stream = None
+        if use_torch:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("relpic needs a ROCm GPU (torch.cuda.is_available() is False)")
+            torch.cuda.set_device(device)
+            self.allocator = TorchAllocator(device)
+            self.torch_stream = torch.cuda.current_stream(device)
+            stream = self.torch_stream.cuda_stream
+        self.h = relpic_create(grid, C, self.prec, device, stream, self.allocator)
+        self.species = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().relpic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_species(self, q_over_m, Q, capacity):
+        sid = ctypes.c_int()
+        check(load().relpic_add_species(self.h, float(q_over_m), float(Q), int(capacity), ctypes.byref(sid)))
+        self.species.append(sid.value)
+        return sid.value
+
+    def load_particles(self, species, cell, offset, u):
+        cell = np.ascontiguousarray(cell, dtype=np.int32).reshape(-1, self.ndim)
+        offset = np.ascontiguousarray(offset, dtype=np.float64).reshape(-1, self.ndim)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+        n = cell.shape[0]
+        check(load().relpic_load_particles(self.h, species, n, cell.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           _dp(offset), _dp(u)))
+
+    def set_injection(self, species, ppc, uth, seed):
+        p = (ctypes.c_int * 3)(*(list(ppc) + [1] * (3 - len(ppc))))
+        check(load().relpic_set_injection(self.h, species, p, float(uth), ctypes.c_uint64(seed)))
+
+    def set_background_rho(self, rho):
+        a = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        check(load().relpic_set_background_rho(self.h, _dp(a), a.size))
+
+    def step(self, nsteps=1):
+        relpic_step(self.h, nsteps)
+
+    def sync(self):
+        relpic_sync(self.h)
+
+    def field(self, name):
+        out = np.empty(self.N)
+        check(load().relpic_read_field(self.h, FIELDS.index(name), _dp(out), self.N))
+        return out.reshape(self.shape)
+
+    def set_field(self, name, arr):
+        a = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1)
+        check(load().relpic_write_field(self.h, FIELDS.index(name), _dp(a), a.size))
+
+    def field_device_ptr(self, name):
+        p = ctypes.c_void_p()
+        eb = ctypes.c_int()
+        check(load().relpic_field_device_ptr(self.h, FIELDS.index(name), ctypes.byref(p), ctypes.byref(eb)))
+        return p.value, eb.value
+
+    def particles(self, species, cap):
+        cell = np.zeros((cap, self.ndim), dtype=np.int32)
+        off = np.zeros((cap, self.ndim))
+        u = np.zeros((cap, 3))
+        alive = np.zeros(cap, dtype=np.uint8)
+        n = ctypes.c_int64()
+        check(load().relpic_read_particles(self.h, species, cap, cell.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           _dp(off), _dp(u), alive.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                           ctypes.byref(n)))
+        k = n.value
+        return cell[:k], off[:k], u[:k], alive[:k].astype(bool)
+
+    def diagnostics(self):
+        d = Diag()
+        check(load().relpic_diagnostics(self.h, ctypes.byref(d)))
+        return d.as_dict()
+
+    def get_step(self):
+        a = ctypes.c_int64()
+        b = ctypes.c_int64()
+        check(load().relpic_get_step(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def profile_enable(self, on=True):
+        check(load().relpic_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        p = Profile()
+        check(load().relpic_profile_read(self.h, ctypes.byref(p)))
+        return {k: (int(p.launches[i]), float(p.total_ms[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    @property
+    def correction_halfwidth(self):
+        v = ctypes.c_int()
+        check(load().relpic_correction_halfwidth(self.h, ctypes.byref(v)))
+        return v.value

@@ -1,0 +1,81 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/relpic.h declares, and rejects bad descriptors on the host."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1910_13529_amd import relpic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "relpic.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(relpic_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = relpic.load()
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for name in syms:
+        assert hasattr(L, name), name
+    assert set(syms) == set(relpic.EXPORTS)
+
+
+def test_fit_entry_point_reproduces_table1():
+    from oracle.fit import TABLE1
+    C, err = relpic.relpic_fit_coefficients(4.0, 16, 2, 0.6, 10.0)
+    assert np.abs(C - TABLE1).max() < 5e-6
+    assert err < 2e-7
+    assert abs(np.sum((2 * np.arange(1, 17) - 1) * C) - 1.0) < 1e-12
+
+
+def test_fit_rejects_bad_order():
+    with pytest.raises(relpic.RelpicError) as e:
+        relpic.relpic_fit_coefficients(4.0, 4, 3)
+    assert e.value.status == relpic.RELPIC_EINVAL
+
+
+def _grid(**kw):
+    g = dict(ndim=2, n=(64, 32, 1), dx=(1.0, 1.0, 1.0), dt=0.5, window=False)
+    g.update(kw)
+    return g
+
+
+def test_create_rejects_unstable_dt():
+    # 2D Yee with dx1 = dx2 = 1 is stable only for dt < 1/sqrt(2)
+    with pytest.raises(relpic.RelpicError) as e:
+        relpic.relpic_create(_grid(dt=0.75))
+    assert e.value.status == relpic.RELPIC_EUNSTABLE
+
+
+def test_create_rejects_unstable_custom_dt():
+    # Table 1's operator reaches 1.45 x sin(k dx/2) near k = 0.7 k_g1: the
+    # customized solver's Courant limit is tighter than Yee's
+    from oracle.fit import TABLE1
+    with pytest.raises(relpic.RelpicError) as e:
+        relpic.relpic_create(_grid(dt=0.68), solver_C=TABLE1)
+    assert e.value.status == relpic.RELPIC_EUNSTABLE
+
+
+@pytest.mark.parametrize("bad", [dict(ndim=4), dict(n=(4, 32, 1)), dict(dx=(0.0, 1.0, 1.0)), dict(dt=-1.0),
+                                 dict(window=True, window_speed=3.0)])
+def test_create_rejects_bad_descriptor(bad):
+    with pytest.raises(relpic.RelpicError) as e:
+        relpic.relpic_create(_grid(**bad))
+    assert e.value.status == relpic.RELPIC_EINVAL
+
+
+def test_courant_limit_matches_dispersion_oracle():
+    # the library's limit and the oracle's symbol maximum agree
+    from oracle import dispersion
+    from oracle.fit import TABLE1
+    dx = (1.0, 1.0)
+    cn = dispersion.courant_number(None, dx, 0.5, C1=TABLE1)
+    dt_lim = 0.5 / cn
+    with pytest.raises(relpic.RelpicError):
+        relpic.relpic_create(_grid(dt=dt_lim * 1.001), solver_C=TABLE1)
