@@ -176,10 +176,20 @@ relpic_status relpic_write_field(relpic_sim *sim, relpic_field f, const double *
 relpic_status relpic_field_device_ptr(relpic_sim *sim, relpic_field f, void **device_ptr, int *elem_bytes);
 
 /* Copy particles of a species to host (synchronizing).  cell [cap][ndim]
- * (x1 global), offset [cap][ndim], u [cap][3], alive [cap]; *n_out = number
- * of particle slots (alive or dropped). */
+ * (x1 global), offset [cap][ndim], u [cap][3], alive [cap], id [cap]
+ * (nullable: the particle's load order within the species, injected
+ * particles numbered after); *n_out = number of particle slots (alive or
+ * dropped).  Slots are in the library's current (cell-sorted) order. */
 relpic_status relpic_read_particles(relpic_sim *sim, int species, int64_t cap, int32_t *cell, double *offset,
-                                    double *u, uint8_t *alive, int64_t *n_out);
+                                    double *u, uint8_t *alive, int64_t *id, int64_t *n_out);
+
+/* Particle sort (a2).  The push kernel deposits through per-workgroup LDS
+ * tiles, which pays off when particles are stored in cell order.  Species
+ * are sorted by cell (dropped particles removed) before the first step after
+ * a load, and every `interval` steps if interval > 0 (default 0).  Sorting
+ * synchronizes the stream. */
+relpic_status relpic_sort_particles(relpic_sim *sim);
+relpic_status relpic_set_sort_interval(relpic_sim *sim, int64_t interval);
 
 /* FP64 diagnostics (synchronizing). */
 relpic_status relpic_diagnostics(relpic_sim *sim, relpic_diag *out);

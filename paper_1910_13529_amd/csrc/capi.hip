@@ -27,6 +27,18 @@ struct Species {
   int *cell = nullptr;
   void *o[3] = {nullptr, nullptr, nullptr};
   void *u[3] = {nullptr, nullptr, nullptr};
+  int *id = nullptr;
+  long long next_id = 0;
+  // second buffers for the sort (swapped after each sort)
+  int *cell2 = nullptr;
+  void *o2[3] = {nullptr, nullptr, nullptr};
+  void *u2[3] = {nullptr, nullptr, nullptr};
+  int *id2 = nullptr;
+  unsigned *keys = nullptr, *keys2 = nullptr, *idx = nullptr, *idx2 = nullptr;
+  void *sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  bool dirty = true;   // needs a sort before the next step
+  int K = 1;           // particles per thread in the push kernel
   bool inject = false;
   int ppc[3] = {1, 1, 1};
   double uth = 0.0;
@@ -65,6 +77,7 @@ struct relpic_sim {
   int ng = 0;
   std::vector<Species> sp;
   long long step = 0, ws = 0;
+  long long sort_interval = 0;  // re-sort every this many steps (0: only after loads)
   int *err = nullptr;
   double *dbuf = nullptr;      // diagnostics accumulators (8 doubles)
   double *rho = nullptr;       // FP64 scratch for the Gauss diagnostic
@@ -181,6 +194,50 @@ double cell_volume(const relpic_sim *s) {
   return v;
 }
 
+// Sort a species by cell (dropped particles last), drop the dropped ones,
+// and pick the push chunk size from the particles per occupied cell.
+template <typename Real>
+relpic_status do_sort(relpic_sim *s, Species &sp) {
+  sp.dirty = false;
+  if (sp.n <= 1) return RELPIC_OK;
+  Particles<Real> src = parts<Real>(sp);
+  launch_sort_keys<Real>(src, sp.keys, sp.idx, s->st);
+  size_t need = 0;
+  HIP_OK(sort_pairs(nullptr, need, sp.keys, sp.keys2, sp.idx, sp.idx2, sp.n, s->st));
+  if (need > sp.sort_tmp_bytes) {
+    sp.sort_tmp = dev_alloc(s, need);
+    if (!sp.sort_tmp) return fail(RELPIC_ENOMEM, "sort: temporary storage allocation failed");
+    sp.sort_tmp_bytes = need;
+  }
+  HIP_OK(sort_pairs(sp.sort_tmp, need, sp.keys, sp.keys2, sp.idx, sp.idx2, sp.n, s->st));
+  Particles<Real> dst = src;
+  dst.cell = sp.cell2;
+  dst.o1 = (Real *)sp.o2[0];
+  dst.o2 = (Real *)sp.o2[1];
+  dst.o3 = (Real *)sp.o2[2];
+  dst.u1 = (Real *)sp.u2[0];
+  dst.u2 = (Real *)sp.u2[1];
+  dst.u3 = (Real *)sp.u2[2];
+  unsigned long long *cnt = (unsigned long long *)(s->dbuf + 6);
+  unsigned long long *runs = (unsigned long long *)(s->dbuf + 7);
+  HIP_OK(hipMemsetAsync(s->dbuf + 6, 0, 2 * sizeof(double), s->st));
+  launch_permute<Real>(src, dst, sp.id, sp.id2, sp.idx2, s->ndim, cnt, s->st);
+  launch_count_runs(sp.keys2, sp.n, runs, s->st);
+  unsigned long long h[2] = {0, 0};
+  HIP_OK(hipMemcpyAsync(h, s->dbuf + 6, sizeof(h), hipMemcpyDeviceToHost, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
+  std::swap(sp.cell, sp.cell2);
+  for (int d = 0; d < 3; ++d) {
+    std::swap(sp.o[d], sp.o2[d]);
+    std::swap(sp.u[d], sp.u2[d]);
+  }
+  std::swap(sp.id, sp.id2);
+  sp.n = (long long)h[0];
+  const double ppc = h[1] ? (double)h[0] / (double)h[1] : 0.0;
+  sp.K = ppc >= 512.0 ? 8 : (ppc >= 64.0 ? 4 : (ppc >= 16.0 ? 2 : 1));
+  return RELPIC_OK;
+}
+
 template <typename Real>
 relpic_status do_steps(relpic_sim *s, long long nsteps) {
   const double dt = s->grid.dt;
@@ -196,6 +253,9 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
   const Real e2 = (Real)(dt / s->dx[1]), e3 = (Real)(s->ndim == 3 ? dt / s->dx[2] : 0.0);
   const bool window = s->grid.bc1 == RELPIC_BC_WINDOW;
   for (long long it = 0; it < nsteps; ++it) {
+    for (auto &sp : s->sp)
+      if (sp.dirty || (s->sort_interval > 0 && s->step % s->sort_interval == 0 && it > 0))
+        if (relpic_status r = do_sort<Real>(s, sp)) return r;
     int shift = 0;
     if (window) {
       const long long tgt = window_target(s, s->step + 1);
@@ -213,7 +273,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       q.fv = (Real)(sp.Q / dV);
       q.shift = shift;
       ProfScope ps(s, 0);
-      launch_push_deposit<Real>(s->ndim, g, f, parts<Real>(sp), q, s->err, s->st);
+      launch_push_deposit<Real>(s->ndim, g, f, parts<Real>(sp), q, sp.K, s->err, s->st);
     }
     const Real *J1src = f.J1;
     if (s->M > 1) {
@@ -243,9 +303,10 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
         if (!sp.inject) continue;
         const long long nnew = (long long)sp.ppc[0] * sp.ppc[1] * sp.ppc[2] * s->n[1] * s->n[2];
         if (sp.n + nnew > sp.cap) return fail(RELPIC_ERANGE, "injection exceeds species capacity");
-        launch_inject_slab<Real>(s->ndim, g2, parts<Real>(sp), sp.n, s->n[0] - 3, sp.ppc[0], sp.ppc[1], sp.ppc[2],
-                                 sp.uth, sp.seed, sp.inj_count, s->st);
+        launch_inject_slab<Real>(s->ndim, g2, parts<Real>(sp), sp.id, sp.n, s->n[0] - 3, sp.ppc[0], sp.ppc[1],
+                                 sp.ppc[2], sp.uth, sp.seed, sp.inj_count, sp.next_id, s->st);
         sp.n += nnew;
+        sp.next_id += nnew;
         sp.inj_count += (unsigned long long)nnew;
       }
     }
@@ -457,11 +518,20 @@ relpic_status relpic_add_species(relpic_sim *s, double q_over_m, double Q, int64
   sp.cap = capacity;
   const size_t cap = (size_t)std::max<int64_t>(capacity, 1);
   sp.cell = (int *)dev_alloc(s, sizeof(int) * cap);
-  bool ok = sp.cell != nullptr;
+  sp.cell2 = (int *)dev_alloc(s, sizeof(int) * cap);
+  sp.id = (int *)dev_alloc(s, sizeof(int) * cap);
+  sp.id2 = (int *)dev_alloc(s, sizeof(int) * cap);
+  sp.keys = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
+  sp.keys2 = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
+  sp.idx = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
+  sp.idx2 = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
+  bool ok = sp.cell && sp.cell2 && sp.id && sp.id2 && sp.keys && sp.keys2 && sp.idx && sp.idx2;
   for (int d = 0; d < 3 && ok; ++d) {
     sp.o[d] = (d < s->ndim) ? dev_alloc(s, s->esz * cap) : nullptr;
+    sp.o2[d] = (d < s->ndim) ? dev_alloc(s, s->esz * cap) : nullptr;
     sp.u[d] = dev_alloc(s, s->esz * cap);
-    ok = (d >= s->ndim || sp.o[d]) && sp.u[d];
+    sp.u2[d] = dev_alloc(s, s->esz * cap);
+    ok = (d >= s->ndim || (sp.o[d] && sp.o2[d])) && sp.u[d] && sp.u2[d];
   }
   if (!ok) return fail(RELPIC_ENOMEM, "add_species: allocation failed");
   s->sp.push_back(sp);
@@ -509,6 +579,10 @@ relpic_status relpic_load_particles(relpic_sim *s, int species, int64_t n, const
     packed[i] = col + s->n[0] * (c2 + s->n[1] * c3);
   }
   HIP_OK(hipMemcpyAsync(sp.cell + sp.n, packed.data(), sizeof(int) * n, hipMemcpyHostToDevice, s->st));
+  std::vector<int> ids(n);
+  for (int64_t i = 0; i < n; ++i) ids[i] = (int)(sp.next_id + i);
+  HIP_OK(hipMemcpyAsync(sp.id + sp.n, ids.data(), sizeof(int) * n, hipMemcpyHostToDevice, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
   std::vector<float> tmp(s->prec == RELPIC_FP32 ? n : 0);
   auto put = [&](void *dst, const std::vector<double> &src) -> relpic_status {
     char *d = (char *)dst + s->esz * sp.n;
@@ -527,6 +601,8 @@ relpic_status relpic_load_particles(relpic_sim *s, int species, int64_t n, const
   for (int d = 0; d < 3; ++d)
     if (relpic_status r = put(sp.u[d], u64[d])) return r;
   sp.n += n;
+  sp.next_id += n;
+  sp.dirty = true;
   return RELPIC_OK;
 }
 
@@ -639,7 +715,7 @@ relpic_status relpic_field_device_ptr(relpic_sim *s, relpic_field f, void **ptr,
 }
 
 relpic_status relpic_read_particles(relpic_sim *s, int species, int64_t cap, int32_t *cell, double *offset, double *u,
-                                    uint8_t *alive, int64_t *n_out) {
+                                    uint8_t *alive, int64_t *id, int64_t *n_out) {
   if (relpic_status r = check_sim(s)) return r;
   if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "read_particles: bad species");
   Species &sp = s->sp[species];
@@ -647,8 +723,9 @@ relpic_status relpic_read_particles(relpic_sim *s, int species, int64_t cap, int
   if (cap < sp.n || !cell || !offset || !u || !alive) return fail(RELPIC_ERANGE, "read_particles: buffers too small");
   const long long n = sp.n;
   const int nd = s->ndim;
-  std::vector<int> packed(n);
+  std::vector<int> packed(n), ids(n);
   HIP_OK(hipMemcpyAsync(packed.data(), sp.cell, sizeof(int) * n, hipMemcpyDeviceToHost, s->st));
+  HIP_OK(hipMemcpyAsync(ids.data(), sp.id, sizeof(int) * n, hipMemcpyDeviceToHost, s->st));
   std::vector<unsigned char> raw(s->esz * std::max<long long>(n, 1));
   auto get = [&](const void *src, int stride_idx, int stride, double *dst) -> relpic_status {
     HIP_OK(hipMemcpyAsync(raw.data(), src, s->esz * n, hipMemcpyDeviceToHost, s->st));
@@ -675,6 +752,7 @@ relpic_status relpic_read_particles(relpic_sim *s, int species, int64_t cap, int
   for (long long i = 0; i < n; ++i) {
     const int pk = packed[i];
     alive[i] = pk >= 0 ? 1 : 0;
+    if (id) id[i] = ids[i];
     if (pk < 0) {
       for (int d = 0; d < nd; ++d) cell[i * nd + d] = 0;
       continue;
@@ -700,6 +778,22 @@ relpic_status relpic_get_step(relpic_sim *s, int64_t *step, int64_t *window_star
   if (relpic_status r = check_sim(s)) return r;
   if (step) *step = s->step;
   if (window_start) *window_start = s->ws;
+  return RELPIC_OK;
+}
+
+relpic_status relpic_sort_particles(relpic_sim *s) {
+  if (relpic_status r = check_sim(s)) return r;
+  for (auto &sp : s->sp) {
+    relpic_status r = s->prec == RELPIC_FP32 ? do_sort<float>(s, sp) : do_sort<double>(s, sp);
+    if (r) return r;
+  }
+  return RELPIC_OK;
+}
+
+relpic_status relpic_set_sort_interval(relpic_sim *s, int64_t interval) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (interval < 0) return fail(RELPIC_EINVAL, "sort interval must be >= 0");
+  s->sort_interval = interval;
   return RELPIC_OK;
 }
 

@@ -24,9 +24,22 @@ template <typename Real>
 void launch_jcorr(const Geo &g, const Real *J1, Real *J1c, const Real *taps, int ng, hipStream_t st);
 template <typename Real>
 void launch_zero_column(const Geo &g, const Fields<Real> &f, int col, hipStream_t st);
+// K particles per thread; each workgroup handles a contiguous chunk of
+// 256 * K particles (sorted by cell for the LDS-tiled deposit to pay off)
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const Particles<Real> &p,
-                         const PushParams<Real> &q, int *err, hipStream_t st);
+                         const PushParams<Real> &q, int K, int *err, hipStream_t st);
+
+// ---- particle sort by cell ------------------------------------------------------
+template <typename Real>
+void launch_sort_keys(const Particles<Real> &p, unsigned *keys, unsigned *idx, hipStream_t st);
+template <typename Real>
+void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, const int *id_src, int *id_dst,
+                    const unsigned *perm, int ndim, unsigned long long *alive, hipStream_t st);
+void launch_count_runs(const unsigned *keys, long long n, unsigned long long *runs, hipStream_t st);
+// radix sort of (key, index) pairs; temp/temp_bytes from a first call with temp = null
+hipError_t sort_pairs(void *temp, size_t &temp_bytes, const unsigned *keys_in, unsigned *keys_out,
+                      const unsigned *idx_in, unsigned *idx_out, long long n, hipStream_t st);
 
 // ---- FP64 diagnostics ----------------------------------------------------------
 // acc[0] += 1/2 sum (E^2 + B^2)
@@ -48,8 +61,8 @@ void launch_diag_gauss(int ndim, const Geo &g, const Fields<Real> &f, const Axia
 
 // ---- plasma injection ------------------------------------------------------------
 template <typename Real>
-void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, long long first, int win_cell, int ppc1, int ppc2,
-                        int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
-                        hipStream_t st);
+void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, int *id, long long first, int win_cell, int ppc1,
+                        int ppc2, int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
+                        long long id0, hipStream_t st);
 
 }  // namespace relpic

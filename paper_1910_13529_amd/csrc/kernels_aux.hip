@@ -166,8 +166,9 @@ __device__ __forceinline__ double normal_k(unsigned long long seed, unsigned lon
 }
 
 template <typename Real>
-__global__ void k_inject(int ndim, Geo g, Particles<Real> p, long long first, int win_cell, int ppc1, int ppc2,
-                         int ppc3, double uth, unsigned long long seed, unsigned long long counter0) {
+__global__ void k_inject(int ndim, Geo g, Particles<Real> p, int *id, long long first, int win_cell, int ppc1,
+                         int ppc2, int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
+                         long long id0) {
   const long long per = (long long)ppc1 * ppc2 * ppc3;
   const long long total = per * g.n2 * g.n3;
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -180,6 +181,7 @@ __global__ void k_inject(int ndim, Geo g, Particles<Real> p, long long first, in
   const long long k = first + t;
   const int s1 = col_of(g, win_cell);
   p.cell[k] = s1 + g.n1 * (i2 + g.n2 * i3);
+  id[k] = (int)(id0 + t);
   p.o1[k] = (Real)((a + 0.5) / ppc1 - 0.5);
   p.o2[k] = (Real)((b + 0.5) / ppc2 - 0.5);
   if (ndim == 3) p.o3[k] = (Real)((c + 0.5) / ppc3 - 0.5);
@@ -231,12 +233,12 @@ void launch_diag_gauss(int ndim, const Geo &g, const Fields<Real> &f, const Axia
 }
 
 template <typename Real>
-void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, long long first, int win_cell, int ppc1, int ppc2,
-                        int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
-                        hipStream_t st) {
+void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, int *id, long long first, int win_cell, int ppc1,
+                        int ppc2, int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
+                        long long id0, hipStream_t st) {
   const long long total = (long long)ppc1 * ppc2 * ppc3 * g.n2 * g.n3;
-  k_inject<Real><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(ndim, g, p, first, win_cell, ppc1, ppc2, ppc3, uth,
-                                                                    seed, counter0);
+  k_inject<Real><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(ndim, g, p, id, first, win_cell, ppc1, ppc2, ppc3,
+                                                                    uth, seed, counter0, id0);
 }
 
 #define RELPIC_INST_AUX(Real)                                                                                      \
@@ -246,8 +248,8 @@ void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, long long fir
   template void launch_diag_rho<Real>(int, const Geo &, const Particles<Real> &, double, double *, hipStream_t);   \
   template void launch_diag_gauss<Real>(int, const Geo &, const Fields<Real> &, const Axial<double> &, double,      \
                                         double, const double *, const double *, int, double *, hipStream_t);       \
-  template void launch_inject_slab<Real>(int, const Geo &, Particles<Real>, long long, int, int, int, int, double, \
-                                         unsigned long long, unsigned long long, hipStream_t);
+  template void launch_inject_slab<Real>(int, const Geo &, Particles<Real>, int *, long long, int, int, int, int,   \
+                                         double, unsigned long long, unsigned long long, long long, hipStream_t);
 
 RELPIC_INST_AUX(float)
 RELPIC_INST_AUX(double)

@@ -5,9 +5,25 @@
 //
 // Positions are (packed storage cell, offset in [-1/2, 1/2) cell units), so
 // FP32 offsets keep full precision at any distance from the origin.
+//
+// Deposit.  Particles are kept sorted by cell, so the 64 lanes of a wavefront
+// mostly share one or two neighbouring cells of one (x2, x3) row.  Each
+// workgroup walks a contiguous chunk of particles and accumulates current in
+// an LDS tile that covers the chunk's cells; at the end it adds the non-zero
+// tile entries to J in HBM with one atomic each.  Inside a wavefront, lanes
+// whose stencils fit a common box of 5 x 4 (x 4) points first sum their
+// contributions with a recursive-halving reduce-scatter over the 64 lanes
+// (each lane ends up owning at most two box points), so a dense bunch costs
+// a few cross-lane moves per particle instead of ~60 conflicting atomics.
+// Lanes that do not fit the box add their stencil to the tile directly.
+#include <climits>
+
 #include "kernels.h"
 
 namespace relpic {
+
+constexpr int kPushBlock = 256;
+constexpr int kTileBytes = 24576;  // LDS current tile per workgroup
 
 // quadratic B-spline weights at nodes -1, 0, +1 for a particle at offset d
 // from node 0 (d in [-1/2, 1/2])
@@ -31,20 +47,18 @@ __device__ __forceinline__ int qw_half(int c, Real o, Real w[3]) {
   return c - 1;
 }
 
-template <typename Real, int DIM>
+template <typename Real>
 struct Stagger {
-  // node (N) and half (H) stencils per dimension
   int bN[3], bH[3];
   Real wN[3][3], wH[3][3];
 };
 
-template <typename Real, int DIM>
-__device__ __forceinline__ Real interp(const Geo &g, const Real *f, const Stagger<Real, DIM> &s, const bool h1,
-                                       const bool h2, const bool h3) {
-  const int b1 = h1 ? s.bH[0] : s.bN[0];
-  const int b2 = h2 ? s.bH[1] : s.bN[1];
-  const Real *w1 = h1 ? s.wH[0] : s.wN[0];
-  const Real *w2 = h2 ? s.wH[1] : s.wN[1];
+// Interpolate one field component; H1..H3 select half-integer (staggered)
+// or node weights along each dimension.
+template <typename Real, int DIM, bool H1, bool H2, bool H3>
+__device__ __forceinline__ Real interp(const Geo &g, const Real *f, const Stagger<Real> &s) {
+  const int b1 = H1 ? s.bH[0] : s.bN[0];
+  const int b2 = H2 ? s.bH[1] : s.bN[1];
   int cols[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) cols[a] = col_of(g, b1 - 1 + a);
@@ -56,12 +70,11 @@ __device__ __forceinline__ Real interp(const Geo &g, const Real *f, const Stagge
       Real r = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
-        if (cols[a] >= 0) r += w1[a] * f[row + cols[a]];
-      acc += w2[b] * r;
+        if (cols[a] >= 0) r += (H1 ? s.wH[0][a] : s.wN[0][a]) * f[row + cols[a]];
+      acc += (H2 ? s.wH[1][b] : s.wN[1][b]) * r;
     }
   } else {
-    const int b3 = h3 ? s.bH[2] : s.bN[2];
-    const Real *w3 = h3 ? s.wH[2] : s.wN[2];
+    const int b3 = H3 ? s.bH[2] : s.bN[2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int i3 = wrap(b3 - 1 + c, g.n3);
@@ -72,10 +85,10 @@ __device__ __forceinline__ Real interp(const Geo &g, const Real *f, const Stagge
         Real r = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-          if (cols[a] >= 0) r += w1[a] * f[row + cols[a]];
-        rc += w2[b] * r;
+          if (cols[a] >= 0) r += (H1 ? s.wH[0][a] : s.wN[0][a]) * f[row + cols[a]];
+        rc += (H2 ? s.wH[1][b] : s.wN[1][b]) * r;
       }
-      acc += w3[c] * rc;
+      acc += (H3 ? s.wH[2][c] : s.wN[2][c]) * rc;
     }
   }
   return acc;
@@ -92,8 +105,8 @@ __device__ __forceinline__ int esirkepov_1d(Real o0, int sh, Real o1, Real S0[4]
   Real run = 0;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int k = base + a;        // node relative to the old cell
-    const int k1 = k - sh;         // node relative to the new cell
+    const int k = base + a;  // node relative to the old cell
+    const int k1 = k - sh;   // node relative to the new cell
     const Real s0 = (k >= -1 && k <= 1) ? w0[k + 1] : Real(0);
     const Real s1 = (k1 >= -1 && k1 <= 1) ? w1[k1 + 1] : Real(0);
     S0[a] = s0;
@@ -104,199 +117,492 @@ __device__ __forceinline__ int esirkepov_1d(Real o0, int sh, Real o1, Real S0[4]
   return base;
 }
 
+// Where deposits go: the workgroup's LDS tile if it covers the point, else
+// J in HBM.  Coordinates are the window x1 index and unwrapped x2, x3.
 template <typename Real>
-__device__ __forceinline__ void jadd(Real *J, long long idx, Real v) {
-  if (v != Real(0)) atomicAdd(J + idx, v);
+struct Sink {
+  Real *tile;        // 3 components x T1 x T2 x T3, or null
+  int t1, t2, t3;    // tile origin
+  int T1, T2, T3;    // tile extents
+  int tn;            // T1 * T2 * T3
+  Real *J[3];
+  Geo g;
+
+  __device__ __forceinline__ void add(int comp, int x1, int x2, int x3, Real v) const {
+    if (v == Real(0)) return;
+    if (tile) {
+      const int a = x1 - t1, b = x2 - t2, c = x3 - t3;
+      if (a >= 0 && a < T1 && b >= 0 && b < T2 && c >= 0 && c < T3) {
+        atomicAdd(tile + comp * tn + a + T1 * (b + T2 * c), v);
+        return;
+      }
+    }
+    const int col = col_of(g, x1);
+    if (col < 0) return;
+    const long long row = (long long)g.n1 * (wrap(x2, g.n2) + (long long)g.n2 * wrap(x3, g.n3));
+    atomicAdd(J[comp] + row + col, v);
+  }
+};
+
+// One level of the reduce-scatter: v[0..S) is summed with the partner lane
+// (lane ^ bit); lanes with the bit set keep the upper half.
+template <typename Real, int S>
+__device__ __forceinline__ void rs_level(Real *v, int lane, int bit, int &off) {
+  constexpr int H = (S + 1) / 2;
+  const bool up = (lane & bit) != 0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const Real lo = v[j];
+    const Real hi = (j + H < S) ? v[j + H] : Real(0);
+    const Real send = up ? lo : hi;
+    const Real keep = up ? hi : lo;
+    v[j] = keep + __shfl_xor(send, bit, 64);
+  }
+  if (up) off += H;
 }
 
+// 80 (3D) or 20 (2D) box values summed over the wavefront; returns with each
+// lane holding values for box indices off, off + 1 (3D) or off (2D).
 template <typename Real, int DIM>
-__global__ __launch_bounds__(256) void k_push_deposit(Geo g, Fields<Real> f, Particles<Real> p, PushParams<Real> q,
-                                                      int *err) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  const int packed = p.cell[i];
-  if (packed < 0) return;
-  // decode storage cell -> window cell along x1, rows along x2/x3
-  const int s1 = packed % g.n1;
-  const int rest = packed / g.n1;
-  const int c2 = rest % g.n2;
-  const int c3 = DIM == 3 ? rest / g.n2 : 0;
-  int c1 = s1 - g.ws_mod;
-  if (c1 < 0) c1 += g.n1;
-  const int c[3] = {c1, c2, c3};
-  const Real o[3] = {p.o1[i], p.o2[i], DIM == 3 ? p.o3[i] : Real(0)};
-
-  // ---- gather E^n, B^n at x^n
-  Stagger<Real, DIM> st;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    st.bN[d] = c[d];
-    qw(o[d], st.wN[d]);
-    st.bH[d] = qw_half(c[d], o[d], st.wH[d]);
+__device__ __forceinline__ void reduce_scatter(Real *v, int lane, int &off) {
+  off = 0;
+  if (DIM == 3) {
+    rs_level<Real, 80>(v, lane, 32, off);
+    rs_level<Real, 40>(v, lane, 16, off);
+    rs_level<Real, 20>(v, lane, 8, off);
+    rs_level<Real, 10>(v, lane, 4, off);
+    rs_level<Real, 5>(v, lane, 2, off);
+    rs_level<Real, 3>(v, lane, 1, off);
+  } else {
+    rs_level<Real, 20>(v, lane, 32, off);
+    rs_level<Real, 10>(v, lane, 16, off);
+    rs_level<Real, 5>(v, lane, 8, off);
+    rs_level<Real, 3>(v, lane, 4, off);
+    rs_level<Real, 2>(v, lane, 2, off);
+    rs_level<Real, 1>(v, lane, 1, off);
   }
-  const Real E1 = interp<Real, DIM>(g, f.E1, st, true, false, false);
-  const Real E2 = interp<Real, DIM>(g, f.E2, st, false, true, false);
-  const Real E3 = interp<Real, DIM>(g, f.E3, st, false, false, true);
-  const Real B1 = interp<Real, DIM>(g, f.B1, st, false, true, true);
-  const Real B2 = interp<Real, DIM>(g, f.B2, st, true, false, true);
-  const Real B3 = interp<Real, DIM>(g, f.B3, st, true, true, false);
+}
 
-  // ---- relativistic Boris push
-  const Real a = q.half_qmdt;
-  Real um1 = p.u1[i] + a * E1, um2 = p.u2[i] + a * E2, um3 = p.u3[i] + a * E3;
-  const Real gm = sqrt(Real(1) + um1 * um1 + um2 * um2 + um3 * um3);
-  const Real t1 = a * B1 / gm, t2 = a * B2 / gm, t3 = a * B3 / gm;
-  const Real t2s = t1 * t1 + t2 * t2 + t3 * t3;
-  const Real f2 = Real(2) / (Real(1) + t2s);
-  const Real s1v = f2 * t1, s2v = f2 * t2, s3v = f2 * t3;
-  const Real up1 = um1 + (um2 * t3 - um3 * t2);
-  const Real up2 = um2 + (um3 * t1 - um1 * t3);
-  const Real up3 = um3 + (um1 * t2 - um2 * t1);
-  const Real un1 = um1 + (up2 * s3v - up3 * s2v) + a * E1;
-  const Real un2 = um2 + (up3 * s1v - up1 * s3v) + a * E2;
-  const Real un3 = um3 + (up1 * s2v - up2 * s1v) + a * E3;
-  const Real gn = sqrt(Real(1) + un1 * un1 + un2 * un2 + un3 * un3);
-  const Real ig = Real(1) / gn;
-  if (!(un1 == un1) || !(un2 == un2) || !(un3 == un3)) atomicOr(err, 2);
-
-  // ---- x^{n+1} = x^n + dt u / gamma, in cell units, as cell + offset
-  const Real un[3] = {un1, un2, un3};
-  int sh[3] = {0, 0, 0};
-  Real on[3] = {o[0], o[1], o[2]};
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const Real dlt = q.dtdx[d] * un[d] * ig;
-    if (!(dlt < Real(1) && dlt > Real(-1))) atomicOr(err, 1);
-    Real v = o[d] + dlt;
-    int k = 0;
-    if (v >= Real(0.5)) k = 1;
-    else if (v < Real(-0.5)) k = -1;
-    sh[d] = k;
-    on[d] = v - Real(k);
-  }
-
-  // ---- Esirkepov current J^{n+1/2}
+// Everything the deposit needs from one pushed particle.
+template <typename Real>
+struct Moved {
+  int c[3];          // old cell (window x1, x2, x3)
+  int base[3];       // first stencil node relative to the old cell (-2 or -1)
   Real S0[3][4], DS[3][4], cum[3][4];
-  int base[3];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) base[d] = esirkepov_1d(o[d], sh[d], on[d], S0[d], DS[d], cum[d]);
-  int col[4];
-#pragma unroll
-  for (int aa = 0; aa < 4; ++aa) col[aa] = col_of(g, c1 + base[0] + aa);
+  Real jz;           // Q v3 / dV (2D out-of-plane current)
+};
 
+template <typename Real>
+__device__ __forceinline__ Real wperp(const Real *S0a, const Real *DSa, const Real *S0b, const Real *DSb, int a,
+                                      int b) {
+  return S0a[a] * S0b[b] + Real(0.5) * DSa[a] * S0b[b] + Real(0.5) * S0a[a] * DSb[b] +
+         DSa[a] * DSb[b] * Real(1.0 / 3.0);
+}
+
+// Direct Esirkepov deposit of one particle into the sink.
+template <typename Real, int DIM>
+__device__ __forceinline__ void deposit_direct(const Moved<Real> &m, const PushParams<Real> &q, const Sink<Real> &sk) {
+  const int x1 = m.c[0] + m.base[0], x2 = m.c[1] + m.base[1];
   if (DIM == 2) {
-    long long row[4];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) row[bb] = (long long)g.n1 * wrap(c2 + base[1] + bb, g.n2);
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
-      const Real wt = q.f1 * (S0[1][bb] + Real(0.5) * DS[1][bb]);
+      const Real wt = q.f1 * (m.S0[1][bb] + Real(0.5) * m.DS[1][bb]);
 #pragma unroll
-      for (int aa = 0; aa < 3; ++aa)
-        if (col[aa] >= 0) jadd(f.J1, row[bb] + col[aa], wt * cum[0][aa]);
+      for (int aa = 0; aa < 3; ++aa) sk.add(0, x1 + aa, x2 + bb, 0, wt * m.cum[0][aa]);
     }
 #pragma unroll
     for (int aa = 0; aa < 4; ++aa) {
-      if (col[aa] < 0) continue;
-      const Real wt = q.f2 * (S0[0][aa] + Real(0.5) * DS[0][aa]);
+      const Real wt = q.f2 * (m.S0[0][aa] + Real(0.5) * m.DS[0][aa]);
 #pragma unroll
-      for (int bb = 0; bb < 3; ++bb) jadd(f.J2, row[bb] + col[aa], wt * cum[1][bb]);
+      for (int bb = 0; bb < 3; ++bb) sk.add(1, x1 + aa, x2 + bb, 0, wt * m.cum[1][bb]);
     }
-    const Real jz = q.fv * un3 * ig;
 #pragma unroll
-    for (int aa = 0; aa < 4; ++aa) {
-      if (col[aa] < 0) continue;
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const Real w3 = S0[0][aa] * S0[1][bb] + Real(0.5) * DS[0][aa] * S0[1][bb] + Real(0.5) * S0[0][aa] * DS[1][bb] +
-                        DS[0][aa] * DS[1][bb] * Real(1.0 / 3.0);
-        jadd(f.J3, row[bb] + col[aa], jz * w3);
-      }
-    }
-  } else {
-    long long row[4][4];
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc)
+    for (int aa = 0; aa < 4; ++aa)
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb)
-        row[cc][bb] =
-            (long long)g.n1 * (wrap(c2 + base[1] + bb, g.n2) + (long long)g.n2 * wrap(c3 + base[2] + cc, g.n3));
-    const Real third = Real(1.0 / 3.0);
-    // J1: transverse weight x running sum of DS1
+        sk.add(2, x1 + aa, x2 + bb, 0, m.jz * wperp(m.S0[0], m.DS[0], m.S0[1], m.DS[1], aa, bb));
+  } else {
+    const int x3 = m.c[2] + m.base[2];
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc)
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
-        const Real wt = q.f1 * (S0[1][bb] * S0[2][cc] + Real(0.5) * DS[1][bb] * S0[2][cc] +
-                                Real(0.5) * S0[1][bb] * DS[2][cc] + DS[1][bb] * DS[2][cc] * third);
+        const Real wt = q.f1 * wperp(m.S0[1], m.DS[1], m.S0[2], m.DS[2], bb, cc);
         if (wt == Real(0)) continue;
 #pragma unroll
-        for (int aa = 0; aa < 3; ++aa)
-          if (col[aa] >= 0) jadd(f.J1, row[cc][bb] + col[aa], wt * cum[0][aa]);
+        for (int aa = 0; aa < 3; ++aa) sk.add(0, x1 + aa, x2 + bb, x3 + cc, wt * m.cum[0][aa]);
       }
-    // J2
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc)
 #pragma unroll
       for (int aa = 0; aa < 4; ++aa) {
-        if (col[aa] < 0) continue;
-        const Real wt = q.f2 * (S0[0][aa] * S0[2][cc] + Real(0.5) * DS[0][aa] * S0[2][cc] +
-                                Real(0.5) * S0[0][aa] * DS[2][cc] + DS[0][aa] * DS[2][cc] * third);
+        const Real wt = q.f2 * wperp(m.S0[0], m.DS[0], m.S0[2], m.DS[2], aa, cc);
         if (wt == Real(0)) continue;
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb) jadd(f.J2, row[cc][bb] + col[aa], wt * cum[1][bb]);
+        for (int bb = 0; bb < 3; ++bb) sk.add(1, x1 + aa, x2 + bb, x3 + cc, wt * m.cum[1][bb]);
       }
-    // J3
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
       for (int aa = 0; aa < 4; ++aa) {
-        if (col[aa] < 0) continue;
-        const Real wt = q.f3 * (S0[0][aa] * S0[1][bb] + Real(0.5) * DS[0][aa] * S0[1][bb] +
-                                Real(0.5) * S0[0][aa] * DS[1][bb] + DS[0][aa] * DS[1][bb] * third);
+        const Real wt = q.f3 * wperp(m.S0[0], m.DS[0], m.S0[1], m.DS[1], aa, bb);
         if (wt == Real(0)) continue;
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) jadd(f.J3, row[cc][bb] + col[aa], wt * cum[2][cc]);
+        for (int cc = 0; cc < 3; ++cc) sk.add(2, x1 + aa, x2 + bb, x3 + cc, wt * m.cum[2][cc]);
       }
   }
+}
 
-  // ---- store the new state
-  const int n1c = c1 + sh[0];
-  int alive = 1;
-  if (g.window) {
-    const int after = n1c - q.shift;  // window cell after this step's shift
-    if (after < 2 || after > g.n1 - 3) alive = 0;
+// Shift a 4-point stencil array into the 5-point box frame: out[b] = in[b - o].
+template <typename Real>
+__device__ __forceinline__ Real ext5(const Real *in, int o, int b) {
+  const Real a = (b <= 3) ? in[b] : Real(0);
+  const Real c = (b >= 1) ? in[b - 1] : Real(0);
+  return o ? c : a;
+}
+
+// Wavefront-collective deposit (every lane of the wave must call it).
+template <typename Real, int DIM>
+__device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, const PushParams<Real> &q, const Sink<Real> &sk) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long act = __ballot(active);
+  if (act == 0ULL) return;
+  const int first = __ffsll((long long)act) - 1;
+  const int c2w = __shfl(m.c[1], first, 64);
+  const int c3w = __shfl(m.c[2], first, 64);
+  const bool inrow = active && m.c[1] == c2w && (DIM == 2 || m.c[2] == c3w);
+  int cmin = inrow ? m.c[0] : INT_MAX;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cmin = min(cmin, __shfl_xor(cmin, o, 64));
+  const int o1 = m.c[0] + m.base[0] - (cmin - 1);
+  const bool fits = inrow && (o1 == 0 || o1 == 1) && m.base[1] == -1 && (DIM == 2 || m.base[2] == -1);
+  const unsigned long long fm = __ballot(fits);
+  if (__popcll(fm) >= 8) {
+    constexpr int NB = DIM == 3 ? 80 : 20;
+    const int oo = fits ? o1 : 0;
+    Real e1S0[5], e1DS[5], e1cum[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      e1S0[b] = ext5(m.S0[0], oo, b);
+      e1DS[b] = ext5(m.DS[0], oo, b);
+      e1cum[b] = ext5(m.cum[0], oo, b);
+    }
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      Real v[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const int b = k % 5, a2 = (k / 5) % 4, a3 = k / 20;
+        Real val = 0;
+        if (DIM == 2) {
+          if (comp == 0) val = (b - oo >= 0 && b - oo <= 2) ? q.f1 * e1cum[b] * (m.S0[1][a2] + Real(0.5) * m.DS[1][a2]) : Real(0);
+          if (comp == 1) val = (a2 <= 2) ? q.f2 * m.cum[1][a2] * (e1S0[b] + Real(0.5) * e1DS[b]) : Real(0);
+          if (comp == 2) val = m.jz * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2);
+        } else {
+          if (comp == 0)
+            val = (b - oo >= 0 && b - oo <= 2) ? q.f1 * e1cum[b] * wperp(m.S0[1], m.DS[1], m.S0[2], m.DS[2], a2, a3)
+                                               : Real(0);
+          if (comp == 1)
+            val = (a2 <= 2) ? q.f2 * m.cum[1][a2] * wperp(e1S0, e1DS, m.S0[2], m.DS[2], b, a3) : Real(0);
+          if (comp == 2)
+            val = (a3 <= 2) ? q.f3 * m.cum[2][a3] * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2) : Real(0);
+        }
+        v[k] = fits ? val : Real(0);
+      }
+      int off;
+      reduce_scatter<Real, DIM>(v, lane, off);
+#pragma unroll
+      for (int j = 0; j < (DIM == 3 ? 2 : 1); ++j) {
+        const int k = off + j;
+        if (k < NB) {
+          const int b = k % 5, a2 = (k / 5) % 4, a3 = k / 20;
+          sk.add(comp, cmin - 1 + b, c2w - 1 + a2, DIM == 3 ? c3w - 1 + a3 : 0, v[j]);
+        }
+      }
+    }
+    if (active && !fits) deposit_direct<Real, DIM>(m, q, sk);
+  } else if (active) {
+    deposit_direct<Real, DIM>(m, q, sk);
   }
-  if (!alive) {
-    p.cell[i] = -1;
-    return;
+}
+
+template <typename Real, int DIM>
+__global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real> f, Particles<Real> p,
+                                                             PushParams<Real> q, int K, int *err) {
+  __shared__ __align__(16) unsigned char tile_raw[kTileBytes];
+  __shared__ int box[6];
+  Real *tile = reinterpret_cast<Real *>(tile_raw);
+  const long long chunk0 = (long long)blockIdx.x * kPushBlock * K;
+  const int tid = threadIdx.x;
+
+  // ---- chunk bounding box (window x1, x2, x3) of the particles' old cells
+  if (tid == 0) {
+    box[0] = box[2] = box[4] = INT_MAX;
+    box[1] = box[3] = box[5] = INT_MIN;
   }
-  const int ns1 = col_of(g, n1c);
-  const int ns2 = wrap(c2 + sh[1], g.n2);
-  const int ns3 = DIM == 3 ? wrap(c3 + sh[2], g.n3) : 0;
-  p.cell[i] = ns1 + g.n1 * (ns2 + g.n2 * ns3);
-  p.o1[i] = on[0];
-  p.o2[i] = on[1];
-  if (DIM == 3) p.o3[i] = on[2];
-  p.u1[i] = un1;
-  p.u2[i] = un2;
-  p.u3[i] = un3;
+  __syncthreads();
+  {
+    int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+    for (int k = 0; k < K; ++k) {
+      const long long i = chunk0 + (long long)k * kPushBlock + tid;
+      if (i >= p.n) break;
+      const int packed = p.cell[i];
+      if (packed < 0) continue;
+      const int s1 = packed % g.n1, rest = packed / g.n1;
+      int c1 = s1 - g.ws_mod;
+      if (c1 < 0) c1 += g.n1;
+      const int cc[3] = {c1, rest % g.n2, DIM == 3 ? rest / g.n2 : 0};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        mn[d] = min(mn[d], cc[d]);
+        mx[d] = max(mx[d], cc[d]);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        mn[d] = min(mn[d], __shfl_xor(mn[d], o, 64));
+        mx[d] = max(mx[d], __shfl_xor(mx[d], o, 64));
+      }
+    }
+    if ((tid & 63) == 0 && mn[0] != INT_MAX) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        atomicMin(&box[2 * d], mn[d]);
+        atomicMax(&box[2 * d + 1], mx[d]);
+      }
+    }
+  }
+  __syncthreads();
+  Sink<Real> sk;
+  sk.g = g;
+  sk.J[0] = f.J1;
+  sk.J[1] = f.J2;
+  sk.J[2] = f.J3;
+  sk.tile = nullptr;
+  sk.t1 = box[0] - 2;
+  sk.t2 = box[2] - 2;
+  sk.t3 = DIM == 3 ? box[4] - 2 : 0;
+  sk.T1 = sk.T2 = sk.T3 = 1;
+  sk.tn = 0;
+  if (box[0] != INT_MAX) {
+    const long long T1 = (long long)box[1] - box[0] + 5, T2 = (long long)box[3] - box[2] + 5;
+    const long long T3 = DIM == 3 ? (long long)box[5] - box[4] + 5 : 1;
+    if (3 * T1 * T2 * T3 * (long long)sizeof(Real) <= kTileBytes) {
+      sk.T1 = (int)T1;
+      sk.T2 = (int)T2;
+      sk.T3 = (int)T3;
+      sk.tn = (int)(T1 * T2 * T3);
+      sk.tile = tile;
+      for (int t = tid; t < 3 * sk.tn; t += kPushBlock) tile[t] = Real(0);
+    }
+  }
+  __syncthreads();
+
+  // ---- gather, push, move and deposit, K particles per thread
+  for (int k = 0; k < K; ++k) {
+    const long long i = chunk0 + (long long)k * kPushBlock + tid;
+    const int packed = (i < p.n) ? p.cell[i] : -1;
+    const bool active = packed >= 0;
+    Moved<Real> m;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      m.c[d] = 0;
+      m.base[d] = -1;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) m.S0[d][a] = m.DS[d][a] = m.cum[d][a] = Real(0);
+    }
+    m.jz = 0;
+    if (active) {
+      const int s1 = packed % g.n1;
+      const int rest = packed / g.n1;
+      const int c2 = rest % g.n2;
+      const int c3 = DIM == 3 ? rest / g.n2 : 0;
+      int c1 = s1 - g.ws_mod;
+      if (c1 < 0) c1 += g.n1;
+      m.c[0] = c1;
+      m.c[1] = c2;
+      m.c[2] = c3;
+      const Real o[3] = {p.o1[i], p.o2[i], DIM == 3 ? p.o3[i] : Real(0)};
+
+      Stagger<Real> st;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        st.bN[d] = m.c[d];
+        qw(o[d], st.wN[d]);
+        st.bH[d] = qw_half(m.c[d], o[d], st.wH[d]);
+      }
+      const Real E1 = interp<Real, DIM, true, false, false>(g, f.E1, st);
+      const Real E2 = interp<Real, DIM, false, true, false>(g, f.E2, st);
+      const Real E3 = interp<Real, DIM, false, false, true>(g, f.E3, st);
+      const Real B1 = interp<Real, DIM, false, true, true>(g, f.B1, st);
+      const Real B2 = interp<Real, DIM, true, false, true>(g, f.B2, st);
+      const Real B3 = interp<Real, DIM, true, true, false>(g, f.B3, st);
+
+      // relativistic Boris push
+      const Real a = q.half_qmdt;
+      const Real um1 = p.u1[i] + a * E1, um2 = p.u2[i] + a * E2, um3 = p.u3[i] + a * E3;
+      const Real gm = sqrt(Real(1) + um1 * um1 + um2 * um2 + um3 * um3);
+      const Real t1 = a * B1 / gm, t2 = a * B2 / gm, t3 = a * B3 / gm;
+      const Real t2s = t1 * t1 + t2 * t2 + t3 * t3;
+      const Real f2 = Real(2) / (Real(1) + t2s);
+      const Real s1v = f2 * t1, s2v = f2 * t2, s3v = f2 * t3;
+      const Real up1 = um1 + (um2 * t3 - um3 * t2);
+      const Real up2 = um2 + (um3 * t1 - um1 * t3);
+      const Real up3 = um3 + (um1 * t2 - um2 * t1);
+      const Real un1 = um1 + (up2 * s3v - up3 * s2v) + a * E1;
+      const Real un2 = um2 + (up3 * s1v - up1 * s3v) + a * E2;
+      const Real un3 = um3 + (up1 * s2v - up2 * s1v) + a * E3;
+      const Real gn = sqrt(Real(1) + un1 * un1 + un2 * un2 + un3 * un3);
+      const Real ig = Real(1) / gn;
+      if (!(un1 == un1) || !(un2 == un2) || !(un3 == un3)) atomicOr(err, 2);
+
+      // x^{n+1} = x^n + dt u / gamma, in cell units, as cell + offset
+      const Real un[3] = {un1, un2, un3};
+      int sh[3] = {0, 0, 0};
+      Real on[3] = {o[0], o[1], o[2]};
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const Real dlt = q.dtdx[d] * un[d] * ig;
+        if (!(dlt < Real(1) && dlt > Real(-1))) atomicOr(err, 1);
+        const Real v = o[d] + dlt;
+        int kk = 0;
+        if (v >= Real(0.5))
+          kk = 1;
+        else if (v < Real(-0.5))
+          kk = -1;
+        sh[d] = kk;
+        on[d] = v - Real(kk);
+      }
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) m.base[d] = esirkepov_1d(o[d], sh[d], on[d], m.S0[d], m.DS[d], m.cum[d]);
+      if (DIM == 2) {
+        // the out-of-plane direction carries the time-averaged shape weight
+        m.jz = q.fv * un3 * ig;
+      }
+
+      // store the new state
+      const int n1c = c1 + sh[0];
+      bool alive = true;
+      if (g.window) {
+        const int after = n1c - q.shift;  // window cell after this step's shift
+        if (after < 2 || after > g.n1 - 3) alive = false;
+      }
+      if (!alive) {
+        p.cell[i] = -1;
+      } else {
+        const int ns1 = col_of(g, n1c);
+        const int ns2 = wrap(c2 + sh[1], g.n2);
+        const int ns3 = DIM == 3 ? wrap(c3 + sh[2], g.n3) : 0;
+        p.cell[i] = ns1 + g.n1 * (ns2 + g.n2 * ns3);
+        p.o1[i] = on[0];
+        p.o2[i] = on[1];
+        if (DIM == 3) p.o3[i] = on[2];
+        p.u1[i] = un1;
+        p.u2[i] = un2;
+        p.u3[i] = un3;
+      }
+    }
+    deposit_wave<Real, DIM>(active, m, q, sk);
+  }
+
+  // ---- flush the tile to HBM: one atomic per non-zero point
+  if (sk.tile) {
+    __syncthreads();
+    for (int t = tid; t < 3 * sk.tn; t += kPushBlock) {
+      const Real v = tile[t];
+      if (v == Real(0)) continue;
+      const int comp = t / sk.tn;
+      int r = t - comp * sk.tn;
+      const int a = r % sk.T1;
+      r /= sk.T1;
+      const int b = r % sk.T2;
+      const int c = r / sk.T2;
+      const int col = col_of(g, sk.t1 + a);
+      if (col < 0) continue;
+      const long long row = (long long)g.n1 * (wrap(sk.t2 + b, g.n2) + (long long)g.n2 * wrap(sk.t3 + c, g.n3));
+      Real *Jc = comp == 0 ? sk.J[0] : (comp == 1 ? sk.J[1] : sk.J[2]);
+      atomicAdd(Jc + row + col, v);
+    }
+  }
 }
 
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const Particles<Real> &p,
-                         const PushParams<Real> &q, int *err, hipStream_t st) {
+                         const PushParams<Real> &q, int K, int *err, hipStream_t st) {
   if (p.n <= 0) return;
-  const unsigned blocks = (unsigned)((p.n + 255) / 256);
+  const long long per = (long long)kPushBlock * K;
+  const unsigned blocks = (unsigned)((p.n + per - 1) / per);
   if (ndim == 3)
-    k_push_deposit<Real, 3><<<blocks, 256, 0, st>>>(g, f, p, q, err);
+    k_push_deposit<Real, 3><<<blocks, kPushBlock, 0, st>>>(g, f, p, q, K, err);
   else
-    k_push_deposit<Real, 2><<<blocks, 256, 0, st>>>(g, f, p, q, err);
+    k_push_deposit<Real, 2><<<blocks, kPushBlock, 0, st>>>(g, f, p, q, K, err);
 }
 
-template void launch_push_deposit<float>(int, const Geo &, const Fields<float> &, const Particles<float> &,
-                                         const PushParams<float> &, int *, hipStream_t);
-template void launch_push_deposit<double>(int, const Geo &, const Fields<double> &, const Particles<double> &,
-                                          const PushParams<double> &, int *, hipStream_t);
+// ---- particle sort (cell order) ---------------------------------------------------
+
+template <typename Real>
+__global__ void k_sort_keys(Particles<Real> p, unsigned *keys, unsigned *idx) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const int c = p.cell[i];
+  keys[i] = c < 0 ? 0xFFFFFFFFu : (unsigned)c;
+  idx[i] = (unsigned)i;
+}
+
+template <typename Real>
+__global__ void k_permute(Particles<Real> src, Particles<Real> dst, const int *id_src, int *id_dst,
+                          const unsigned *perm, int ndim, unsigned long long *alive) {
+  const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (j >= src.n) return;
+  const long long i = perm[j];
+  const int c = src.cell[i];
+  dst.cell[j] = c;
+  dst.o1[j] = src.o1[i];
+  dst.o2[j] = src.o2[i];
+  if (ndim == 3) dst.o3[j] = src.o3[i];
+  dst.u1[j] = src.u1[i];
+  dst.u2[j] = src.u2[i];
+  dst.u3[j] = src.u3[i];
+  id_dst[j] = id_src[i];
+  if (c >= 0) atomicAdd(alive, 1ULL);
+}
+
+// number of distinct alive cells in a sorted key array (density estimate)
+__global__ void k_count_runs(const unsigned *keys, long long n, unsigned long long *runs) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned k = keys[i];
+  if (k != 0xFFFFFFFFu && (i == 0 || keys[i - 1] != k)) atomicAdd(runs, 1ULL);
+}
+
+void launch_count_runs(const unsigned *keys, long long n, unsigned long long *runs, hipStream_t st) {
+  if (n <= 0) return;
+  k_count_runs<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(keys, n, runs);
+}
+
+template <typename Real>
+void launch_sort_keys(const Particles<Real> &p, unsigned *keys, unsigned *idx, hipStream_t st) {
+  if (p.n <= 0) return;
+  k_sort_keys<Real><<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(p, keys, idx);
+}
+
+template <typename Real>
+void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, const int *id_src, int *id_dst,
+                    const unsigned *perm, int ndim, unsigned long long *alive, hipStream_t st) {
+  if (src.n <= 0) return;
+  k_permute<Real><<<(unsigned)((src.n + 255) / 256), 256, 0, st>>>(src, dst, id_src, id_dst, perm, ndim, alive);
+}
+
+#define RELPIC_INST_PART(Real)                                                                                   \
+  template void launch_push_deposit<Real>(int, const Geo &, const Fields<Real> &, const Particles<Real> &,      \
+                                          const PushParams<Real> &, int, int *, hipStream_t);                  \
+  template void launch_sort_keys<Real>(const Particles<Real> &, unsigned *, unsigned *, hipStream_t);           \
+  template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \
+                                     const unsigned *, int, unsigned long long *, hipStream_t);
+
+RELPIC_INST_PART(float)
+RELPIC_INST_PART(double)
 
 }  // namespace relpic

@@ -25,7 +25,7 @@ EXPORTS = (
     "relpic_set_injection", "relpic_set_background_rho", "relpic_step", "relpic_sync", "relpic_read_field",
     "relpic_write_field", "relpic_field_device_ptr", "relpic_read_particles", "relpic_diagnostics",
     "relpic_get_step", "relpic_correction_halfwidth", "relpic_profile_enable", "relpic_profile_read",
-    "relpic_last_error",
+    "relpic_sort_particles", "relpic_set_sort_interval", "relpic_last_error",
 )
 KERNEL_CLASSES = ("push_deposit", "jcorr", "bhalf", "efull", "window")
 
@@ -100,7 +100,9 @@ def load():
     L.relpic_write_field.argtypes = [P, ctypes.c_int, dp, I64]
     L.relpic_field_device_ptr.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ip]
     L.relpic_read_particles.argtypes = [P, ctypes.c_int, I64, ctypes.POINTER(ctypes.c_int32), dp, dp,
-                                        ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(I64)]
+                                        ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    L.relpic_sort_particles.argtypes = [P]
+    L.relpic_set_sort_interval.argtypes = [P, I64]
     L.relpic_diagnostics.argtypes = [P, ctypes.POINTER(Diag)]
     L.relpic_get_step.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.relpic_correction_halfwidth.argtypes = [P, ip]
@@ -275,17 +277,31 @@ class Sim:
         check(load().relpic_field_device_ptr(self.h, FIELDS.index(name), ctypes.byref(p), ctypes.byref(eb)))
         return p.value, eb.value
 
-    def particles(self, species, cap):
+    def particles(self, species, cap, order_by_id=True):
+        """(cell, offset, u, alive) of every slot; by default reordered by
+        particle id (load order), so runs can be compared slot by slot."""
         cell = np.zeros((cap, self.ndim), dtype=np.int32)
         off = np.zeros((cap, self.ndim))
         u = np.zeros((cap, 3))
         alive = np.zeros(cap, dtype=np.uint8)
+        ids = np.zeros(cap, dtype=np.int64)
         n = ctypes.c_int64()
         check(load().relpic_read_particles(self.h, species, cap, cell.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                            _dp(off), _dp(u), alive.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
-                                           ctypes.byref(n)))
+                                           ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(n)))
         k = n.value
-        return cell[:k], off[:k], u[:k], alive[:k].astype(bool)
+        cell, off, u, alive, ids = cell[:k], off[:k], u[:k], alive[:k].astype(bool), ids[:k]
+        if order_by_id:
+            o = np.argsort(ids, kind="stable")
+            cell, off, u, alive, ids = cell[o], off[o], u[o], alive[o], ids[o]
+        self.last_ids = ids
+        return cell, off, u, alive
+
+    def sort_particles(self):
+        check(load().relpic_sort_particles(self.h))
+
+    def set_sort_interval(self, n):
+        check(load().relpic_set_sort_interval(self.h, int(n)))
 
     def diagnostics(self):
         d = Diag()
