@@ -42,12 +42,10 @@ def algorithmic_bytes(kernel, ncells, npart, esz):
     """Algorithmic HBM bytes of one launch of each kernel class."""
     if kernel == "push_deposit":   # particle state read + written: cell int32 + 3 offsets + 3 momenta
         return npart * 2 * (4 + 6 * esz)
-    if kernel == "bhalf":          # E read, B read + written
+    if kernel == "curl_e":         # E read, B read, B written (B at the next half step)
         return ncells * 9 * esz
-    if kernel == "efull":          # B, E, J read; E written; J cleared
-        return ncells * 15 * esz
-    if kernel == "jcorr":          # J1 read, corrected J1 written
-        return ncells * 2 * esz
+    if kernel == "curl_b":         # B read, E read + written
+        return ncells * 9 * esz
     return 0
 
 
@@ -176,7 +174,7 @@ def main():
     ms = 1e3 * r["wall_s"] / args.steps
     cell_rate = ncells * args.steps / r["wall_s"]
     part_rate = npart * args.steps / r["wall_s"]
-    step_bytes = ncells * 18 * esz + npart * 2 * (4 + 6 * esz)
+    step_bytes = ncells * 18 * esz + npart * 2 * (4 + 6 * esz)  # E, B read + written; particle state
 
     # dominant kernel and its roofline
     prof = r["prof"]

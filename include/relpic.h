@@ -202,9 +202,9 @@ relpic_status relpic_correction_halfwidth(relpic_sim *sim, int *halfwidth);
 
 /* Per-kernel timing with HIP events recorded on the bound stream around every
  * launch (adds a small gap between launches; off by default).  Kernel classes:
- * 0 push+deposit, 1 J1 correction, 2 B half step, 3 E step, 4 window shift
- * and injection. */
-#define RELPIC_NUM_KERNEL_CLASSES 5
+ * 0 push+deposit, 1 J1 correction, 2 B update (curl E), 3 E update (curl B),
+ * 4 window shift and injection, 5 current added to E inside the deposit box. */
+#define RELPIC_NUM_KERNEL_CLASSES 6
 typedef struct {
   int64_t launches[RELPIC_NUM_KERNEL_CLASSES];
   double total_ms[RELPIC_NUM_KERNEL_CLASSES];

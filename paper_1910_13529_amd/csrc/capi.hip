@@ -72,7 +72,9 @@ struct relpic_sim {
   relpic_device dev{};
   hipStream_t st = nullptr;
   long long N = 0;
-  void *F[10] = {};  // E1 E2 E3 B1 B2 B3 J1 J2 J3 J1c
+  void *F[10] = {};  // E1 E2 E3 B1 B2 B3 J1 J2 J3 J1c; B holds B^n between calls
+  void *Bx[3] = {};  // second B buffer (B at the other half-integer time inside a call)
+  JBox *jbox = nullptr;  // two deposit boxes, alternating by step parity
   void *taps = nullptr;
   int ng = 0;
   std::vector<Species> sp;
@@ -239,30 +241,68 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
 }
 
 template <typename Real>
+Axial<Real> axial_scaled(const relpic_sim *s, double c) {
+  Axial<Real> ax{};
+  ax.M = s->M;
+  for (int l = 0; l < s->M; ++l) ax.c[l] = (Real)(s->C[l] * c / s->dx[0]);
+  return ax;
+}
+
+// Bout = Bin - c curl+ E (c = dt for a full step, +-dt/2 for half steps)
+template <typename Real>
+void curl_e(relpic_sim *s, const Geo &g, Real *const Bin[3], Real *const Bout[3], double c) {
+  const Fields<Real> f = fields<Real>(s);
+  const Real h2 = (Real)(c / s->dx[1]), h3 = (Real)(s->ndim == 3 ? c / s->dx[2] : 0.0);
+  launch_curl_e<Real>(s->ndim, g, f, Bin, Bout, axial_scaled<Real>(s, c), h2, h3, s->st);
+}
+
+template <typename Real>
 relpic_status do_steps(relpic_sim *s, long long nsteps) {
+  if (nsteps == 0) return RELPIC_OK;
   const double dt = s->grid.dt;
   const double dV = cell_volume(s);
-  Fields<Real> f = fields<Real>(s);
-  Axial<Real> axB{}, axE{};
-  axB.M = axE.M = s->M;
-  for (int l = 0; l < s->M; ++l) {
-    axB.c[l] = (Real)(s->C[l] * 0.5 * dt / s->dx[0]);
-    axE.c[l] = (Real)(s->C[l] * dt / s->dx[0]);
-  }
-  const Real h2 = (Real)(0.5 * dt / s->dx[1]), h3 = (Real)(s->ndim == 3 ? 0.5 * dt / s->dx[2] : 0.0);
+  const Axial<Real> axE = axial_scaled<Real>(s, dt);
   const Real e2 = (Real)(dt / s->dx[1]), e3 = (Real)(s->ndim == 3 ? dt / s->dx[2] : 0.0);
   const bool window = s->grid.bc1 == RELPIC_BC_WINDOW;
+  Real *Ba[3] = {(Real *)s->F[3], (Real *)s->F[4], (Real *)s->F[5]};
+  Real *Bb[3] = {(Real *)s->Bx[0], (Real *)s->Bx[1], (Real *)s->Bx[2]};
+  auto swapB = [&]() {
+    for (int d = 0; d < 3; ++d) std::swap(Ba[d], Bb[d]);
+  };
+  // prologue: B^{n-1/2} = B^n + (dt/2) curl+ E^n
+  {
+    ProfScope ps(s, 2);
+    curl_e<Real>(s, make_geo(s), Ba, Bb, -0.5 * dt);
+  }
+  swapB();
+  relpic_status status = RELPIC_OK;
   for (long long it = 0; it < nsteps; ++it) {
     for (auto &sp : s->sp)
       if (sp.dirty || (s->sort_interval > 0 && s->step % s->sort_interval == 0 && it > 0))
-        if (relpic_status r = do_sort<Real>(s, sp)) return r;
+        if ((status = do_sort<Real>(s, sp))) break;
+    if (status) break;
     int shift = 0;
     if (window) {
       const long long tgt = window_target(s, s->step + 1);
-      if (tgt - s->ws > 1) return fail(RELPIC_EUNSTABLE, "window moves more than one cell per step");
+      if (tgt - s->ws > 1) {
+        status = fail(RELPIC_EUNSTABLE, "window moves more than one cell per step");
+        break;
+      }
       shift = tgt > s->ws ? 1 : 0;
     }
     const Geo g = make_geo(s);
+    JBox *box = s->jbox + (s->step & 1);
+    JBox *next = s->jbox + ((s->step + 1) & 1);
+    // B^{n+1/2} = B^{n-1/2} - dt curl+ E^n
+    {
+      ProfScope ps(s, 2);
+      curl_e<Real>(s, g, Ba, Bb, dt);
+    }
+    Fields<Real> f = fields<Real>(s);
+    f.B1 = Ba[0];
+    f.B2 = Ba[1];
+    f.B3 = Ba[2];
+    const HalfB<Real> Bh{Bb[0], Bb[1], Bb[2]};
     for (auto &sp : s->sp) {
       PushParams<Real> q{};
       q.half_qmdt = (Real)(0.5 * sp.qm * dt);
@@ -273,44 +313,64 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       q.fv = (Real)(sp.Q / dV);
       q.shift = shift;
       ProfScope ps(s, 0);
-      launch_push_deposit<Real>(s->ndim, g, f, parts<Real>(sp), q, sp.K, s->err, s->st);
+      launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, sp.K, box, s->err, s->st);
     }
     const Real *J1src = f.J1;
     if (s->M > 1) {
       ProfScope ps(s, 1);
-      launch_jcorr<Real>(g, f.J1, f.J1c, (const Real *)s->taps, s->ng, s->st);
+      launch_jcorr<Real>(g, f.J1, f.J1c, (const Real *)s->taps, s->ng, box, s->st);
       J1src = f.J1c;
     }
-    {
-      ProfScope ps(s, 2);
-      launch_bhalf<Real>(s->ndim, g, f, axB, h2, h3, s->st);
-    }
+    // E^{n+1} = E^n + dt (curl- B^{n+1/2} - J^{n+1/2})
+    f.B1 = Bb[0];
+    f.B2 = Bb[1];
+    f.B3 = Bb[2];
     {
       ProfScope ps(s, 3);
-      launch_efull<Real>(s->ndim, g, f, J1src, axE, e2, e3, (Real)dt, s->st);
+      launch_curl_b<Real>(s->ndim, g, f, axE, e2, e3, s->st);
     }
     {
-      ProfScope ps(s, 2);
-      launch_bhalf<Real>(s->ndim, g, f, axB, h2, h3, s->st);
+      ProfScope ps(s, 5);
+      launch_add_j<Real>(g, f, J1src, (Real)dt, box, s->M > 1 ? s->ng : 0, next, s->st);
     }
+    swapB();
     s->step += 1;
     if (shift) {
       ProfScope ps(s, 4);
-      launch_zero_column<Real>(g, f, g.ws_mod, s->st);
+      Fields<Real> fz = fields<Real>(s);
+      fz.B1 = Ba[0];
+      fz.B2 = Ba[1];
+      fz.B3 = Ba[2];
+      launch_new_slab<Real>(g, fz, Bb, g.ws_mod, axial_scaled<Real>(s, 0.5 * dt), s->st);
       s->ws += 1;
       const Geo g2 = make_geo(s);
       for (auto &sp : s->sp) {
         if (!sp.inject) continue;
         const long long nnew = (long long)sp.ppc[0] * sp.ppc[1] * sp.ppc[2] * s->n[1] * s->n[2];
-        if (sp.n + nnew > sp.cap) return fail(RELPIC_ERANGE, "injection exceeds species capacity");
+        if (sp.n + nnew > sp.cap) {
+          status = fail(RELPIC_ERANGE, "injection exceeds species capacity");
+          break;
+        }
         launch_inject_slab<Real>(s->ndim, g2, parts<Real>(sp), sp.id, sp.n, s->n[0] - 3, sp.ppc[0], sp.ppc[1],
                                  sp.ppc[2], sp.uth, sp.seed, sp.inj_count, sp.next_id, s->st);
         sp.n += nnew;
         sp.next_id += nnew;
         sp.inj_count += (unsigned long long)nnew;
       }
+      if (status) break;
     }
   }
+  // epilogue: B^{n+1} = B^{n+1/2} - (dt/2) curl+ E^{n+1}, back in the canonical buffer
+  {
+    ProfScope ps(s, 2);
+    curl_e<Real>(s, make_geo(s), Ba, Bb, 0.5 * dt);
+  }
+  swapB();
+  for (int d = 0; d < 3; ++d) {
+    s->F[3 + d] = Ba[d];
+    s->Bx[d] = Bb[d];
+  }
+  if (status) return status;
   HIP_OK(hipGetLastError());
   return RELPIC_OK;
 }
@@ -463,11 +523,20 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
       return fail(RELPIC_ENOMEM, "create: field allocation failed");
     }
   }
+  for (int d = 0; d < 3; ++d) {
+    s->Bx[d] = dev_alloc(s, s->esz * N);
+    if (!s->Bx[d]) {
+      dev_free_all(s);
+      delete s;
+      return fail(RELPIC_ENOMEM, "create: field allocation failed");
+    }
+  }
+  s->jbox = (JBox *)dev_alloc(s, 2 * sizeof(JBox));
   s->err = (int *)dev_alloc(s, 64);
   s->dbuf = (double *)dev_alloc(s, 8 * sizeof(double));
   s->rho = (double *)dev_alloc(s, sizeof(double) * N);
   s->taps = dev_alloc(s, s->esz * (kMaxTaps + 1));
-  if (!s->err || !s->dbuf || !s->rho || !s->taps) {
+  if (!s->err || !s->dbuf || !s->rho || !s->taps || !s->jbox) {
     dev_free_all(s);
     delete s;
     return fail(RELPIC_ENOMEM, "create: allocation failed");
@@ -475,7 +544,13 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
   hipError_t e = hipSuccess;
   for (int k = 0; k < 10 && e == hipSuccess; ++k)
     if (s->F[k]) e = hipMemsetAsync(s->F[k], 0, s->esz * N, s->st);
+  for (int d = 0; d < 3 && e == hipSuccess; ++d) e = hipMemsetAsync(s->Bx[d], 0, s->esz * N, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->err, 0, 64, s->st);
+  if (e == hipSuccess) {
+    launch_reset_box(s->jbox, s->st);
+    launch_reset_box(s->jbox + 1, s->st);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess && M > 1) {
     std::vector<unsigned char> host(s->esz * taps.size());
     for (size_t i = 0; i < taps.size(); ++i) {

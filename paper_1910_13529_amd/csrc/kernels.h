@@ -14,21 +14,34 @@ struct PushParams {
   int shift;       // 1 if the window advances after this step
 };
 
+// Bout = Bin - curl+ E with the time factor folded into ax, h2, h3
 template <typename Real>
-void launch_bhalf(int ndim, const Geo &g, const Fields<Real> &f, const Axial<Real> &ax, Real h2, Real h3,
+void launch_curl_e(int ndim, const Geo &g, const Fields<Real> &f, Real *const Bin[3], Real *const Bout[3],
+                   const Axial<Real> &ax, Real h2, Real h3, hipStream_t st);
+// E += curl- B (f.B*), time factor folded into ax, e2, e3
+template <typename Real>
+void launch_curl_b(int ndim, const Geo &g, const Fields<Real> &f, const Axial<Real> &ax, Real e2, Real e3,
+                   hipStream_t st);
+// E -= dt J inside the J box (x1 widened by pad), J cleared there, `next` box reset
+template <typename Real>
+void launch_add_j(const Geo &g, const Fields<Real> &f, const Real *J1src, Real dt, const JBox *box, int pad,
+                  JBox *next, hipStream_t st);
+template <typename Real>
+void launch_jcorr(const Geo &g, const Real *J1, Real *J1c, const Real *taps, int ng, const JBox *box,
                   hipStream_t st);
+// new leading slab after a window shift: E = 0, B (f.B*, at n + 1/2) such
+// that B^{n+1} = 0 there, other B buffer Bx cleared
 template <typename Real>
-void launch_efull(int ndim, const Geo &g, const Fields<Real> &f, const Real *J1src, const Axial<Real> &ax, Real e2,
-                  Real e3, Real dt, hipStream_t st);
-template <typename Real>
-void launch_jcorr(const Geo &g, const Real *J1, Real *J1c, const Real *taps, int ng, hipStream_t st);
-template <typename Real>
-void launch_zero_column(const Geo &g, const Fields<Real> &f, int col, hipStream_t st);
+void launch_new_slab(const Geo &g, const Fields<Real> &f, Real *const Bx[3], int col, const Axial<Real> &ax,
+                     hipStream_t st);
+void launch_reset_box(JBox *b, hipStream_t st);
+
 // K particles per thread; each workgroup handles a contiguous chunk of
 // 256 * K particles (sorted by cell for the LDS-tiled deposit to pay off)
 template <typename Real>
-void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const Particles<Real> &p,
-                         const PushParams<Real> &q, int K, int *err, hipStream_t st);
+void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
+                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *jbox, int *err,
+                         hipStream_t st);
 
 // ---- particle sort by cell ------------------------------------------------------
 template <typename Real>

@@ -47,51 +47,58 @@ __device__ __forceinline__ int qw_half(int c, Real o, Real w[3]) {
   return c - 1;
 }
 
+// Gather stencils of one particle: storage columns (x1), row offsets (x2 as
+// n1 * i2, x3 as n1 * n2 * i3) and weights, for node (N) and half-integer (H)
+// points.
 template <typename Real>
 struct Stagger {
-  int bN[3], bH[3];
+  int colN[3], colH[3];
+  long long rowN2[3], rowH2[3], rowN3[3], rowH3[3];
   Real wN[3][3], wH[3][3];
 };
 
 // Interpolate one field component; H1..H3 select half-integer (staggered)
-// or node weights along each dimension.
-template <typename Real, int DIM, bool H1, bool H2, bool H3>
-__device__ __forceinline__ Real interp(const Geo &g, const Real *f, const Stagger<Real> &s) {
-  const int b1 = H1 ? s.bH[0] : s.bN[0];
-  const int b2 = H2 ? s.bH[1] : s.bN[1];
-  int cols[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) cols[a] = col_of(g, b1 - 1 + a);
+// or node weights along each dimension.  With f2 non-null the field is the
+// average of f and f2 (B at integer time from its two half-step values).
+template <typename Real, int DIM, bool H1, bool H2, bool H3, bool AVG>
+__device__ __forceinline__ Real interp(const Stagger<Real> &s, const Real *f, const Real *f2) {
+  const int *cols = H1 ? s.colH : s.colN;
+  const long long *r2 = H2 ? s.rowH2 : s.rowN2;
   Real acc = 0;
   if (DIM == 2) {
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const long long row = (long long)g.n1 * wrap(b2 - 1 + b, g.n2);
       Real r = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
-        if (cols[a] >= 0) r += (H1 ? s.wH[0][a] : s.wN[0][a]) * f[row + cols[a]];
+        if (cols[a] >= 0) {
+          const long long id = r2[b] + cols[a];
+          const Real v = AVG ? f[id] + f2[id] : f[id];
+          r += (H1 ? s.wH[0][a] : s.wN[0][a]) * v;
+        }
       acc += (H2 ? s.wH[1][b] : s.wN[1][b]) * r;
     }
   } else {
-    const int b3 = H3 ? s.bH[2] : s.bN[2];
+    const long long *r3 = H3 ? s.rowH3 : s.rowN3;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const int i3 = wrap(b3 - 1 + c, g.n3);
       Real rc = 0;
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const long long row = (long long)g.n1 * (wrap(b2 - 1 + b, g.n2) + (long long)g.n2 * i3);
         Real r = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-          if (cols[a] >= 0) r += (H1 ? s.wH[0][a] : s.wN[0][a]) * f[row + cols[a]];
+          if (cols[a] >= 0) {
+            const long long id = r2[b] + r3[c] + cols[a];
+            const Real v = AVG ? f[id] + f2[id] : f[id];
+            r += (H1 ? s.wH[0][a] : s.wN[0][a]) * v;
+          }
         rc += (H2 ? s.wH[1][b] : s.wN[1][b]) * r;
       }
       acc += (H3 ? s.wH[2][c] : s.wN[2][c]) * rc;
     }
   }
-  return acc;
+  return AVG ? Real(0.5) * acc : acc;
 }
 
 // Esirkepov shape arrays on four nodes starting at old cell + base:
@@ -137,9 +144,9 @@ struct Sink {
         return;
       }
     }
-    const int col = col_of(g, x1);
+    const int col = col_near(g, x1);
     if (col < 0) return;
-    const long long row = (long long)g.n1 * (wrap(x2, g.n2) + (long long)g.n2 * wrap(x3, g.n3));
+    const long long row = (long long)g.n1 * (wrap_near(x2, g.n2) + (long long)g.n2 * wrap_near(x3, g.n3));
     atomicAdd(J[comp] + row + col, v);
   }
 };
@@ -327,8 +334,9 @@ __device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, 
 }
 
 template <typename Real, int DIM>
-__global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real> f, Particles<Real> p,
-                                                             PushParams<Real> q, int K, int *err) {
+__global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real> f, HalfB<Real> Bh,
+                                                             Particles<Real> p, PushParams<Real> q, int K,
+                                                             JBox *jbox, int *err) {
   __shared__ __align__(16) unsigned char tile_raw[kTileBytes];
   __shared__ int box[6];
   Real *tile = reinterpret_cast<Real *>(tile_raw);
@@ -375,6 +383,27 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
     }
   }
   __syncthreads();
+  if (tid == 0 && box[0] != INT_MAX) {
+    // deposits of this chunk land within its old cells +- 2
+    int lo[3] = {box[0] - 2, box[2] - 2, DIM == 3 ? box[4] - 2 : 0};
+    int hi[3] = {box[1] + 2, box[3] + 2, DIM == 3 ? box[5] + 2 : 0};
+    const int nn[3] = {g.n1, g.n2, g.n3};
+    if (g.window) {
+      lo[0] = max(lo[0], 0);
+      hi[0] = min(hi[0], g.n1 - 1);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (lo[d] < 0 || hi[d] >= nn[d]) {
+        lo[d] = 0;
+        hi[d] = nn[d] - 1;
+      }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&jbox->lo[d], lo[d]);
+      atomicMax(&jbox->hi[d], hi[d]);
+    }
+  }
   Sink<Real> sk;
   sk.g = g;
   sk.J[0] = f.J1;
@@ -427,18 +456,50 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
       const Real o[3] = {p.o1[i], p.o2[i], DIM == 3 ? p.o3[i] : Real(0)};
 
       Stagger<Real> st;
+      int bH[3];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        st.bN[d] = m.c[d];
         qw(o[d], st.wN[d]);
-        st.bH[d] = qw_half(m.c[d], o[d], st.wH[d]);
+        bH[d] = qw_half(m.c[d], o[d], st.wH[d]);
       }
-      const Real E1 = interp<Real, DIM, true, false, false>(g, f.E1, st);
-      const Real E2 = interp<Real, DIM, false, true, false>(g, f.E2, st);
-      const Real E3 = interp<Real, DIM, false, false, true>(g, f.E3, st);
-      const Real B1 = interp<Real, DIM, false, true, true>(g, f.B1, st);
-      const Real B2 = interp<Real, DIM, true, false, true>(g, f.B2, st);
-      const Real B3 = interp<Real, DIM, true, true, false>(g, f.B3, st);
+      {
+        // window cells c-2 .. c+1 cover both stencils (half: bH-1 .. bH+1, bH in {c-1, c})
+        int cx[4];
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) cx[k2] = col_near(g, c1 - 2 + k2);
+        const bool hlo = bH[0] < c1;
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2) {
+          st.colN[a2] = cx[a2 + 1];
+          st.colH[a2] = hlo ? cx[a2] : cx[a2 + 1];
+        }
+        long long r2x[4];
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) r2x[k2] = (long long)g.n1 * wrap_near(c2 - 2 + k2, g.n2);
+        const bool h2lo = bH[1] < c2;
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2) {
+          st.rowN2[a2] = r2x[a2 + 1];
+          st.rowH2[a2] = h2lo ? r2x[a2] : r2x[a2 + 1];
+        }
+        if (DIM == 3) {
+          long long r3x[4];
+#pragma unroll
+          for (int k2 = 0; k2 < 4; ++k2) r3x[k2] = (long long)g.n1 * g.n2 * wrap_near(c3 - 2 + k2, g.n3);
+          const bool h3lo = bH[2] < c3;
+#pragma unroll
+          for (int a2 = 0; a2 < 3; ++a2) {
+            st.rowN3[a2] = r3x[a2 + 1];
+            st.rowH3[a2] = h3lo ? r3x[a2] : r3x[a2 + 1];
+          }
+        }
+      }
+      const Real E1 = interp<Real, DIM, true, false, false, false>(st, f.E1, nullptr);
+      const Real E2 = interp<Real, DIM, false, true, false, false>(st, f.E2, nullptr);
+      const Real E3 = interp<Real, DIM, false, false, true, false>(st, f.E3, nullptr);
+      const Real B1 = interp<Real, DIM, false, true, true, true>(st, f.B1, Bh.B1);
+      const Real B2 = interp<Real, DIM, true, false, true, true>(st, f.B2, Bh.B2);
+      const Real B3 = interp<Real, DIM, true, true, false, true>(st, f.B3, Bh.B3);
 
       // relativistic Boris push
       const Real a = q.half_qmdt;
@@ -519,9 +580,10 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
       r /= sk.T1;
       const int b = r % sk.T2;
       const int c = r / sk.T2;
-      const int col = col_of(g, sk.t1 + a);
+      const int col = col_near(g, sk.t1 + a);
       if (col < 0) continue;
-      const long long row = (long long)g.n1 * (wrap(sk.t2 + b, g.n2) + (long long)g.n2 * wrap(sk.t3 + c, g.n3));
+      const long long row =
+          (long long)g.n1 * (wrap_near(sk.t2 + b, g.n2) + (long long)g.n2 * wrap_near(sk.t3 + c, g.n3));
       Real *Jc = comp == 0 ? sk.J[0] : (comp == 1 ? sk.J[1] : sk.J[2]);
       atomicAdd(Jc + row + col, v);
     }
@@ -529,15 +591,16 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
 }
 
 template <typename Real>
-void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const Particles<Real> &p,
-                         const PushParams<Real> &q, int K, int *err, hipStream_t st) {
+void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
+                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *jbox, int *err,
+                         hipStream_t st) {
   if (p.n <= 0) return;
   const long long per = (long long)kPushBlock * K;
   const unsigned blocks = (unsigned)((p.n + per - 1) / per);
   if (ndim == 3)
-    k_push_deposit<Real, 3><<<blocks, kPushBlock, 0, st>>>(g, f, p, q, K, err);
+    k_push_deposit<Real, 3><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, jbox, err);
   else
-    k_push_deposit<Real, 2><<<blocks, kPushBlock, 0, st>>>(g, f, p, q, K, err);
+    k_push_deposit<Real, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, jbox, err);
 }
 
 // ---- particle sort (cell order) ---------------------------------------------------
@@ -596,8 +659,9 @@ void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, cons
 }
 
 #define RELPIC_INST_PART(Real)                                                                                   \
-  template void launch_push_deposit<Real>(int, const Geo &, const Fields<Real> &, const Particles<Real> &,      \
-                                          const PushParams<Real> &, int, int *, hipStream_t);                  \
+  template void launch_push_deposit<Real>(int, const Geo &, const Fields<Real> &, const HalfB<Real> &,          \
+                                          const Particles<Real> &, const PushParams<Real> &, int, JBox *, int *, \
+                                          hipStream_t);                                                          \
   template void launch_sort_keys<Real>(const Particles<Real> &, unsigned *, unsigned *, hipStream_t);           \
   template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \
                                      const unsigned *, int, unsigned long long *, hipStream_t);

@@ -33,6 +33,12 @@ struct Axial {
   Real c[kMaxM];
 };
 
+// The second B buffer (B at the other half-integer time).
+template <typename Real>
+struct HalfB {
+  const Real *B1, *B2, *B3;
+};
+
 template <typename Real>
 struct Particles {
   int *cell;  // packed storage index s1 + n1 * (s2 + n2 * s3); -1 = dropped
@@ -56,5 +62,22 @@ __device__ __forceinline__ int wrap(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;
 }
+
+// wrap for indices known to lie in [-n, 2n)
+__device__ __forceinline__ int wrap_near(int i, int n) {
+  i = i < 0 ? i + n : i;
+  return i >= n ? i - n : i;
+}
+
+// col_of for window cells within one grid length of the window ([-n1, 2 n1))
+__device__ __forceinline__ int col_near(const Geo &g, int l) {
+  if (g.window && (l < 0 || l >= g.n1)) return -1;
+  return wrap_near(l + g.ws_mod, g.n1);
+}
+
+// Current bounding box of deposited J: window x1 and wrapped x2, x3 (min, max).
+struct JBox {
+  int lo[3], hi[3];
+};
 
 }  // namespace relpic

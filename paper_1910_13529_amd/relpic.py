@@ -27,7 +27,7 @@ EXPORTS = (
     "relpic_get_step", "relpic_correction_halfwidth", "relpic_profile_enable", "relpic_profile_read",
     "relpic_sort_particles", "relpic_set_sort_interval", "relpic_last_error",
 )
-KERNEL_CLASSES = ("push_deposit", "jcorr", "bhalf", "efull", "window")
+KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j")
 
 
 class RelpicError(RuntimeError):
@@ -65,7 +65,7 @@ class Diag(ctypes.Structure):
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 5), ("total_ms", ctypes.c_double * 5)]
+    _fields_ = [("launches", ctypes.c_int64 * 6), ("total_ms", ctypes.c_double * 6)]
 
 
 _lib = None
