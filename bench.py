@@ -153,7 +153,19 @@ def main():
     ap.add_argument("--npart", type=int, default=1 << 22)
     ap.add_argument("--solvers", default="custom,yee")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the PIC step here is a single-GPU build "
               "(multi-GPU sharding along x2/x3 is a design note, not implemented); use --gpus 1", file=sys.stderr)

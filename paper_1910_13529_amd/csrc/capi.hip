@@ -457,7 +457,9 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
       return fail(RELPIC_EINVAL, "create: bad n or dx");
     N *= grid->n[d];
   }
-  if (N >= (1LL << 31)) return fail(RELPIC_EINVAL, "create: grid exceeds 2^31 cells");
+  // kernels address field arrays with 32-bit byte offsets
+  if (N * (prec == RELPIC_FP64 ? 8LL : 4LL) >= (1LL << 32))
+    return fail(RELPIC_EINVAL, "create: field arrays above 4 GiB each (2^30 cells FP32, 2^29 FP64)");
   if (grid->n[0] < 8 || grid->n[1] < 2 || (grid->ndim == 3 && grid->n[2] < 2))
     return fail(RELPIC_EINVAL, "create: grid too small (n1 >= 8, n2, n3 >= 2)");
   if (grid->n[1] > 65535 || (grid->ndim == 3 && grid->n[2] > 65535))

@@ -70,26 +70,63 @@ __global__ __launch_bounds__(kRedBlock) void k_kinetic(Particles<Real> p, double
   }
 }
 
+// rho of the particles (FP64).  Lanes of a wavefront that share the first
+// active lane's cell (the common case for cell-sorted particles) sum their
+// 3 x 3 (x 3) node weights across the wavefront first, one atomic per node.
 template <typename Real, int DIM>
 __global__ __launch_bounds__(kRedBlock) void k_rho(Geo g, Particles<Real> p, double qdv, double *rho) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  const int packed = p.cell[i];
-  if (packed < 0) return;
-  const int s1 = packed % g.n1;
-  const int rest = packed / g.n1;
-  const int c2 = rest % g.n2;
-  const int c3 = DIM == 3 ? rest / g.n2 : 0;
-  int c1 = s1 - g.ws_mod;
-  if (c1 < 0) c1 += g.n1;
-  double w[3][3];
-  const double o[3] = {(double)p.o1[i], (double)p.o2[i], DIM == 3 ? (double)p.o3[i] : 0.0};
-  for (int d = 0; d < DIM; ++d) {
-    const double a = 0.5 - o[d], b = 0.5 + o[d];
-    w[d][0] = 0.5 * a * a;
-    w[d][1] = 0.75 - o[d] * o[d];
-    w[d][2] = 0.5 * b * b;
+  const int packed = (i < p.n) ? p.cell[i] : -1;
+  const bool active = packed >= 0;
+  int c1 = 0, c2 = 0, c3 = 0;
+  double w[3][3] = {{0, 0, 0}, {0, 0, 0}, {1, 0, 0}};
+  if (active) {
+    const int s1 = packed % g.n1;
+    const int rest = packed / g.n1;
+    c2 = rest % g.n2;
+    c3 = DIM == 3 ? rest / g.n2 : 0;
+    c1 = s1 - g.ws_mod;
+    if (c1 < 0) c1 += g.n1;
+    const double o[3] = {(double)p.o1[i], (double)p.o2[i], DIM == 3 ? (double)p.o3[i] : 0.0};
+    for (int d = 0; d < DIM; ++d) {
+      const double a = 0.5 - o[d], b = 0.5 + o[d];
+      w[d][0] = 0.5 * a * a;
+      w[d][1] = 0.75 - o[d] * o[d];
+      w[d][2] = 0.5 * b * b;
+    }
   }
+  const unsigned long long act = __ballot(active);
+  if (act == 0ULL) return;
+  const int first = __ffsll((long long)act) - 1;
+  const int k1 = __shfl(c1, first, 64), k2 = __shfl(c2, first, 64), k3 = __shfl(c3, first, 64);
+  const bool same = active && c1 == k1 && c2 == k2 && c3 == k3;
+  constexpr int S = DIM == 3 ? 27 : 9;
+  double v[S];
+  for (int k = 0; k < S; ++k) v[k] = same ? qdv * w[0][k % 3] * w[1][(k / 3) % 3] * (DIM == 3 ? w[2][k / 9] : 1.0) : 0.0;
+  const int lane = threadIdx.x & 63;
+  int off = 0;
+  int size = S;
+  for (int bit = 32; bit >= 1; bit >>= 1) {
+    const int h = (size + 1) / 2;
+    const bool up = (lane & bit) != 0;
+    for (int j = 0; j < h; ++j) {
+      const double lo = v[j];
+      const double hi = (j + h < size) ? v[j + h] : 0.0;
+      const double send = up ? lo : hi;
+      v[j] = (up ? hi : lo) + __shfl_xor(send, bit, 64);
+    }
+    if (up) off += h;
+    size = h;
+  }
+  if (off < S && v[0] != 0.0) {
+    const int a = off % 3, b = (off / 3) % 3, c = off / 9;
+    const int col = col_of(g, k1 - 1 + a);
+    if (col >= 0) {
+      const long long row = (long long)g.n1 * (wrap(k2 - 1 + b, g.n2) + (long long)g.n2 * (DIM == 3 ? wrap(k3 - 1 + c, g.n3) : 0));
+      atomicAdd(rho + row + col, v[0]);
+    }
+  }
+  if (!active || same) return;
   for (int cc = 0; cc < (DIM == 3 ? 3 : 1); ++cc) {
     const int i3 = DIM == 3 ? wrap(c3 - 1 + cc, g.n3) : 0;
     const double w3 = DIM == 3 ? w[2][cc] : 1.0;

@@ -47,39 +47,45 @@ __device__ __forceinline__ int qw_half(int c, Real o, Real w[3]) {
   return c - 1;
 }
 
-// Gather stencils of one particle: storage columns (x1), row offsets (x2 as
-// n1 * i2, x3 as n1 * n2 * i3) and weights, for node (N) and half-integer (H)
-// points.
+// Gather stencils of one particle: element offsets of the x1 columns and of
+// the x2 (n1 * i2) and x3 (n1 * n2 * i3) rows, for node (N) and half-integer
+// (H) points, and the weights.  Offsets are 32-bit (the library keeps every
+// field array below 4 GiB) so loads take a scalar base plus one vector
+// offset; x1 points outside the moving window carry weight 0 and a valid
+// dummy column.
 template <typename Real>
 struct Stagger {
-  int colN[3], colH[3];
-  long long rowN2[3], rowH2[3], rowN3[3], rowH3[3];
+  unsigned colN[3], colH[3];
+  unsigned rowN2[3], rowH2[3], rowN3[3], rowH3[3];
   Real wN[3][3], wH[3][3];
 };
 
-// Interpolate one field component; H1..H3 select half-integer (staggered)
-// or node weights along each dimension.  With f2 non-null the field is the
-// average of f and f2 (B at integer time from its two half-step values).
+// Load element `id` through a 32-bit byte offset from the array base.
+template <typename Real>
+__device__ __forceinline__ Real ld32(const Real *__restrict__ f, unsigned id) {
+  return *reinterpret_cast<const Real *>(reinterpret_cast<const char *>(f) + (unsigned)(id * (unsigned)sizeof(Real)));
+}
+
 template <typename Real, int DIM, bool H1, bool H2, bool H3, bool AVG>
-__device__ __forceinline__ Real interp(const Stagger<Real> &s, const Real *f, const Real *f2) {
-  const int *cols = H1 ? s.colH : s.colN;
-  const long long *r2 = H2 ? s.rowH2 : s.rowN2;
+__device__ __forceinline__ Real interp(const Stagger<Real> &s, const Real *__restrict__ f,
+                                       const Real *__restrict__ f2) {
+  const unsigned *cols = H1 ? s.colH : s.colN;
+  const unsigned *r2 = H2 ? s.rowH2 : s.rowN2;
   Real acc = 0;
   if (DIM == 2) {
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       Real r = 0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        if (cols[a] >= 0) {
-          const long long id = r2[b] + cols[a];
-          const Real v = AVG ? f[id] + f2[id] : f[id];
-          r += (H1 ? s.wH[0][a] : s.wN[0][a]) * v;
-        }
+      for (int a = 0; a < 3; ++a) {
+        const unsigned id = r2[b] + cols[a];
+        const Real v = AVG ? ld32(f, id) + ld32(f2, id) : ld32(f, id);
+        r += (H1 ? s.wH[0][a] : s.wN[0][a]) * v;
+      }
       acc += (H2 ? s.wH[1][b] : s.wN[1][b]) * r;
     }
   } else {
-    const long long *r3 = H3 ? s.rowH3 : s.rowN3;
+    const unsigned *r3 = H3 ? s.rowH3 : s.rowN3;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       Real rc = 0;
@@ -87,12 +93,11 @@ __device__ __forceinline__ Real interp(const Stagger<Real> &s, const Real *f, co
       for (int b = 0; b < 3; ++b) {
         Real r = 0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-          if (cols[a] >= 0) {
-            const long long id = r2[b] + r3[c] + cols[a];
-            const Real v = AVG ? f[id] + f2[id] : f[id];
-            r += (H1 ? s.wH[0][a] : s.wN[0][a]) * v;
-          }
+        for (int a = 0; a < 3; ++a) {
+          const unsigned id = r2[b] + r3[c] + cols[a];
+          const Real v = AVG ? ld32(f, id) + ld32(f2, id) : ld32(f, id);
+          r += (H1 ? s.wH[0][a] : s.wN[0][a]) * v;
+        }
         rc += (H2 ? s.wH[1][b] : s.wN[1][b]) * r;
       }
       acc += (H3 ? s.wH[2][c] : s.wN[2][c]) * rc;
@@ -124,6 +129,17 @@ __device__ __forceinline__ int esirkepov_1d(Real o0, int sh, Real o1, Real S0[4]
   return base;
 }
 
+typedef __attribute__((address_space(3))) float lds_f32;
+typedef __attribute__((address_space(3))) double lds_f64;
+
+// atomic add to a workgroup-shared (LDS) address: ds_add_f32 / ds_add_f64
+__device__ __forceinline__ void lds_add(float *p, float v) {
+  __hip_atomic_fetch_add((lds_f32 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(double *p, double v) {
+  __hip_atomic_fetch_add((lds_f64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Where deposits go: the workgroup's LDS tile if it covers the point, else
 // J in HBM.  Coordinates are the window x1 index and unwrapped x2, x3.
 template <typename Real>
@@ -140,7 +156,7 @@ struct Sink {
     if (tile) {
       const int a = x1 - t1, b = x2 - t2, c = x3 - t3;
       if (a >= 0 && a < T1 && b >= 0 && b < T2 && c >= 0 && c < T3) {
-        atomicAdd(tile + comp * tn + a + T1 * (b + T2 * c), v);
+        lds_add(tile + comp * tn + a + T1 * (b + T2 * c), v);
         return;
       }
     }
@@ -168,26 +184,29 @@ __device__ __forceinline__ void rs_level(Real *v, int lane, int bit, int &off) {
   if (up) off += H;
 }
 
-// 80 (3D) or 20 (2D) box values summed over the wavefront; returns with each
-// lane holding values for box indices off, off + 1 (3D) or off (2D).
-template <typename Real, int DIM>
+// Sum v[0..S) over the 64 lanes of the wavefront (S <= 64); afterwards each
+// lane holds in v[0] the total for index `off` (padding when off >= S).
+template <typename Real, int S, int BIT>
 __device__ __forceinline__ void reduce_scatter(Real *v, int lane, int &off) {
-  off = 0;
-  if (DIM == 3) {
-    rs_level<Real, 80>(v, lane, 32, off);
-    rs_level<Real, 40>(v, lane, 16, off);
-    rs_level<Real, 20>(v, lane, 8, off);
-    rs_level<Real, 10>(v, lane, 4, off);
-    rs_level<Real, 5>(v, lane, 2, off);
-    rs_level<Real, 3>(v, lane, 1, off);
-  } else {
-    rs_level<Real, 20>(v, lane, 32, off);
-    rs_level<Real, 10>(v, lane, 16, off);
-    rs_level<Real, 5>(v, lane, 8, off);
-    rs_level<Real, 3>(v, lane, 4, off);
-    rs_level<Real, 2>(v, lane, 2, off);
-    rs_level<Real, 1>(v, lane, 1, off);
+  if constexpr (BIT >= 1) {
+    rs_level<Real, S>(v, lane, BIT, off);
+    reduce_scatter<Real, (S + 1) / 2, BIT / 2>(v, lane, off);
   }
+}
+
+// Reduce an N1 x N2 x N3 box of per-lane values over the wavefront and add
+// the totals (one per lane) to the sink at box origin (x1, x2, x3).
+template <typename Real, int N1, int N2, int N3, typename F>
+__device__ __forceinline__ void box_reduce_add(const Sink<Real> &sk, int comp, int lane, bool fits, int x1, int x2,
+                                               int x3, F val) {
+  constexpr int S = N1 * N2 * N3;
+  static_assert(S <= 64, "box larger than a wavefront");
+  Real v[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) v[k] = fits ? val(k % N1, (k / N1) % N2, k / (N1 * N2)) : Real(0);
+  int off = 0;
+  reduce_scatter<Real, S, 32>(v, lane, off);
+  if (off < S) sk.add(comp, x1 + off % N1, x2 + (off / N1) % N2, x3 + off / (N1 * N2), v[0]);
 }
 
 // Everything the deposit needs from one pushed particle.
@@ -269,8 +288,14 @@ __device__ __forceinline__ Real ext5(const Real *in, int o, int b) {
 }
 
 // Wavefront-collective deposit (every lane of the wave must call it).
+// A lane joins the reduction when it lies in the wave's (x2, x3) row, does not
+// cross a transverse cell boundary this step, and its x1 stencil starts at
+// most one node after the wave's leftmost one.  Its exact supports are then
+// J1: 4 x 3 x 3 half/node points, J2: 5 x 2 x 3, J3: 5 x 3 x 2 (2D: 4 x 3,
+// 5 x 2, 5 x 3), all inside boxes that every such lane shares.
 template <typename Real, int DIM>
-__device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, const PushParams<Real> &q, const Sink<Real> &sk) {
+__device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, const PushParams<Real> &q,
+                                             const Sink<Real> &sk) {
   const int lane = threadIdx.x & 63;
   const unsigned long long act = __ballot(active);
   if (act == 0ULL) return;
@@ -282,50 +307,46 @@ __device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, 
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) cmin = min(cmin, __shfl_xor(cmin, o, 64));
   const int o1 = m.c[0] + m.base[0] - (cmin - 1);
-  const bool fits = inrow && (o1 == 0 || o1 == 1) && m.base[1] == -1 && (DIM == 2 || m.base[2] == -1);
+  // no transverse crossing: base -1 and no DS on the fourth node
+  const bool flat2 = m.base[1] == -1 && m.DS[1][3] == Real(0);
+  const bool flat3 = DIM == 2 || (m.base[2] == -1 && m.DS[2][3] == Real(0));
+  const bool fits = inrow && (o1 == 0 || o1 == 1) && flat2 && flat3;
   const unsigned long long fm = __ballot(fits);
-  if (__popcll(fm) >= 8) {
-    constexpr int NB = DIM == 3 ? 80 : 20;
+  if (__popcll(fm) >= 4) {
     const int oo = fits ? o1 : 0;
-    Real e1S0[5], e1DS[5], e1cum[5];
+    Real e1S0[5], e1DS[5];
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
       e1S0[b] = ext5(m.S0[0], oo, b);
       e1DS[b] = ext5(m.DS[0], oo, b);
-      e1cum[b] = ext5(m.cum[0], oo, b);
     }
-#pragma unroll
-    for (int comp = 0; comp < 3; ++comp) {
-      Real v[NB];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const int b = k % 5, a2 = (k / 5) % 4, a3 = k / 20;
-        Real val = 0;
-        if (DIM == 2) {
-          if (comp == 0) val = (b - oo >= 0 && b - oo <= 2) ? q.f1 * e1cum[b] * (m.S0[1][a2] + Real(0.5) * m.DS[1][a2]) : Real(0);
-          if (comp == 1) val = (a2 <= 2) ? q.f2 * m.cum[1][a2] * (e1S0[b] + Real(0.5) * e1DS[b]) : Real(0);
-          if (comp == 2) val = m.jz * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2);
-        } else {
-          if (comp == 0)
-            val = (b - oo >= 0 && b - oo <= 2) ? q.f1 * e1cum[b] * wperp(m.S0[1], m.DS[1], m.S0[2], m.DS[2], a2, a3)
-                                               : Real(0);
-          if (comp == 1)
-            val = (a2 <= 2) ? q.f2 * m.cum[1][a2] * wperp(e1S0, e1DS, m.S0[2], m.DS[2], b, a3) : Real(0);
-          if (comp == 2)
-            val = (a3 <= 2) ? q.f3 * m.cum[2][a3] * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2) : Real(0);
-        }
-        v[k] = fits ? val : Real(0);
-      }
-      int off;
-      reduce_scatter<Real, DIM>(v, lane, off);
-#pragma unroll
-      for (int j = 0; j < (DIM == 3 ? 2 : 1); ++j) {
-        const int k = off + j;
-        if (k < NB) {
-          const int b = k % 5, a2 = (k / 5) % 4, a3 = k / 20;
-          sk.add(comp, cmin - 1 + b, c2w - 1 + a2, DIM == 3 ? c3w - 1 + a3 : 0, v[j]);
-        }
-      }
+    // J1 at x1 half points: running sum of DS1 (three entries) shifted by oo
+    auto cum1 = [&](int b) -> Real {
+      const Real lo = (b <= 2) ? m.cum[0][b] : Real(0);
+      const Real hi = (b >= 1 && b <= 3) ? m.cum[0][b - 1] : Real(0);
+      return oo ? hi : lo;
+    };
+    const int x1 = cmin - 1, x2 = c2w - 1, x3 = DIM == 3 ? c3w - 1 : 0;
+    if (DIM == 3) {
+      box_reduce_add<Real, 4, 3, 3>(sk, 0, lane, fits, x1, x2, x3, [&](int b, int a2, int a3) {
+        return q.f1 * cum1(b) * wperp(m.S0[1], m.DS[1], m.S0[2], m.DS[2], a2, a3);
+      });
+      box_reduce_add<Real, 5, 2, 3>(sk, 1, lane, fits, x1, x2, x3, [&](int b, int a2, int a3) {
+        return q.f2 * m.cum[1][a2] * wperp(e1S0, e1DS, m.S0[2], m.DS[2], b, a3);
+      });
+      box_reduce_add<Real, 5, 3, 2>(sk, 2, lane, fits, x1, x2, x3, [&](int b, int a2, int a3) {
+        return q.f3 * m.cum[2][a3] * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2);
+      });
+    } else {
+      box_reduce_add<Real, 4, 3, 1>(sk, 0, lane, fits, x1, x2, 0, [&](int b, int a2, int) {
+        return q.f1 * cum1(b) * (m.S0[1][a2] + Real(0.5) * m.DS[1][a2]);
+      });
+      box_reduce_add<Real, 5, 2, 1>(sk, 1, lane, fits, x1, x2, 0, [&](int b, int a2, int) {
+        return q.f2 * m.cum[1][a2] * (e1S0[b] + Real(0.5) * e1DS[b]);
+      });
+      box_reduce_add<Real, 5, 3, 1>(sk, 2, lane, fits, x1, x2, 0, [&](int b, int a2, int) {
+        return m.jz * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2);
+      });
     }
     if (active && !fits) deposit_direct<Real, DIM>(m, q, sk);
   } else if (active) {
@@ -470,12 +491,15 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
         const bool hlo = bH[0] < c1;
 #pragma unroll
         for (int a2 = 0; a2 < 3; ++a2) {
-          st.colN[a2] = cx[a2 + 1];
-          st.colH[a2] = hlo ? cx[a2] : cx[a2 + 1];
+          const int cn = cx[a2 + 1], ch = hlo ? cx[a2] : cx[a2 + 1];
+          st.colN[a2] = cn < 0 ? 0u : (unsigned)cn;
+          st.colH[a2] = ch < 0 ? 0u : (unsigned)ch;
+          if (cn < 0) st.wN[0][a2] = Real(0);
+          if (ch < 0) st.wH[0][a2] = Real(0);
         }
-        long long r2x[4];
+        unsigned r2x[4];
 #pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) r2x[k2] = (long long)g.n1 * wrap_near(c2 - 2 + k2, g.n2);
+        for (int k2 = 0; k2 < 4; ++k2) r2x[k2] = (unsigned)g.n1 * (unsigned)wrap_near(c2 - 2 + k2, g.n2);
         const bool h2lo = bH[1] < c2;
 #pragma unroll
         for (int a2 = 0; a2 < 3; ++a2) {
@@ -483,9 +507,10 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
           st.rowH2[a2] = h2lo ? r2x[a2] : r2x[a2 + 1];
         }
         if (DIM == 3) {
-          long long r3x[4];
+          unsigned r3x[4];
 #pragma unroll
-          for (int k2 = 0; k2 < 4; ++k2) r3x[k2] = (long long)g.n1 * g.n2 * wrap_near(c3 - 2 + k2, g.n3);
+          for (int k2 = 0; k2 < 4; ++k2)
+            r3x[k2] = (unsigned)g.n1 * (unsigned)g.n2 * (unsigned)wrap_near(c3 - 2 + k2, g.n3);
           const bool h3lo = bH[2] < c3;
 #pragma unroll
           for (int a2 = 0; a2 < 3; ++a2) {
