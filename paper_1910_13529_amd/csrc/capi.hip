@@ -75,6 +75,8 @@ struct relpic_sim {
   void *F[10] = {};  // E1 E2 E3 B1 B2 B3 J1 J2 J3 J1c; B holds B^n between calls
   void *Bx[3] = {};  // second B buffer (B at the other half-integer time inside a call)
   JBox *jbox = nullptr;  // two deposit boxes, alternating by step parity
+  JBox *blockbox = nullptr;  // per-workgroup deposit boxes of the push kernel
+  long long blockbox_n = 0;
   void *taps = nullptr;
   int ng = 0;
   std::vector<Species> sp;
@@ -312,9 +314,19 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       q.f3 = (Real)(s->ndim == 3 ? -sp.Q * s->dx[2] / (dV * dt) : 0.0);
       q.fv = (Real)(sp.Q / dV);
       q.shift = shift;
+      const long long nb = push_blocks(sp.n, sp.K);
+      if (nb > s->blockbox_n) {
+        s->blockbox = (JBox *)dev_alloc(s, sizeof(JBox) * (size_t)nb);
+        if (!s->blockbox) {
+          status = fail(RELPIC_ENOMEM, "step: allocation of workgroup boxes failed");
+          break;
+        }
+        s->blockbox_n = nb;
+      }
       ProfScope ps(s, 0);
-      launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, sp.K, box, s->err, s->st);
+      launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, sp.K, s->blockbox, box, s->err, s->st);
     }
+    if (status) break;
     const Real *J1src = f.J1;
     if (s->M > 1) {
       ProfScope ps(s, 1);

@@ -38,10 +38,12 @@ void launch_reset_box(JBox *b, hipStream_t st);
 
 // K particles per thread; each workgroup handles a contiguous chunk of
 // 256 * K particles (sorted by cell for the LDS-tiled deposit to pay off)
+// blockbox: push_blocks(n, K) scratch boxes, merged into *jbox after the launch
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
-                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *jbox, int *err,
-                         hipStream_t st);
+                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *blockbox, JBox *jbox,
+                         int *err, hipStream_t st);
+long long push_blocks(long long n, int K);
 
 // ---- particle sort by cell ------------------------------------------------------
 template <typename Real>

@@ -23,7 +23,23 @@
 namespace relpic {
 
 constexpr int kPushBlock = 256;
-constexpr int kTileBytes = 24576;  // LDS current tile per workgroup
+constexpr int kTileBytes = 49152;  // LDS tile per workgroup: J (3 components) + E, B (6)
+
+typedef __attribute__((address_space(3))) float lds_f32;
+typedef __attribute__((address_space(3))) double lds_f64;
+
+// atomic add to a workgroup-shared (LDS) address: ds_add_f32 / ds_add_f64
+__device__ __forceinline__ void lds_add(float *p, float v) {
+  __hip_atomic_fetch_add((lds_f32 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(double *p, double v) {
+  __hip_atomic_fetch_add((lds_f64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// load from a workgroup-shared (LDS) address
+__device__ __forceinline__ float lds_ld(const float *p) { return *(const lds_f32 *)p; }
+__device__ __forceinline__ double lds_ld(const double *p) { return *(const lds_f64 *)p; }
+
 
 // quadratic B-spline weights at nodes -1, 0, +1 for a particle at offset d
 // from node 0 (d in [-1/2, 1/2])
@@ -106,6 +122,38 @@ __device__ __forceinline__ Real interp(const Stagger<Real> &s, const Real *__res
   return AVG ? Real(0.5) * acc : acc;
 }
 
+// Gather from the workgroup's LDS copy of E and B (B already averaged to
+// integer time): tile offsets of the x1 cells c-2 .. c+1 and of the x2/x3
+// rows c-2 .. c+1 (scaled by the tile strides).
+struct StaggerL {
+  int x1[4], x2[4], x3[4];
+  bool h1lo, h2lo, h3lo;
+};
+
+template <typename Real, int DIM, bool H1, bool H2, bool H3>
+__device__ __forceinline__ Real interp_lds(const StaggerL &s, const Real wN[3][3], const Real wH[3][3],
+                                           const Real *ft) {
+  Real acc = 0;
+#pragma unroll
+  for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) {
+    const int z = DIM == 3 ? ((H3 && s.h3lo) ? s.x3[c] : s.x3[c + 1]) : 0;
+    Real rc = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int y = (H2 && s.h2lo) ? s.x2[b] : s.x2[b + 1];
+      Real r = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int x = (H1 && s.h1lo) ? s.x1[a] : s.x1[a + 1];
+        r += (H1 ? wH[0][a] : wN[0][a]) * lds_ld(ft + x + y + z);
+      }
+      rc += (H2 ? wH[1][b] : wN[1][b]) * r;
+    }
+    acc += DIM == 3 ? (H3 ? wH[2][c] : wN[2][c]) * rc : rc;
+  }
+  return acc;
+}
+
 // Esirkepov shape arrays on four nodes starting at old cell + base:
 // S0 at x^n, DS = S(x^{n+1}) - S(x^n); cum = running sum of DS.
 template <typename Real>
@@ -127,17 +175,6 @@ __device__ __forceinline__ int esirkepov_1d(Real o0, int sh, Real o1, Real S0[4]
     cum[a] = run;
   }
   return base;
-}
-
-typedef __attribute__((address_space(3))) float lds_f32;
-typedef __attribute__((address_space(3))) double lds_f64;
-
-// atomic add to a workgroup-shared (LDS) address: ds_add_f32 / ds_add_f64
-__device__ __forceinline__ void lds_add(float *p, float v) {
-  __hip_atomic_fetch_add((lds_f32 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_add(double *p, double v) {
-  __hip_atomic_fetch_add((lds_f64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Where deposits go: the workgroup's LDS tile if it covers the point, else
@@ -357,7 +394,7 @@ __device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, 
 template <typename Real, int DIM>
 __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real> f, HalfB<Real> Bh,
                                                              Particles<Real> p, PushParams<Real> q, int K,
-                                                             JBox *jbox, int *err) {
+                                                             JBox *blockbox, int *err) {
   __shared__ __align__(16) unsigned char tile_raw[kTileBytes];
   __shared__ int box[6];
   Real *tile = reinterpret_cast<Real *>(tile_raw);
@@ -404,25 +441,34 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
     }
   }
   __syncthreads();
-  if (tid == 0 && box[0] != INT_MAX) {
-    // deposits of this chunk land within its old cells +- 2
+  if (tid == 0) {
+    // deposits of this chunk land within its old cells +- 2; empty chunks
+    // write an empty box
     int lo[3] = {box[0] - 2, box[2] - 2, DIM == 3 ? box[4] - 2 : 0};
     int hi[3] = {box[1] + 2, box[3] + 2, DIM == 3 ? box[5] + 2 : 0};
     const int nn[3] = {g.n1, g.n2, g.n3};
-    if (g.window) {
-      lo[0] = max(lo[0], 0);
-      hi[0] = min(hi[0], g.n1 - 1);
-    }
+    if (box[0] == INT_MAX) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-      if (lo[d] < 0 || hi[d] >= nn[d]) {
-        lo[d] = 0;
-        hi[d] = nn[d] - 1;
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = INT_MAX;
+        hi[d] = -INT_MAX;
+      }
+    } else {
+      if (g.window) {
+        lo[0] = max(lo[0], 0);
+        hi[0] = min(hi[0], g.n1 - 1);
       }
 #pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (lo[d] < 0 || hi[d] >= nn[d]) {
+          lo[d] = 0;
+          hi[d] = nn[d] - 1;
+        }
+    }
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      atomicMin(&jbox->lo[d], lo[d]);
-      atomicMax(&jbox->hi[d], hi[d]);
+      blockbox[blockIdx.x].lo[d] = lo[d];
+      blockbox[blockIdx.x].hi[d] = hi[d];
     }
   }
   Sink<Real> sk;
@@ -439,16 +485,42 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
   if (box[0] != INT_MAX) {
     const long long T1 = (long long)box[1] - box[0] + 5, T2 = (long long)box[3] - box[2] + 5;
     const long long T3 = DIM == 3 ? (long long)box[5] - box[4] + 5 : 1;
-    if (3 * T1 * T2 * T3 * (long long)sizeof(Real) <= kTileBytes) {
+    if (9 * T1 * T2 * T3 * (long long)sizeof(Real) <= kTileBytes) {
       sk.T1 = (int)T1;
       sk.T2 = (int)T2;
       sk.T3 = (int)T3;
       sk.tn = (int)(T1 * T2 * T3);
       sk.tile = tile;
-      for (int t = tid; t < 3 * sk.tn; t += kPushBlock) tile[t] = Real(0);
+      // J part cleared; E and B^n staged for the gather (zero outside the window)
+      const int tn = sk.tn;
+      for (int t = tid; t < 9 * tn; t += kPushBlock) {
+        const int comp = t / tn;
+        Real v = Real(0);
+        if (comp >= 3) {
+          int r = t - comp * tn;
+          const int a = r % sk.T1;
+          r /= sk.T1;
+          const int b = r % sk.T2;
+          const int c = r / sk.T2;
+          const int col = col_of(g, sk.t1 + a);
+          if (col >= 0) {
+            const long long id = (long long)g.n1 * (wrap(sk.t2 + b, g.n2) + (long long)g.n2 * wrap(sk.t3 + c, g.n3)) + col;
+            switch (comp) {
+              case 3: v = f.E1[id]; break;
+              case 4: v = f.E2[id]; break;
+              case 5: v = f.E3[id]; break;
+              case 6: v = Real(0.5) * (f.B1[id] + Bh.B1[id]); break;
+              case 7: v = Real(0.5) * (f.B2[id] + Bh.B2[id]); break;
+              default: v = Real(0.5) * (f.B3[id] + Bh.B3[id]); break;
+            }
+          }
+        }
+        tile[t] = v;
+      }
     }
   }
   __syncthreads();
+  const bool lds_fields = sk.tile != nullptr;
 
   // ---- gather, push, move and deposit, K particles per thread
   for (int k = 0; k < K; ++k) {
@@ -476,6 +548,7 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
       m.c[2] = c3;
       const Real o[3] = {p.o1[i], p.o2[i], DIM == 3 ? p.o3[i] : Real(0)};
 
+      Real E1, E2, E3, B1, B2, B3;
       Stagger<Real> st;
       int bH[3];
 #pragma unroll
@@ -483,6 +556,25 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
         qw(o[d], st.wN[d]);
         bH[d] = qw_half(m.c[d], o[d], st.wH[d]);
       }
+      if (lds_fields) {
+        StaggerL sl;
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+          sl.x1[k2] = c1 - 2 + k2 - sk.t1;
+          sl.x2[k2] = sk.T1 * (c2 - 2 + k2 - sk.t2);
+          sl.x3[k2] = sk.T1 * sk.T2 * (c3 - 2 + k2 - sk.t3);
+        }
+        sl.h1lo = bH[0] < c1;
+        sl.h2lo = bH[1] < c2;
+        sl.h3lo = DIM == 3 && bH[2] < c3;
+        const Real *ft = tile + 3 * sk.tn;
+        E1 = interp_lds<Real, DIM, true, false, false>(sl, st.wN, st.wH, ft);
+        E2 = interp_lds<Real, DIM, false, true, false>(sl, st.wN, st.wH, ft + sk.tn);
+        E3 = interp_lds<Real, DIM, false, false, true>(sl, st.wN, st.wH, ft + 2 * sk.tn);
+        B1 = interp_lds<Real, DIM, false, true, true>(sl, st.wN, st.wH, ft + 3 * sk.tn);
+        B2 = interp_lds<Real, DIM, true, false, true>(sl, st.wN, st.wH, ft + 4 * sk.tn);
+        B3 = interp_lds<Real, DIM, true, true, false>(sl, st.wN, st.wH, ft + 5 * sk.tn);
+      } else {
       {
         // window cells c-2 .. c+1 cover both stencils (half: bH-1 .. bH+1, bH in {c-1, c})
         int cx[4];
@@ -519,12 +611,14 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
           }
         }
       }
-      const Real E1 = interp<Real, DIM, true, false, false, false>(st, f.E1, nullptr);
-      const Real E2 = interp<Real, DIM, false, true, false, false>(st, f.E2, nullptr);
-      const Real E3 = interp<Real, DIM, false, false, true, false>(st, f.E3, nullptr);
-      const Real B1 = interp<Real, DIM, false, true, true, true>(st, f.B1, Bh.B1);
-      const Real B2 = interp<Real, DIM, true, false, true, true>(st, f.B2, Bh.B2);
-      const Real B3 = interp<Real, DIM, true, true, false, true>(st, f.B3, Bh.B3);
+      E1 = interp<Real, DIM, true, false, false, false>(st, f.E1, nullptr);
+      E2 = interp<Real, DIM, false, true, false, false>(st, f.E2, nullptr);
+      E3 = interp<Real, DIM, false, false, true, false>(st, f.E3, nullptr);
+      B1 = interp<Real, DIM, false, true, true, true>(st, f.B1, Bh.B1);
+      B2 = interp<Real, DIM, true, false, true, true>(st, f.B2, Bh.B2);
+      B3 = interp<Real, DIM, true, true, false, true>(st, f.B3, Bh.B3);
+
+      }
 
       // relativistic Boris push
       const Real a = q.half_qmdt;
@@ -615,17 +709,46 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
   }
 }
 
+// Box of a set of per-workgroup boxes merged into *out (one workgroup).
+__global__ __launch_bounds__(256) void k_merge_boxes(const JBox *boxes, int nbox, JBox *out) {
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {-INT_MAX, -INT_MAX, -INT_MAX};
+  for (int b = threadIdx.x; b < nbox; b += blockDim.x)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], boxes[b].lo[d]);
+      hi[d] = max(hi[d], boxes[b].hi[d]);
+    }
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
+    }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&out->lo[d], lo[d]);
+      atomicMax(&out->hi[d], hi[d]);
+    }
+}
+
+long long push_blocks(long long n, int K) {
+  const long long per = (long long)kPushBlock * K;
+  return n <= 0 ? 0 : (n + per - 1) / per;
+}
+
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
-                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *jbox, int *err,
-                         hipStream_t st) {
+                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *blockbox, JBox *jbox,
+                         int *err, hipStream_t st) {
   if (p.n <= 0) return;
-  const long long per = (long long)kPushBlock * K;
-  const unsigned blocks = (unsigned)((p.n + per - 1) / per);
+  const unsigned blocks = (unsigned)push_blocks(p.n, K);
   if (ndim == 3)
-    k_push_deposit<Real, 3><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, jbox, err);
+    k_push_deposit<Real, 3><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
   else
-    k_push_deposit<Real, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, jbox, err);
+    k_push_deposit<Real, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
+  k_merge_boxes<<<1, 256, 0, st>>>(blockbox, (int)blocks, jbox);
 }
 
 // ---- particle sort (cell order) ---------------------------------------------------
@@ -685,8 +808,8 @@ void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, cons
 
 #define RELPIC_INST_PART(Real)                                                                                   \
   template void launch_push_deposit<Real>(int, const Geo &, const Fields<Real> &, const HalfB<Real> &,          \
-                                          const Particles<Real> &, const PushParams<Real> &, int, JBox *, int *, \
-                                          hipStream_t);                                                          \
+                                          const Particles<Real> &, const PushParams<Real> &, int, JBox *, JBox *, \
+                                          int *, hipStream_t);                                                   \
   template void launch_sort_keys<Real>(const Particles<Real> &, unsigned *, unsigned *, hipStream_t);           \
   template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \
                                      const unsigned *, int, unsigned long long *, hipStream_t);
