@@ -13,7 +13,6 @@ step + E step + B half step + window bookkeeping.  Inputs are resident on the
 GPU before the timed region.
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -24,18 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-CSRC = os.path.join(ROOT, "paper_1910_13529_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
-
-
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(kernel, ncells, npart, esz):
@@ -200,6 +188,7 @@ def main():
         try:
             tf = json.load(open(TRAFFIC_FILE))
             ent = tf.get("kernels", {}).get("%s/%s/%s" % (head, args.precision, dom))
+            from paper_1910_13529_amd.profiling import kernel_source_hash
             if ent and tf.get("source_hash") == kernel_source_hash() and args.grid == "512,256,256":
                 traffic = ent["hbm_bytes_per_launch"]
         except Exception:
