@@ -87,6 +87,121 @@ def run_gpu(args, w, cell, off, u, Q, solver):
     return dict(wall_s=wall, event_ms=ev_ms, prof=prof, diag=diag, nprof=nprof)
 
 
+def run_batch(args):
+    """The batched workload: 256 independent 2D periodic runs (n1 in 128..1024,
+    n2 in 64..256, gamma log-uniform 1e1..1e5, dt/dx1 in 0.3..0.99, Yee and
+    customized mixed), 4096 particles each, one launch per phase over all
+    runs, graph-recorded, tile shapes from the autotuner."""
+    import torch
+    from paper_1910_13529_amd import workloads
+    from paper_1910_13529_amd.relpic import Batch
+    runs = workloads.batch_workload(256, solver=args.batch_solver)
+    b = Batch([r["grid"] for r in runs], [r["C"] for r in runs], precision=args.precision)
+    for br, r in zip(b.runs, runs):
+        sid = br.add_species(-1.0, r["Q"], len(r["cell"]))
+        br.load_particles(sid, r["cell"], r["offset"], r["u"])
+    b.step(1)
+    b.sync()
+    tune = b.autotune(reps=20)
+    stream = torch.cuda.current_stream()
+    b.step(args.warmup)
+    b.sync()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    b.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.sync()
+    ev_ms = ev0.elapsed_time(ev1)
+    # B update alone, timed again after the run (HIP events on the same stream)
+    tune_after = b.autotune(reps=20)
+    diag = [b.runs[k].diagnostics() for k in (0, 128, 255)]
+    b.close()
+    return runs, dict(wall_s=wall, event_ms=ev_ms, tune=tune, tune_after=tune_after, diag=diag)
+
+
+def batch_cpu_baseline(runs, nsample=8, steps=2):
+    """The FP64 oracle on `nsample` of the runs (every 256/nsample-th), `steps` full steps each."""
+    import numpy as np
+    from oracle.pic import OracleSim
+    picks = list(range(0, len(runs), max(1, len(runs) // nsample)))[:nsample]
+    tcells = tparts = tsec = 0.0
+    for k in picks:
+        r = runs[k]
+        g = r["grid"]
+        o = OracleSim(g["n"][:2], g["dx"][:2], g["dt"], C=[1.0] if r["C"] is None else list(r["C"]), window=False)
+        o.add_particles(r["cell"].astype(np.float64) + r["offset"], r["u"], r["Q"], -1.0)
+        t0 = time.perf_counter()
+        o.step(steps)
+        tsec += time.perf_counter() - t0
+        tcells += g["n"][0] * g["n"][1] * steps
+        tparts += len(r["cell"]) * steps
+        o.close()
+    return {"value": tcells / tsec, "unit": "cell-updates/s", "particle_steps_per_s": tparts / tsec, "cores": 1,
+            "kind": "oracle",
+            "sample": "FP64 C oracle, single thread: runs %s of the batched workload, %d full steps each "
+                      "(%.1f s in total)" % (picks, steps, tsec)}
+
+
+def batch_main(args):
+    runs, r = run_batch(args)
+    ncells = sum(x["grid"]["n"][0] * x["grid"]["n"][1] for x in runs)
+    npart = sum(len(x["cell"]) for x in runs)
+    esz = 4 if args.precision == "fp32" else 8
+    ms = 1e3 * r["wall_s"] / args.steps
+    avg_ms = r["tune_after"]["ms_chosen"]
+    alg = algorithmic_bytes("curl_e", ncells, npart, esz)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    step_bytes = ncells * 18 * esz + npart * 2 * (4 + 5 * esz)
+    out = {
+        "metric": "particle-steps/s + field cell-updates/s per PIC step; % HBM peak; FP32 vs FP64",
+        "value": ncells * args.steps / r["wall_s"],
+        "unit": "cell-updates/s",
+        "particle_steps_per_s": npart * args.steps / r["wall_s"],
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "event_ms_per_step": r["event_ms"] / args.steps,
+        "hbm_frac_step": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched: 256 independent 2D periodic single-bunch runs (n1 128..1024, n2 64..256, "
+                        "gamma log-uniform 1e1..1e5, dt/dx1 0.3..0.99, %s solvers), 4096 particles each, one "
+                        "launch per phase over all runs, graph-recorded" % args.batch_solver,
+            "cells": ncells,
+            "particles": npart,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "batch_curl_e",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_ms": avg_ms,
+            "algorithmic_bytes_per_launch": alg,
+        },
+        "autotune": r["tune"],
+        "diag": [{k: d[k] for k in ("step", "n_alive", "w_field", "gauss_max", "rho_max", "error_word")}
+                 for d in r["diag"]],
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = batch_cpu_baseline(runs)
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(args, w, cell, off, u, Q, solver):
     """The FP64 oracle on the host: a bounded sample of the same workload.
 
@@ -141,6 +256,9 @@ def main():
     ap.add_argument("--npart", type=int, default=1 << 22)
     ap.add_argument("--solvers", default="custom,yee")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="beam3d", choices=["beam3d", "batch"],
+                    help="beam3d: the 3D beam (default); batch: the 256-run batched workload")
+    ap.add_argument("--batch-solver", default="mixed", choices=["mixed", "yee", "custom"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -159,6 +277,9 @@ def main():
               "(multi-GPU sharding along x2/x3 is a design note, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch":
+        batch_main(args)
+        return
     w, cell, off, u, Q = make_workload(args)
     ncells = int(math.prod(w.n))
     npart = len(cell)

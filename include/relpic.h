@@ -203,8 +203,9 @@ relpic_status relpic_correction_halfwidth(relpic_sim *sim, int *halfwidth);
 /* Per-kernel timing with HIP events recorded on the bound stream around every
  * launch (adds a small gap between launches; off by default).  Kernel classes:
  * 0 push+deposit, 1 J1 correction, 2 B update (curl E), 3 E update (curl B),
- * 4 window shift and injection, 5 current added to E inside the deposit box. */
-#define RELPIC_NUM_KERNEL_CLASSES 6
+ * 4 window shift and injection, 5 current added to E inside the deposit box,
+ * 6 merge of the push workgroups' deposit boxes. */
+#define RELPIC_NUM_KERNEL_CLASSES 7
 typedef struct {
   int64_t launches[RELPIC_NUM_KERNEL_CLASSES];
   double total_ms[RELPIC_NUM_KERNEL_CLASSES];
@@ -215,6 +216,81 @@ relpic_status relpic_profile_enable(relpic_sim *sim, int on);
 
 /* Synchronize and return the totals accumulated since enabling. */
 relpic_status relpic_profile_read(relpic_sim *sim, relpic_profile *out);
+
+/* ---- Batched many-run path ------------------------------------------------
+ *
+ * A batch advances many independent 2D runs with a periodic x1 boundary,
+ * each with its own grid (n1, n2, dx1, dx2), time step and axial operator
+ * (Yee or customized, its own M and C_l) and its own particles, as one
+ * launch per phase of the step over all runs; the launches between two
+ * particle sorts are recorded once into a HIP graph and replayed.  Every run
+ * computes what a single relpic_sim with the same descriptors computes (the
+ * per-cell and per-particle device code is shared).
+ *
+ * Each run is a relpic_sim owned by the batch (relpic_batch_run): species,
+ * particle loads, field reads and writes and diagnostics use the single-run
+ * calls on that handle.  Calling relpic_step on a run handle is allowed; the
+ * batch notices and rebuilds its tables at its next step.  Runs may not use
+ * plasma injection.
+ *
+ * Field kernels work on tiles of SEG x1 cells times ROWS x2 rows (256
+ * threads): shape 0 = 256 x 1, 1 = 128 x 2, 2 = 64 x 4, chosen per run.  The
+ * default gives every run the shape with the fewest tiles;
+ * relpic_batch_autotune measures and picks. */
+typedef struct relpic_batch relpic_batch;
+
+/* Create nruns runs from grids[nruns] and solvers[nruns] (NULL: all Yee),
+ * with the validation of relpic_create per run.  RELPIC_EINVAL unless every
+ * grid is 2D with bc1 = RELPIC_BC_PERIODIC. */
+relpic_status relpic_batch_create(int nruns, const relpic_grid *grids, const relpic_solver *solvers,
+                                  relpic_precision prec, const relpic_device *dev, relpic_batch **out);
+
+/* Destroys the batch and its run handles. */
+relpic_status relpic_batch_destroy(relpic_batch *batch);
+
+/* Run handle (owned by the batch, valid until relpic_batch_destroy). */
+relpic_status relpic_batch_run(relpic_batch *batch, int run, relpic_sim **sim);
+
+/* Enqueue nsteps steps of every run on the bound stream (asynchronous).  The
+ * first step after particle loads sorts them (synchronizing); particles are
+ * re-sorted every graph_steps steps (every 20 with graphs off). */
+relpic_status relpic_batch_step(relpic_batch *batch, int64_t nsteps);
+
+/* Wait for the stream; RELPIC_EDEVICE if a kernel set the error word. */
+relpic_status relpic_batch_sync(relpic_batch *batch);
+
+/* Steps per recorded graph (even; 0 = launch every kernel directly).
+ * Default 20. */
+relpic_status relpic_batch_set_graph_steps(relpic_batch *batch, int steps);
+
+/* Tile shape per run (shape[nruns], values 0..2; NULL keeps the current
+ * shapes) and the field kernels' grid: grid_workgroups = 0 launches one
+ * workgroup per tile, a positive multiple of 8 launches that many
+ * persistent workgroups that loop over the tiles. */
+relpic_status relpic_batch_set_tiling(relpic_batch *batch, const int *shape, int grid_workgroups);
+relpic_status relpic_batch_get_tiling(relpic_batch *batch, int *shape, int *grid_workgroups);
+
+/* Autotuner report (times are per launch of the B update, in ms). */
+typedef struct {
+  double ms_uniform[3];    /* every run on shape 0, 1, 2; one workgroup per tile */
+  double ms_model;         /* per-run shapes from the fitted per-tile cost of each shape */
+  double ms_persistent[2]; /* best assignment on 2048 and 4096 persistent workgroups (0: not tried) */
+  double ms_chosen;
+  int choice;              /* 0..2: uniform shape, 3: per-run model */
+  int grid_workgroups;     /* field-kernel grid chosen */
+  int runs_per_shape[3];
+} relpic_batch_tune;
+
+/* Time the B update (curl E) of the whole batch under each uniform tile
+ * shape, fit a cost per tile for each shape, give every run the shape whose
+ * modelled cost (tiles x cost per tile) is lowest, time that, then try
+ * persistent grids; keep the fastest.  reps launches per timing.  Leaves the
+ * simulation state unchanged (the timed launches write only the B buffer
+ * that is free between calls).  Synchronizing. */
+relpic_status relpic_batch_autotune(relpic_batch *batch, int reps, relpic_batch_tune *out);
+
+/* relpic_read_field on one run. */
+relpic_status relpic_batch_read_field(relpic_batch *batch, int run, relpic_field f, double *host, int64_t count);
 
 const char *relpic_last_error(void);
 

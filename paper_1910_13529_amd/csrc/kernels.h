@@ -41,8 +41,10 @@ void launch_reset_box(JBox *b, hipStream_t st);
 // blockbox: push_blocks(n, K) scratch boxes, merged into *jbox after the launch
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
-                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *blockbox, JBox *jbox,
-                         int *err, hipStream_t st);
+                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *blockbox, int *err,
+                         hipStream_t st);
+// *jbox = union of the nbox per-workgroup boxes (atomic min/max into *jbox)
+void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStream_t st);
 long long push_blocks(long long n, int K);
 
 // ---- particle sort by cell ------------------------------------------------------

@@ -11,136 +11,27 @@
 // 256-cell segment of one x1 row; the row and its 2M-cell halo are staged
 // in LDS for the axial stencil, and workgroups are renumbered so that each
 // XCD sweeps a contiguous band of rows (neighbouring rows share its L2).
-#include "kernels.h"
+#include "field_tiles.h"
 
 namespace relpic {
 
-constexpr int kSeg = 256;
-constexpr int kNumXcd = 8;
-
-template <typename Real>
-__device__ __forceinline__ Real ldc(const Real *f, long long row, int col) {
-  return col >= 0 ? f[row + col] : Real(0);
-}
-
-// Workgroup -> (x1 segment, i2, i3), XCD-contiguous.  Returns false for the
-// padding workgroups of the last band.
-__device__ __forceinline__ bool tile_of(const Geo &g, int nseg, int &l0, int &i2, int &i3) {
-  const long long nb = (long long)nseg * g.n2 * g.n3;
-  const long long per = (nb + kNumXcd - 1) / kNumXcd;
-  const long long bid = blockIdx.x;
-  const long long lin = (bid % kNumXcd) * per + bid / kNumXcd;
-  if (lin >= nb) return false;
-  const int seg = (int)(lin % nseg);
-  const long long r = lin / nseg;
-  i2 = (int)(r % g.n2);
-  i3 = (int)(r / g.n2);
-  l0 = seg * kSeg;
-  return true;
-}
-
-__host__ __device__ inline unsigned tile_blocks(const Geo &g) {
-  const long long nseg = (g.n1 + kSeg - 1) / kSeg;
-  const long long nb = nseg * g.n2 * g.n3;
-  const long long per = (nb + kNumXcd - 1) / kNumXcd;
-  return (unsigned)(per * kNumXcd);
-}
-
-// Bout = Bin - curl+ E  (coefficients already carry the time step:
-// ax.c[l] = C_l c / dx1, h2 = c / dx2, h3 = c / dx3).
 template <typename Real, int DIM, int MM>
 __global__ __launch_bounds__(kSeg) void k_curl_e(Geo g, Fields<Real> f, const Real *Bin1, const Real *Bin2,
                                                  const Real *Bin3, Real *Bout1, Real *Bout2, Real *Bout3,
                                                  Axial<Real> ax, Real h2, Real h3) {
-  __shared__ Real sE2[kSeg + 2 * kMaxM], sE3[kSeg + 2 * kMaxM];
+  __shared__ Real sE2[stage_pitch<kSeg>()], sE3[stage_pitch<kSeg>()];
   int l0, i2, i3;
   if (!tile_of(g, (g.n1 + kSeg - 1) / kSeg, l0, i2, i3)) return;
-  const int M = MM > 0 ? MM : ax.M;
-  const long long row = (long long)g.n1 * (i2 + (long long)g.n2 * i3);
-  // stage E2, E3 on window cells [l0 - M + 1, l0 + kSeg + M)
-  const int span = kSeg + 2 * M;
-  for (int t = threadIdx.x; t < span; t += kSeg) {
-    const int col = col_of(g, l0 - M + 1 + t);
-    sE2[t] = ldc(f.E2, row, col);
-    sE3[t] = ldc(f.E3, row, col);
-  }
-  __syncthreads();
-  const int l1 = l0 + threadIdx.x;
-  if (l1 >= g.n1) return;
-  const int s1 = col_near(g, l1);
-  const long long id = row + s1;
-  const int c = threadIdx.x + M - 1;  // LDS index of cell l1
-  Real d1E2 = 0, d1E3 = 0;
-  auto term = [&](int l) {
-    d1E2 += ax.c[l - 1] * (sE2[c + l] - sE2[c - l + 1]);
-    d1E3 += ax.c[l - 1] * (sE3[c + l] - sE3[c - l + 1]);
-  };
-  if (MM > 0) {
-#pragma unroll
-    for (int l = 1; l <= MM; ++l) term(l);
-  } else {
-    for (int l = 1; l <= M; ++l) term(l);
-  }
-  const long long row2p = (long long)g.n1 * (wrap_near(i2 + 1, g.n2) + (long long)g.n2 * i3);
-  const Real E1 = f.E1[id], E2 = sE2[c], E3 = sE3[c];
-  const Real d2E3 = h2 * (f.E3[row2p + s1] - E3);
-  const Real d2E1 = h2 * (f.E1[row2p + s1] - E1);
-  Real d3E2 = 0, d3E1 = 0;
-  if (DIM == 3) {
-    const long long row3p = (long long)g.n1 * (i2 + (long long)g.n2 * wrap_near(i3 + 1, g.n3));
-    d3E2 = h3 * (f.E2[row3p + s1] - E2);
-    d3E1 = h3 * (f.E1[row3p + s1] - E1);
-  }
-  Bout1[id] = Bin1[id] - (d2E3 - d3E2);
-  Bout2[id] = Bin2[id] - (d3E1 - d1E3);
-  Bout3[id] = Bin3[id] - (d1E2 - d2E1);
+  curl_e_tile<Real, DIM, MM, kSeg, 1>(g, f.E1, f.E2, f.E3, Bin1, Bin2, Bin3, Bout1, Bout2, Bout3, ax, h2, h3, l0, i2, i3,
+                                   sE2, sE3);
 }
 
-// E += curl- B  (ax.c[l] = C_l dt / dx1; e2 = dt / dx2; e3 = dt / dx3).
 template <typename Real, int DIM, int MM>
 __global__ __launch_bounds__(kSeg) void k_curl_b(Geo g, Fields<Real> f, Axial<Real> ax, Real e2, Real e3) {
-  __shared__ Real sB2[kSeg + 2 * kMaxM], sB3[kSeg + 2 * kMaxM];
+  __shared__ Real sB2[stage_pitch<kSeg>()], sB3[stage_pitch<kSeg>()];
   int l0, i2, i3;
   if (!tile_of(g, (g.n1 + kSeg - 1) / kSeg, l0, i2, i3)) return;
-  const int M = MM > 0 ? MM : ax.M;
-  const long long row = (long long)g.n1 * (i2 + (long long)g.n2 * i3);
-  // stage B2, B3 on window cells [l0 - M, l0 + kSeg + M)
-  const int span = kSeg + 2 * M;
-  for (int t = threadIdx.x; t < span; t += kSeg) {
-    const int col = col_of(g, l0 - M + t);
-    sB2[t] = ldc(f.B2, row, col);
-    sB3[t] = ldc(f.B3, row, col);
-  }
-  __syncthreads();
-  const int l1 = l0 + threadIdx.x;
-  if (l1 >= g.n1) return;
-  const int s1 = col_near(g, l1);
-  const long long id = row + s1;
-  const int c = threadIdx.x + M;  // LDS index of cell l1
-  Real d1B3 = 0, d1B2 = 0;
-  auto term = [&](int l) {
-    d1B3 += ax.c[l - 1] * (sB3[c + l - 1] - sB3[c - l]);
-    d1B2 += ax.c[l - 1] * (sB2[c + l - 1] - sB2[c - l]);
-  };
-  if (MM > 0) {
-#pragma unroll
-    for (int l = 1; l <= MM; ++l) term(l);
-  } else {
-    for (int l = 1; l <= M; ++l) term(l);
-  }
-  const long long row2m = (long long)g.n1 * (wrap_near(i2 - 1, g.n2) + (long long)g.n2 * i3);
-  const Real B1 = f.B1[id], B2 = sB2[c], B3 = sB3[c];
-  const Real d2B3 = e2 * (B3 - f.B3[row2m + s1]);
-  const Real d2B1 = e2 * (B1 - f.B1[row2m + s1]);
-  Real d3B2 = 0, d3B1 = 0;
-  if (DIM == 3) {
-    const long long row3m = (long long)g.n1 * (i2 + (long long)g.n2 * wrap_near(i3 - 1, g.n3));
-    d3B2 = e3 * (B2 - f.B2[row3m + s1]);
-    d3B1 = e3 * (B1 - f.B1[row3m + s1]);
-  }
-  f.E1[id] += d2B3 - d3B2;
-  f.E2[id] += d3B1 - d1B3;
-  f.E3[id] += d1B2 - d2B1;
+  curl_b_tile<Real, DIM, MM, kSeg, 1>(g, f.E1, f.E2, f.E3, f.B1, f.B2, f.B3, ax, e2, e3, l0, i2, i3, sB2, sB3);
 }
 
 // E -= dt J over the box of deposited current (x1 widened by `pad` for the
@@ -155,32 +46,8 @@ __global__ __launch_bounds__(256) void k_add_j(Geo g, Fields<Real> f, const Real
       next->hi[d] = -0x7fffffff;
     }
   }
-  const JBox b = *box;
-  if (b.hi[0] < b.lo[0]) return;
-  int lo1 = b.lo[0] - pad, hi1 = b.hi[0] + pad;
-  if (g.window) {
-    lo1 = lo1 < 0 ? 0 : lo1;
-    hi1 = hi1 > g.n1 - 1 ? g.n1 - 1 : hi1;
-  } else if (hi1 - lo1 + 1 >= g.n1) {
-    lo1 = 0;
-    hi1 = g.n1 - 1;
-  }
-  const long long w1 = hi1 - lo1 + 1, w2 = b.hi[1] - b.lo[1] + 1, w3 = b.hi[2] - b.lo[2] + 1;
-  const long long tot = w1 * w2 * w3;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
-    const int a = (int)(t % w1);
-    const long long r = t / w1;
-    const int i2 = b.lo[1] + (int)(r % w2);
-    const int i3 = b.lo[2] + (int)(r / w2);
-    const int col = col_of(g, lo1 + a);
-    const long long id = (long long)g.n1 * (i2 + (long long)g.n2 * i3) + col;
-    f.E1[id] -= dt * J1src[id];
-    f.E2[id] -= dt * f.J2[id];
-    f.E3[id] -= dt * f.J3[id];
-    f.J1[id] = Real(0);
-    f.J2[id] = Real(0);
-    f.J3[id] = Real(0);
-  }
+  add_j_box(g, f.E1, f.E2, f.E3, f.J1, f.J2, f.J3, J1src, dt, *box, pad,
+            blockIdx.x * (long long)blockDim.x + threadIdx.x, (long long)gridDim.x * blockDim.x);
 }
 
 // J1c = G * J1 along x1 inside the current box (x1 widened by ng): FIR with
@@ -189,28 +56,8 @@ __global__ __launch_bounds__(256) void k_add_j(Geo g, Fields<Real> f, const Real
 template <typename Real>
 __global__ __launch_bounds__(256) void k_jcorr(Geo g, const Real *J1, Real *J1c, const Real *taps, int ng,
                                                const JBox *box) {
-  const JBox b = *box;
-  if (b.hi[0] < b.lo[0]) return;
-  int lo1 = b.lo[0] - ng, hi1 = b.hi[0] + ng;
-  if (g.window) {
-    lo1 = lo1 < 0 ? 0 : lo1;
-    hi1 = hi1 > g.n1 - 1 ? g.n1 - 1 : hi1;
-  } else if (hi1 - lo1 + 1 >= g.n1) {
-    lo1 = 0;
-    hi1 = g.n1 - 1;
-  }
-  const long long w1 = hi1 - lo1 + 1, w2 = b.hi[1] - b.lo[1] + 1, w3 = b.hi[2] - b.lo[2] + 1;
-  const long long tot = w1 * w2 * w3;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
-    const int l1 = lo1 + (int)(t % w1);
-    const long long r = t / w1;
-    const int i2 = b.lo[1] + (int)(r % w2);
-    const int i3 = b.lo[2] + (int)(r / w2);
-    const long long row = (long long)g.n1 * (i2 + (long long)g.n2 * i3);
-    Real acc = taps[0] * ldc(J1, row, col_of(g, l1));
-    for (int m = 1; m <= ng; ++m) acc += taps[m] * (ldc(J1, row, col_of(g, l1 - m)) + ldc(J1, row, col_of(g, l1 + m)));
-    J1c[row + col_of(g, l1)] = acc;
-  }
+  jcorr_box(g, J1, J1c, taps, ng, *box, blockIdx.x * (long long)blockDim.x + threadIdx.x,
+            (long long)gridDim.x * blockDim.x);
 }
 
 // Window shift after step n, with g the geometry before the shift.  The

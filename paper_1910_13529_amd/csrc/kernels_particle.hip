@@ -8,388 +8,19 @@
 //
 // Deposit.  Particles are kept sorted by cell, so the 64 lanes of a wavefront
 // mostly share one or two neighbouring cells of one (x2, x3) row.  Each
-// workgroup walks a contiguous chunk of particles and accumulates current in
-// an LDS tile that covers the chunk's cells; at the end it adds the non-zero
-// tile entries to J in HBM with one atomic each.  Inside a wavefront, lanes
-// whose stencils fit a common box of 5 x 4 (x 4) points first sum their
-// contributions with a recursive-halving reduce-scatter over the 64 lanes
-// (each lane ends up owning at most two box points), so a dense bunch costs
-// a few cross-lane moves per particle instead of ~60 conflicting atomics.
-// Lanes that do not fit the box add their stencil to the tile directly.
-#include <climits>
-
-#include "kernels.h"
+// workgroup walks a contiguous chunk of particles, stages E and B over the
+// chunk's cells in LDS for the gather, and accumulates current in an LDS tile
+// over the same cells; at the end it adds the non-zero tile entries to J in
+// HBM with one atomic each.  Inside a wavefront, lanes whose stencils share
+// the wavefront's boxes (exact supports when no transverse cell is crossed)
+// first sum their contributions with a recursive-halving reduce-scatter over
+// the 64 lanes (each lane ends up owning one point per component), so a dense
+// bunch costs a few cross-lane moves per particle instead of ~60 conflicting
+// atomics.  Other lanes add their stencil to the tile directly.  The device
+// code lives in particle_chunk.h, shared with the batched kernels.
+#include "particle_chunk.h"
 
 namespace relpic {
-
-constexpr int kPushBlock = 256;
-constexpr int kTileBytes = 49152;  // LDS tile per workgroup: J (3 components) + E, B (6)
-
-typedef __attribute__((address_space(3))) float lds_f32;
-typedef __attribute__((address_space(3))) double lds_f64;
-
-// atomic add to a workgroup-shared (LDS) address: ds_add_f32 / ds_add_f64
-__device__ __forceinline__ void lds_add(float *p, float v) {
-  __hip_atomic_fetch_add((lds_f32 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_add(double *p, double v) {
-  __hip_atomic_fetch_add((lds_f64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// load from a workgroup-shared (LDS) address
-__device__ __forceinline__ float lds_ld(const float *p) { return *(const lds_f32 *)p; }
-__device__ __forceinline__ double lds_ld(const double *p) { return *(const lds_f64 *)p; }
-
-
-// quadratic B-spline weights at nodes -1, 0, +1 for a particle at offset d
-// from node 0 (d in [-1/2, 1/2])
-template <typename Real>
-__device__ __forceinline__ void qw(Real d, Real w[3]) {
-  const Real a = Real(0.5) - d, b = Real(0.5) + d;
-  w[0] = Real(0.5) * a * a;
-  w[1] = Real(0.75) - d * d;
-  w[2] = Real(0.5) * b * b;
-}
-
-// Weights for a component at half-integer points j + 1/2: returns the index
-// j of the middle point and its weights.
-template <typename Real>
-__device__ __forceinline__ int qw_half(int c, Real o, Real w[3]) {
-  if (o >= Real(0)) {
-    qw(o - Real(0.5), w);
-    return c;
-  }
-  qw(o + Real(0.5), w);
-  return c - 1;
-}
-
-// Gather stencils of one particle: element offsets of the x1 columns and of
-// the x2 (n1 * i2) and x3 (n1 * n2 * i3) rows, for node (N) and half-integer
-// (H) points, and the weights.  Offsets are 32-bit (the library keeps every
-// field array below 4 GiB) so loads take a scalar base plus one vector
-// offset; x1 points outside the moving window carry weight 0 and a valid
-// dummy column.
-template <typename Real>
-struct Stagger {
-  unsigned colN[3], colH[3];
-  unsigned rowN2[3], rowH2[3], rowN3[3], rowH3[3];
-  Real wN[3][3], wH[3][3];
-};
-
-// Load element `id` through a 32-bit byte offset from the array base.
-template <typename Real>
-__device__ __forceinline__ Real ld32(const Real *__restrict__ f, unsigned id) {
-  return *reinterpret_cast<const Real *>(reinterpret_cast<const char *>(f) + (unsigned)(id * (unsigned)sizeof(Real)));
-}
-
-template <typename Real, int DIM, bool H1, bool H2, bool H3, bool AVG>
-__device__ __forceinline__ Real interp(const Stagger<Real> &s, const Real *__restrict__ f,
-                                       const Real *__restrict__ f2) {
-  const unsigned *cols = H1 ? s.colH : s.colN;
-  const unsigned *r2 = H2 ? s.rowH2 : s.rowN2;
-  Real acc = 0;
-  if (DIM == 2) {
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      Real r = 0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const unsigned id = r2[b] + cols[a];
-        const Real v = AVG ? ld32(f, id) + ld32(f2, id) : ld32(f, id);
-        r += (H1 ? s.wH[0][a] : s.wN[0][a]) * v;
-      }
-      acc += (H2 ? s.wH[1][b] : s.wN[1][b]) * r;
-    }
-  } else {
-    const unsigned *r3 = H3 ? s.rowH3 : s.rowN3;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      Real rc = 0;
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        Real r = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const unsigned id = r2[b] + r3[c] + cols[a];
-          const Real v = AVG ? ld32(f, id) + ld32(f2, id) : ld32(f, id);
-          r += (H1 ? s.wH[0][a] : s.wN[0][a]) * v;
-        }
-        rc += (H2 ? s.wH[1][b] : s.wN[1][b]) * r;
-      }
-      acc += (H3 ? s.wH[2][c] : s.wN[2][c]) * rc;
-    }
-  }
-  return AVG ? Real(0.5) * acc : acc;
-}
-
-// Gather from the workgroup's LDS copy of E and B (B already averaged to
-// integer time): tile offsets of the x1 cells c-2 .. c+1 and of the x2/x3
-// rows c-2 .. c+1 (scaled by the tile strides).
-struct StaggerL {
-  int x1[4], x2[4], x3[4];
-  bool h1lo, h2lo, h3lo;
-};
-
-template <typename Real, int DIM, bool H1, bool H2, bool H3>
-__device__ __forceinline__ Real interp_lds(const StaggerL &s, const Real wN[3][3], const Real wH[3][3],
-                                           const Real *ft) {
-  Real acc = 0;
-#pragma unroll
-  for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) {
-    const int z = DIM == 3 ? ((H3 && s.h3lo) ? s.x3[c] : s.x3[c + 1]) : 0;
-    Real rc = 0;
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int y = (H2 && s.h2lo) ? s.x2[b] : s.x2[b + 1];
-      Real r = 0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int x = (H1 && s.h1lo) ? s.x1[a] : s.x1[a + 1];
-        r += (H1 ? wH[0][a] : wN[0][a]) * lds_ld(ft + x + y + z);
-      }
-      rc += (H2 ? wH[1][b] : wN[1][b]) * r;
-    }
-    acc += DIM == 3 ? (H3 ? wH[2][c] : wN[2][c]) * rc : rc;
-  }
-  return acc;
-}
-
-// Esirkepov shape arrays on four nodes starting at old cell + base:
-// S0 at x^n, DS = S(x^{n+1}) - S(x^n); cum = running sum of DS.
-template <typename Real>
-__device__ __forceinline__ int esirkepov_1d(Real o0, int sh, Real o1, Real S0[4], Real DS[4], Real cum[4]) {
-  Real w0[3], w1[3];
-  qw(o0, w0);
-  qw(o1, w1);
-  const int base = sh < 0 ? -2 : -1;
-  Real run = 0;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int k = base + a;  // node relative to the old cell
-    const int k1 = k - sh;   // node relative to the new cell
-    const Real s0 = (k >= -1 && k <= 1) ? w0[k + 1] : Real(0);
-    const Real s1 = (k1 >= -1 && k1 <= 1) ? w1[k1 + 1] : Real(0);
-    S0[a] = s0;
-    DS[a] = s1 - s0;
-    run += DS[a];
-    cum[a] = run;
-  }
-  return base;
-}
-
-// Where deposits go: the workgroup's LDS tile if it covers the point, else
-// J in HBM.  Coordinates are the window x1 index and unwrapped x2, x3.
-template <typename Real>
-struct Sink {
-  Real *tile;        // 3 components x T1 x T2 x T3, or null
-  int t1, t2, t3;    // tile origin
-  int T1, T2, T3;    // tile extents
-  int tn;            // T1 * T2 * T3
-  Real *J[3];
-  Geo g;
-
-  __device__ __forceinline__ void add(int comp, int x1, int x2, int x3, Real v) const {
-    if (v == Real(0)) return;
-    if (tile) {
-      const int a = x1 - t1, b = x2 - t2, c = x3 - t3;
-      if (a >= 0 && a < T1 && b >= 0 && b < T2 && c >= 0 && c < T3) {
-        lds_add(tile + comp * tn + a + T1 * (b + T2 * c), v);
-        return;
-      }
-    }
-    const int col = col_near(g, x1);
-    if (col < 0) return;
-    const long long row = (long long)g.n1 * (wrap_near(x2, g.n2) + (long long)g.n2 * wrap_near(x3, g.n3));
-    atomicAdd(J[comp] + row + col, v);
-  }
-};
-
-// One level of the reduce-scatter: v[0..S) is summed with the partner lane
-// (lane ^ bit); lanes with the bit set keep the upper half.
-template <typename Real, int S>
-__device__ __forceinline__ void rs_level(Real *v, int lane, int bit, int &off) {
-  constexpr int H = (S + 1) / 2;
-  const bool up = (lane & bit) != 0;
-#pragma unroll
-  for (int j = 0; j < H; ++j) {
-    const Real lo = v[j];
-    const Real hi = (j + H < S) ? v[j + H] : Real(0);
-    const Real send = up ? lo : hi;
-    const Real keep = up ? hi : lo;
-    v[j] = keep + __shfl_xor(send, bit, 64);
-  }
-  if (up) off += H;
-}
-
-// Sum v[0..S) over the 64 lanes of the wavefront (S <= 64); afterwards each
-// lane holds in v[0] the total for index `off` (padding when off >= S).
-template <typename Real, int S, int BIT>
-__device__ __forceinline__ void reduce_scatter(Real *v, int lane, int &off) {
-  if constexpr (BIT >= 1) {
-    rs_level<Real, S>(v, lane, BIT, off);
-    reduce_scatter<Real, (S + 1) / 2, BIT / 2>(v, lane, off);
-  }
-}
-
-// Reduce an N1 x N2 x N3 box of per-lane values over the wavefront and add
-// the totals (one per lane) to the sink at box origin (x1, x2, x3).
-template <typename Real, int N1, int N2, int N3, typename F>
-__device__ __forceinline__ void box_reduce_add(const Sink<Real> &sk, int comp, int lane, bool fits, int x1, int x2,
-                                               int x3, F val) {
-  constexpr int S = N1 * N2 * N3;
-  static_assert(S <= 64, "box larger than a wavefront");
-  Real v[S];
-#pragma unroll
-  for (int k = 0; k < S; ++k) v[k] = fits ? val(k % N1, (k / N1) % N2, k / (N1 * N2)) : Real(0);
-  int off = 0;
-  reduce_scatter<Real, S, 32>(v, lane, off);
-  if (off < S) sk.add(comp, x1 + off % N1, x2 + (off / N1) % N2, x3 + off / (N1 * N2), v[0]);
-}
-
-// Everything the deposit needs from one pushed particle.
-template <typename Real>
-struct Moved {
-  int c[3];          // old cell (window x1, x2, x3)
-  int base[3];       // first stencil node relative to the old cell (-2 or -1)
-  Real S0[3][4], DS[3][4], cum[3][4];
-  Real jz;           // Q v3 / dV (2D out-of-plane current)
-};
-
-template <typename Real>
-__device__ __forceinline__ Real wperp(const Real *S0a, const Real *DSa, const Real *S0b, const Real *DSb, int a,
-                                      int b) {
-  return S0a[a] * S0b[b] + Real(0.5) * DSa[a] * S0b[b] + Real(0.5) * S0a[a] * DSb[b] +
-         DSa[a] * DSb[b] * Real(1.0 / 3.0);
-}
-
-// Direct Esirkepov deposit of one particle into the sink.
-template <typename Real, int DIM>
-__device__ __forceinline__ void deposit_direct(const Moved<Real> &m, const PushParams<Real> &q, const Sink<Real> &sk) {
-  const int x1 = m.c[0] + m.base[0], x2 = m.c[1] + m.base[1];
-  if (DIM == 2) {
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) {
-      const Real wt = q.f1 * (m.S0[1][bb] + Real(0.5) * m.DS[1][bb]);
-#pragma unroll
-      for (int aa = 0; aa < 3; ++aa) sk.add(0, x1 + aa, x2 + bb, 0, wt * m.cum[0][aa]);
-    }
-#pragma unroll
-    for (int aa = 0; aa < 4; ++aa) {
-      const Real wt = q.f2 * (m.S0[0][aa] + Real(0.5) * m.DS[0][aa]);
-#pragma unroll
-      for (int bb = 0; bb < 3; ++bb) sk.add(1, x1 + aa, x2 + bb, 0, wt * m.cum[1][bb]);
-    }
-#pragma unroll
-    for (int aa = 0; aa < 4; ++aa)
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb)
-        sk.add(2, x1 + aa, x2 + bb, 0, m.jz * wperp(m.S0[0], m.DS[0], m.S0[1], m.DS[1], aa, bb));
-  } else {
-    const int x3 = m.c[2] + m.base[2];
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc)
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const Real wt = q.f1 * wperp(m.S0[1], m.DS[1], m.S0[2], m.DS[2], bb, cc);
-        if (wt == Real(0)) continue;
-#pragma unroll
-        for (int aa = 0; aa < 3; ++aa) sk.add(0, x1 + aa, x2 + bb, x3 + cc, wt * m.cum[0][aa]);
-      }
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc)
-#pragma unroll
-      for (int aa = 0; aa < 4; ++aa) {
-        const Real wt = q.f2 * wperp(m.S0[0], m.DS[0], m.S0[2], m.DS[2], aa, cc);
-        if (wt == Real(0)) continue;
-#pragma unroll
-        for (int bb = 0; bb < 3; ++bb) sk.add(1, x1 + aa, x2 + bb, x3 + cc, wt * m.cum[1][bb]);
-      }
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb)
-#pragma unroll
-      for (int aa = 0; aa < 4; ++aa) {
-        const Real wt = q.f3 * wperp(m.S0[0], m.DS[0], m.S0[1], m.DS[1], aa, bb);
-        if (wt == Real(0)) continue;
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) sk.add(2, x1 + aa, x2 + bb, x3 + cc, wt * m.cum[2][cc]);
-      }
-  }
-}
-
-// Shift a 4-point stencil array into the 5-point box frame: out[b] = in[b - o].
-template <typename Real>
-__device__ __forceinline__ Real ext5(const Real *in, int o, int b) {
-  const Real a = (b <= 3) ? in[b] : Real(0);
-  const Real c = (b >= 1) ? in[b - 1] : Real(0);
-  return o ? c : a;
-}
-
-// Wavefront-collective deposit (every lane of the wave must call it).
-// A lane joins the reduction when it lies in the wave's (x2, x3) row, does not
-// cross a transverse cell boundary this step, and its x1 stencil starts at
-// most one node after the wave's leftmost one.  Its exact supports are then
-// J1: 4 x 3 x 3 half/node points, J2: 5 x 2 x 3, J3: 5 x 3 x 2 (2D: 4 x 3,
-// 5 x 2, 5 x 3), all inside boxes that every such lane shares.
-template <typename Real, int DIM>
-__device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, const PushParams<Real> &q,
-                                             const Sink<Real> &sk) {
-  const int lane = threadIdx.x & 63;
-  const unsigned long long act = __ballot(active);
-  if (act == 0ULL) return;
-  const int first = __ffsll((long long)act) - 1;
-  const int c2w = __shfl(m.c[1], first, 64);
-  const int c3w = __shfl(m.c[2], first, 64);
-  const bool inrow = active && m.c[1] == c2w && (DIM == 2 || m.c[2] == c3w);
-  int cmin = inrow ? m.c[0] : INT_MAX;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) cmin = min(cmin, __shfl_xor(cmin, o, 64));
-  const int o1 = m.c[0] + m.base[0] - (cmin - 1);
-  // no transverse crossing: base -1 and no DS on the fourth node
-  const bool flat2 = m.base[1] == -1 && m.DS[1][3] == Real(0);
-  const bool flat3 = DIM == 2 || (m.base[2] == -1 && m.DS[2][3] == Real(0));
-  const bool fits = inrow && (o1 == 0 || o1 == 1) && flat2 && flat3;
-  const unsigned long long fm = __ballot(fits);
-  if (__popcll(fm) >= 4) {
-    const int oo = fits ? o1 : 0;
-    Real e1S0[5], e1DS[5];
-#pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      e1S0[b] = ext5(m.S0[0], oo, b);
-      e1DS[b] = ext5(m.DS[0], oo, b);
-    }
-    // J1 at x1 half points: running sum of DS1 (three entries) shifted by oo
-    auto cum1 = [&](int b) -> Real {
-      const Real lo = (b <= 2) ? m.cum[0][b] : Real(0);
-      const Real hi = (b >= 1 && b <= 3) ? m.cum[0][b - 1] : Real(0);
-      return oo ? hi : lo;
-    };
-    const int x1 = cmin - 1, x2 = c2w - 1, x3 = DIM == 3 ? c3w - 1 : 0;
-    if (DIM == 3) {
-      box_reduce_add<Real, 4, 3, 3>(sk, 0, lane, fits, x1, x2, x3, [&](int b, int a2, int a3) {
-        return q.f1 * cum1(b) * wperp(m.S0[1], m.DS[1], m.S0[2], m.DS[2], a2, a3);
-      });
-      box_reduce_add<Real, 5, 2, 3>(sk, 1, lane, fits, x1, x2, x3, [&](int b, int a2, int a3) {
-        return q.f2 * m.cum[1][a2] * wperp(e1S0, e1DS, m.S0[2], m.DS[2], b, a3);
-      });
-      box_reduce_add<Real, 5, 3, 2>(sk, 2, lane, fits, x1, x2, x3, [&](int b, int a2, int a3) {
-        return q.f3 * m.cum[2][a3] * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2);
-      });
-    } else {
-      box_reduce_add<Real, 4, 3, 1>(sk, 0, lane, fits, x1, x2, 0, [&](int b, int a2, int) {
-        return q.f1 * cum1(b) * (m.S0[1][a2] + Real(0.5) * m.DS[1][a2]);
-      });
-      box_reduce_add<Real, 5, 2, 1>(sk, 1, lane, fits, x1, x2, 0, [&](int b, int a2, int) {
-        return q.f2 * m.cum[1][a2] * (e1S0[b] + Real(0.5) * e1DS[b]);
-      });
-      box_reduce_add<Real, 5, 3, 1>(sk, 2, lane, fits, x1, x2, 0, [&](int b, int a2, int) {
-        return m.jz * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2);
-      });
-    }
-    if (active && !fits) deposit_direct<Real, DIM>(m, q, sk);
-  } else if (active) {
-    deposit_direct<Real, DIM>(m, q, sk);
-  }
-}
 
 template <typename Real, int DIM>
 __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real> f, HalfB<Real> Bh,
@@ -397,316 +28,7 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
                                                              JBox *blockbox, int *err) {
   __shared__ __align__(16) unsigned char tile_raw[kTileBytes];
   __shared__ int box[6];
-  Real *tile = reinterpret_cast<Real *>(tile_raw);
-  const long long chunk0 = (long long)blockIdx.x * kPushBlock * K;
-  const int tid = threadIdx.x;
-
-  // ---- chunk bounding box (window x1, x2, x3) of the particles' old cells
-  if (tid == 0) {
-    box[0] = box[2] = box[4] = INT_MAX;
-    box[1] = box[3] = box[5] = INT_MIN;
-  }
-  __syncthreads();
-  {
-    int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
-    for (int k = 0; k < K; ++k) {
-      const long long i = chunk0 + (long long)k * kPushBlock + tid;
-      if (i >= p.n) break;
-      const int packed = p.cell[i];
-      if (packed < 0) continue;
-      const int s1 = packed % g.n1, rest = packed / g.n1;
-      int c1 = s1 - g.ws_mod;
-      if (c1 < 0) c1 += g.n1;
-      const int cc[3] = {c1, rest % g.n2, DIM == 3 ? rest / g.n2 : 0};
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        mn[d] = min(mn[d], cc[d]);
-        mx[d] = max(mx[d], cc[d]);
-      }
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        mn[d] = min(mn[d], __shfl_xor(mn[d], o, 64));
-        mx[d] = max(mx[d], __shfl_xor(mx[d], o, 64));
-      }
-    }
-    if ((tid & 63) == 0 && mn[0] != INT_MAX) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        atomicMin(&box[2 * d], mn[d]);
-        atomicMax(&box[2 * d + 1], mx[d]);
-      }
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    // deposits of this chunk land within its old cells +- 2; empty chunks
-    // write an empty box
-    int lo[3] = {box[0] - 2, box[2] - 2, DIM == 3 ? box[4] - 2 : 0};
-    int hi[3] = {box[1] + 2, box[3] + 2, DIM == 3 ? box[5] + 2 : 0};
-    const int nn[3] = {g.n1, g.n2, g.n3};
-    if (box[0] == INT_MAX) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = INT_MAX;
-        hi[d] = -INT_MAX;
-      }
-    } else {
-      if (g.window) {
-        lo[0] = max(lo[0], 0);
-        hi[0] = min(hi[0], g.n1 - 1);
-      }
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (lo[d] < 0 || hi[d] >= nn[d]) {
-          lo[d] = 0;
-          hi[d] = nn[d] - 1;
-        }
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      blockbox[blockIdx.x].lo[d] = lo[d];
-      blockbox[blockIdx.x].hi[d] = hi[d];
-    }
-  }
-  Sink<Real> sk;
-  sk.g = g;
-  sk.J[0] = f.J1;
-  sk.J[1] = f.J2;
-  sk.J[2] = f.J3;
-  sk.tile = nullptr;
-  sk.t1 = box[0] - 2;
-  sk.t2 = box[2] - 2;
-  sk.t3 = DIM == 3 ? box[4] - 2 : 0;
-  sk.T1 = sk.T2 = sk.T3 = 1;
-  sk.tn = 0;
-  if (box[0] != INT_MAX) {
-    const long long T1 = (long long)box[1] - box[0] + 5, T2 = (long long)box[3] - box[2] + 5;
-    const long long T3 = DIM == 3 ? (long long)box[5] - box[4] + 5 : 1;
-    if (9 * T1 * T2 * T3 * (long long)sizeof(Real) <= kTileBytes) {
-      sk.T1 = (int)T1;
-      sk.T2 = (int)T2;
-      sk.T3 = (int)T3;
-      sk.tn = (int)(T1 * T2 * T3);
-      sk.tile = tile;
-      // J part cleared; E and B^n staged for the gather (zero outside the window)
-      const int tn = sk.tn;
-      for (int t = tid; t < 9 * tn; t += kPushBlock) {
-        const int comp = t / tn;
-        Real v = Real(0);
-        if (comp >= 3) {
-          int r = t - comp * tn;
-          const int a = r % sk.T1;
-          r /= sk.T1;
-          const int b = r % sk.T2;
-          const int c = r / sk.T2;
-          const int col = col_of(g, sk.t1 + a);
-          if (col >= 0) {
-            const long long id = (long long)g.n1 * (wrap(sk.t2 + b, g.n2) + (long long)g.n2 * wrap(sk.t3 + c, g.n3)) + col;
-            switch (comp) {
-              case 3: v = f.E1[id]; break;
-              case 4: v = f.E2[id]; break;
-              case 5: v = f.E3[id]; break;
-              case 6: v = Real(0.5) * (f.B1[id] + Bh.B1[id]); break;
-              case 7: v = Real(0.5) * (f.B2[id] + Bh.B2[id]); break;
-              default: v = Real(0.5) * (f.B3[id] + Bh.B3[id]); break;
-            }
-          }
-        }
-        tile[t] = v;
-      }
-    }
-  }
-  __syncthreads();
-  const bool lds_fields = sk.tile != nullptr;
-
-  // ---- gather, push, move and deposit, K particles per thread
-  for (int k = 0; k < K; ++k) {
-    const long long i = chunk0 + (long long)k * kPushBlock + tid;
-    const int packed = (i < p.n) ? p.cell[i] : -1;
-    const bool active = packed >= 0;
-    Moved<Real> m;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      m.c[d] = 0;
-      m.base[d] = -1;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) m.S0[d][a] = m.DS[d][a] = m.cum[d][a] = Real(0);
-    }
-    m.jz = 0;
-    if (active) {
-      const int s1 = packed % g.n1;
-      const int rest = packed / g.n1;
-      const int c2 = rest % g.n2;
-      const int c3 = DIM == 3 ? rest / g.n2 : 0;
-      int c1 = s1 - g.ws_mod;
-      if (c1 < 0) c1 += g.n1;
-      m.c[0] = c1;
-      m.c[1] = c2;
-      m.c[2] = c3;
-      const Real o[3] = {p.o1[i], p.o2[i], DIM == 3 ? p.o3[i] : Real(0)};
-
-      Real E1, E2, E3, B1, B2, B3;
-      Stagger<Real> st;
-      int bH[3];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        qw(o[d], st.wN[d]);
-        bH[d] = qw_half(m.c[d], o[d], st.wH[d]);
-      }
-      if (lds_fields) {
-        StaggerL sl;
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) {
-          sl.x1[k2] = c1 - 2 + k2 - sk.t1;
-          sl.x2[k2] = sk.T1 * (c2 - 2 + k2 - sk.t2);
-          sl.x3[k2] = sk.T1 * sk.T2 * (c3 - 2 + k2 - sk.t3);
-        }
-        sl.h1lo = bH[0] < c1;
-        sl.h2lo = bH[1] < c2;
-        sl.h3lo = DIM == 3 && bH[2] < c3;
-        const Real *ft = tile + 3 * sk.tn;
-        E1 = interp_lds<Real, DIM, true, false, false>(sl, st.wN, st.wH, ft);
-        E2 = interp_lds<Real, DIM, false, true, false>(sl, st.wN, st.wH, ft + sk.tn);
-        E3 = interp_lds<Real, DIM, false, false, true>(sl, st.wN, st.wH, ft + 2 * sk.tn);
-        B1 = interp_lds<Real, DIM, false, true, true>(sl, st.wN, st.wH, ft + 3 * sk.tn);
-        B2 = interp_lds<Real, DIM, true, false, true>(sl, st.wN, st.wH, ft + 4 * sk.tn);
-        B3 = interp_lds<Real, DIM, true, true, false>(sl, st.wN, st.wH, ft + 5 * sk.tn);
-      } else {
-      {
-        // window cells c-2 .. c+1 cover both stencils (half: bH-1 .. bH+1, bH in {c-1, c})
-        int cx[4];
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) cx[k2] = col_near(g, c1 - 2 + k2);
-        const bool hlo = bH[0] < c1;
-#pragma unroll
-        for (int a2 = 0; a2 < 3; ++a2) {
-          const int cn = cx[a2 + 1], ch = hlo ? cx[a2] : cx[a2 + 1];
-          st.colN[a2] = cn < 0 ? 0u : (unsigned)cn;
-          st.colH[a2] = ch < 0 ? 0u : (unsigned)ch;
-          if (cn < 0) st.wN[0][a2] = Real(0);
-          if (ch < 0) st.wH[0][a2] = Real(0);
-        }
-        unsigned r2x[4];
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) r2x[k2] = (unsigned)g.n1 * (unsigned)wrap_near(c2 - 2 + k2, g.n2);
-        const bool h2lo = bH[1] < c2;
-#pragma unroll
-        for (int a2 = 0; a2 < 3; ++a2) {
-          st.rowN2[a2] = r2x[a2 + 1];
-          st.rowH2[a2] = h2lo ? r2x[a2] : r2x[a2 + 1];
-        }
-        if (DIM == 3) {
-          unsigned r3x[4];
-#pragma unroll
-          for (int k2 = 0; k2 < 4; ++k2)
-            r3x[k2] = (unsigned)g.n1 * (unsigned)g.n2 * (unsigned)wrap_near(c3 - 2 + k2, g.n3);
-          const bool h3lo = bH[2] < c3;
-#pragma unroll
-          for (int a2 = 0; a2 < 3; ++a2) {
-            st.rowN3[a2] = r3x[a2 + 1];
-            st.rowH3[a2] = h3lo ? r3x[a2] : r3x[a2 + 1];
-          }
-        }
-      }
-      E1 = interp<Real, DIM, true, false, false, false>(st, f.E1, nullptr);
-      E2 = interp<Real, DIM, false, true, false, false>(st, f.E2, nullptr);
-      E3 = interp<Real, DIM, false, false, true, false>(st, f.E3, nullptr);
-      B1 = interp<Real, DIM, false, true, true, true>(st, f.B1, Bh.B1);
-      B2 = interp<Real, DIM, true, false, true, true>(st, f.B2, Bh.B2);
-      B3 = interp<Real, DIM, true, true, false, true>(st, f.B3, Bh.B3);
-
-      }
-
-      // relativistic Boris push
-      const Real a = q.half_qmdt;
-      const Real um1 = p.u1[i] + a * E1, um2 = p.u2[i] + a * E2, um3 = p.u3[i] + a * E3;
-      const Real gm = sqrt(Real(1) + um1 * um1 + um2 * um2 + um3 * um3);
-      const Real t1 = a * B1 / gm, t2 = a * B2 / gm, t3 = a * B3 / gm;
-      const Real t2s = t1 * t1 + t2 * t2 + t3 * t3;
-      const Real f2 = Real(2) / (Real(1) + t2s);
-      const Real s1v = f2 * t1, s2v = f2 * t2, s3v = f2 * t3;
-      const Real up1 = um1 + (um2 * t3 - um3 * t2);
-      const Real up2 = um2 + (um3 * t1 - um1 * t3);
-      const Real up3 = um3 + (um1 * t2 - um2 * t1);
-      const Real un1 = um1 + (up2 * s3v - up3 * s2v) + a * E1;
-      const Real un2 = um2 + (up3 * s1v - up1 * s3v) + a * E2;
-      const Real un3 = um3 + (up1 * s2v - up2 * s1v) + a * E3;
-      const Real gn = sqrt(Real(1) + un1 * un1 + un2 * un2 + un3 * un3);
-      const Real ig = Real(1) / gn;
-      if (!(un1 == un1) || !(un2 == un2) || !(un3 == un3)) atomicOr(err, 2);
-
-      // x^{n+1} = x^n + dt u / gamma, in cell units, as cell + offset
-      const Real un[3] = {un1, un2, un3};
-      int sh[3] = {0, 0, 0};
-      Real on[3] = {o[0], o[1], o[2]};
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const Real dlt = q.dtdx[d] * un[d] * ig;
-        if (!(dlt < Real(1) && dlt > Real(-1))) atomicOr(err, 1);
-        const Real v = o[d] + dlt;
-        int kk = 0;
-        if (v >= Real(0.5))
-          kk = 1;
-        else if (v < Real(-0.5))
-          kk = -1;
-        sh[d] = kk;
-        on[d] = v - Real(kk);
-      }
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) m.base[d] = esirkepov_1d(o[d], sh[d], on[d], m.S0[d], m.DS[d], m.cum[d]);
-      if (DIM == 2) {
-        // the out-of-plane direction carries the time-averaged shape weight
-        m.jz = q.fv * un3 * ig;
-      }
-
-      // store the new state
-      const int n1c = c1 + sh[0];
-      bool alive = true;
-      if (g.window) {
-        const int after = n1c - q.shift;  // window cell after this step's shift
-        if (after < 2 || after > g.n1 - 3) alive = false;
-      }
-      if (!alive) {
-        p.cell[i] = -1;
-      } else {
-        const int ns1 = col_of(g, n1c);
-        const int ns2 = wrap(c2 + sh[1], g.n2);
-        const int ns3 = DIM == 3 ? wrap(c3 + sh[2], g.n3) : 0;
-        p.cell[i] = ns1 + g.n1 * (ns2 + g.n2 * ns3);
-        p.o1[i] = on[0];
-        p.o2[i] = on[1];
-        if (DIM == 3) p.o3[i] = on[2];
-        p.u1[i] = un1;
-        p.u2[i] = un2;
-        p.u3[i] = un3;
-      }
-    }
-    deposit_wave<Real, DIM>(active, m, q, sk);
-  }
-
-  // ---- flush the tile to HBM: one atomic per non-zero point
-  if (sk.tile) {
-    __syncthreads();
-    for (int t = tid; t < 3 * sk.tn; t += kPushBlock) {
-      const Real v = tile[t];
-      if (v == Real(0)) continue;
-      const int comp = t / sk.tn;
-      int r = t - comp * sk.tn;
-      const int a = r % sk.T1;
-      r /= sk.T1;
-      const int b = r % sk.T2;
-      const int c = r / sk.T2;
-      const int col = col_near(g, sk.t1 + a);
-      if (col < 0) continue;
-      const long long row =
-          (long long)g.n1 * (wrap_near(sk.t2 + b, g.n2) + (long long)g.n2 * wrap_near(sk.t3 + c, g.n3));
-      Real *Jc = comp == 0 ? sk.J[0] : (comp == 1 ? sk.J[1] : sk.J[2]);
-      atomicAdd(Jc + row + col, v);
-    }
-  }
+  push_chunk<Real, DIM>(g, f, Bh, p, q, K, blockIdx.x, blockbox + blockIdx.x, err, tile_raw, box);
 }
 
 // Box of a set of per-workgroup boxes merged into *out (one workgroup).
@@ -740,15 +62,19 @@ long long push_blocks(long long n, int K) {
 
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
-                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *blockbox, JBox *jbox,
-                         int *err, hipStream_t st) {
+                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *blockbox, int *err,
+                         hipStream_t st) {
   if (p.n <= 0) return;
   const unsigned blocks = (unsigned)push_blocks(p.n, K);
   if (ndim == 3)
     k_push_deposit<Real, 3><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
   else
     k_push_deposit<Real, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
-  k_merge_boxes<<<1, 256, 0, st>>>(blockbox, (int)blocks, jbox);
+}
+
+void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStream_t st) {
+  if (nbox <= 0) return;
+  k_merge_boxes<<<1, 256, 0, st>>>(blockbox, (int)nbox, jbox);
 }
 
 // ---- particle sort (cell order) ---------------------------------------------------
@@ -808,8 +134,8 @@ void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, cons
 
 #define RELPIC_INST_PART(Real)                                                                                   \
   template void launch_push_deposit<Real>(int, const Geo &, const Fields<Real> &, const HalfB<Real> &,          \
-                                          const Particles<Real> &, const PushParams<Real> &, int, JBox *, JBox *, \
-                                          int *, hipStream_t);                                                   \
+                                          const Particles<Real> &, const PushParams<Real> &, int, JBox *, int *,  \
+                                          hipStream_t);                                                          \
   template void launch_sort_keys<Real>(const Particles<Real> &, unsigned *, unsigned *, hipStream_t);           \
   template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \
                                      const unsigned *, int, unsigned long long *, hipStream_t);

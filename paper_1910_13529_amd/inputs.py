@@ -130,3 +130,31 @@ def beam_charge(w):
     e = w.extra
     vol = (2.0 * math.pi) ** 1.5 * e["sigma_phys"][0] * e["sigma_phys"][1] * e["sigma_phys"][2]
     return -e["n_peak"] * vol / e["npart"]
+
+
+def batch_draws(nruns=256, seed=4, solver="mixed", spare=8, n1_range=(128, 1024), n2_range=(64, 256)):
+    """Per-run draws of the batched workload: n1 ~ U{128..1024}, n2 ~ U{64..256}
+    (other inclusive ranges for smaller test cases),
+    gamma log-uniform on [10, 1e5], `spare` candidates of dt/dx1 ~ U[0.3, 0.99]
+    (a run takes the first one its stability rule accepts), the solver kind
+    ("yee" or "custom"; "mixed" draws it per run) and the seed of its bunch."""
+    rng = np.random.default_rng(seed)
+    runs = []
+    for r in range(nruns):
+        n1 = int(rng.integers(n1_range[0], n1_range[1] + 1))
+        n2 = int(rng.integers(n2_range[0], n2_range[1] + 1))
+        gamma = float(10.0 ** rng.uniform(1.0, 5.0))
+        ratios = rng.uniform(0.3, 0.99, size=spare)
+        flip = rng.random()
+        kind = solver if solver in ("yee", "custom") else ("yee" if flip < 0.5 else "custom")
+        runs.append({"n1": n1, "n2": n2, "gamma": gamma, "ratios": ratios, "kind": kind,
+                     "seed": seed * 1000003 + r})
+    return runs
+
+
+def batch_bunch(run, npart=4096, sigma_cells=(5.0, 1.0)):
+    """Gaussian bunch of one batched run in cell units: centred at 3/4 of n1
+    on the middle x2 node, sigma 5 cells along x1 and 1 cell along x2,
+    u1 = sqrt(gamma^2 - 1), no transverse momentum."""
+    center = (0.75 * run["n1"], run["n2"] // 2)
+    return gaussian_bunch(run["seed"], npart, center, sigma_cells, run["gamma"], ndim=2, clip_sigmas=4.0)

@@ -25,9 +25,12 @@ EXPORTS = (
     "relpic_set_injection", "relpic_set_background_rho", "relpic_step", "relpic_sync", "relpic_read_field",
     "relpic_write_field", "relpic_field_device_ptr", "relpic_read_particles", "relpic_diagnostics",
     "relpic_get_step", "relpic_correction_halfwidth", "relpic_profile_enable", "relpic_profile_read",
-    "relpic_sort_particles", "relpic_set_sort_interval", "relpic_last_error",
+    "relpic_sort_particles", "relpic_set_sort_interval", "relpic_batch_create", "relpic_batch_destroy",
+    "relpic_batch_run", "relpic_batch_step", "relpic_batch_sync", "relpic_batch_set_graph_steps",
+    "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
+    "relpic_last_error",
 )
-KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j")
+KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes")
 
 
 class RelpicError(RuntimeError):
@@ -65,7 +68,18 @@ class Diag(ctypes.Structure):
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 6), ("total_ms", ctypes.c_double * 6)]
+    _fields_ = [("launches", ctypes.c_int64 * 7), ("total_ms", ctypes.c_double * 7)]
+
+
+class BatchTune(ctypes.Structure):
+    _fields_ = [("ms_uniform", ctypes.c_double * 3), ("ms_model", ctypes.c_double),
+                ("ms_persistent", ctypes.c_double * 2), ("ms_chosen", ctypes.c_double), ("choice", ctypes.c_int),
+                ("grid_workgroups", ctypes.c_int), ("runs_per_shape", ctypes.c_int * 3)]
+
+    def as_dict(self):
+        return {"ms_uniform": list(self.ms_uniform), "ms_model": self.ms_model,
+                "ms_persistent": list(self.ms_persistent), "ms_chosen": self.ms_chosen, "choice": self.choice,
+                "grid_workgroups": self.grid_workgroups, "runs_per_shape": list(self.runs_per_shape)}
 
 
 _lib = None
@@ -78,6 +92,14 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("librelpic.so not built: run __graft_entry__.build() or python -m paper_1910_13529_amd.build")
+    # PyTorch ships its own HIP runtime under the same soname as ROCm's.  Loaded
+    # first, it is the one the library binds to, so the process has a single
+    # runtime and torch's streams and allocations are the library's too;
+    # loaded second, it would come up as a separate runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     I64 = ctypes.c_int64
@@ -108,6 +130,17 @@ def load():
     L.relpic_correction_halfwidth.argtypes = [P, ip]
     L.relpic_profile_enable.argtypes = [P, ctypes.c_int]
     L.relpic_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
+    L.relpic_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(Grid), ctypes.POINTER(Solver), ctypes.c_int,
+                                      ctypes.POINTER(Device), ctypes.POINTER(P)]
+    L.relpic_batch_destroy.argtypes = [P]
+    L.relpic_batch_run.argtypes = [P, ctypes.c_int, ctypes.POINTER(P)]
+    L.relpic_batch_step.argtypes = [P, I64]
+    L.relpic_batch_sync.argtypes = [P]
+    L.relpic_batch_set_graph_steps.argtypes = [P, ctypes.c_int]
+    L.relpic_batch_set_tiling.argtypes = [P, ip, ctypes.c_int]
+    L.relpic_batch_get_tiling.argtypes = [P, ip, ip]
+    L.relpic_batch_autotune.argtypes = [P, ctypes.c_int, ctypes.POINTER(BatchTune)]
+    L.relpic_batch_read_field.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, I64]
     L.relpic_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "relpic_last_error":
@@ -159,9 +192,8 @@ class TorchAllocator:
         self.live.pop(ptr, None)
 
 
-def relpic_create(grid, solver_C=None, precision=RELPIC_FP64, device=0, stream=None, allocator=None):
-    L = load()
-    g = Grid()
+def _grid_struct(grid, g=None):
+    g = Grid() if g is None else g
     g.ndim = grid["ndim"]
     for d in range(3):
         g.n[d] = int(grid["n"][d]) if d < g.ndim else 1
@@ -169,7 +201,12 @@ def relpic_create(grid, solver_C=None, precision=RELPIC_FP64, device=0, stream=N
     g.dt = float(grid["dt"])
     g.bc1 = RELPIC_BC_WINDOW if grid.get("window") else RELPIC_BC_PERIODIC
     g.window_speed = float(grid.get("window_speed", 1.0))
-    s = Solver()
+    return g
+
+
+def _solver_struct(solver_C, s=None):
+    """fills a Solver; returns it and the coefficient array it points to (keep it alive)"""
+    s = Solver() if s is None else s
     Carr = None
     if solver_C is not None and len(solver_C) > 1:
         Carr = np.ascontiguousarray(solver_C, dtype=np.float64)
@@ -178,12 +215,24 @@ def relpic_create(grid, solver_C=None, precision=RELPIC_FP64, device=0, stream=N
     else:
         s.M = 1
         s.C = None
+    return s, Carr
+
+
+def _device_struct(device, stream, allocator):
     dev = Device()
     dev.device = device
     dev.stream = stream
     if allocator is not None:
         dev.alloc = allocator._alloc
         dev.free = allocator._free
+    return dev
+
+
+def relpic_create(grid, solver_C=None, precision=RELPIC_FP64, device=0, stream=None, allocator=None):
+    L = load()
+    g = _grid_struct(grid)
+    s, Carr = _solver_struct(solver_C)
+    dev = _device_struct(device, stream, allocator)
     h = ctypes.c_void_p()
     check(L.relpic_create(ctypes.byref(g), ctypes.byref(s), precision, ctypes.byref(dev), ctypes.byref(h)))
     return h
@@ -201,38 +250,24 @@ def relpic_sync(h):
     return check(load().relpic_sync(h))
 
 
-class Sim:
-    """One simulation on one GPU.  grid: dict(ndim, n, dx, dt, window, window_speed)."""
+def _torch_binding(device):
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("relpic needs a ROCm GPU (torch.cuda.is_available() is False)")
+    torch.cuda.set_device(device)
+    return TorchAllocator(device), torch.cuda.current_stream(device)
 
-    def __init__(self, grid, C=None, precision="fp64", device=0, use_torch=True):
+
+class SimOps:
+    """The single-run calls on a handle (owned by a Sim or by a Batch)."""
+
+    def _init_geometry(self, grid, precision):
         self.ndim = grid["ndim"]
         self.n = tuple(int(v) for v in grid["n"][: self.ndim])
         self.N = int(np.prod(self.n))
         self.shape = tuple(reversed(self.n))
         self.prec = RELPIC_FP64 if precision in ("fp64", RELPIC_FP64) else RELPIC_FP32
-        self.allocator = None
-        stream = None
-        if use_torch:
-            import torch
-            if not torch.cuda.is_available():
-                raise RuntimeError("relpic needs a ROCm GPU (torch.cuda.is_available() is False)")
-            torch.cuda.set_device(device)
-            self.allocator = TorchAllocator(device)
-            self.torch_stream = torch.cuda.current_stream(device)
-            stream = self.torch_stream.cuda_stream
-        self.h = relpic_create(grid, C, self.prec, device, stream, self.allocator)
         self.species = []
-
-    def close(self):
-        if getattr(self, "h", None):
-            load().relpic_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     def add_species(self, q_over_m, Q, capacity):
         sid = ctypes.c_int()
@@ -327,3 +362,111 @@ class Sim:
         v = ctypes.c_int()
         check(load().relpic_correction_halfwidth(self.h, ctypes.byref(v)))
         return v.value
+
+
+class Sim(SimOps):
+    """One simulation on one GPU.  grid: dict(ndim, n, dx, dt, window, window_speed)."""
+
+    def __init__(self, grid, C=None, precision="fp64", device=0, use_torch=True):
+        self._init_geometry(grid, precision)
+        self.allocator = None
+        stream = None
+        if use_torch:
+            self.allocator, self.torch_stream = _torch_binding(device)
+            stream = self.torch_stream.cuda_stream
+        self.h = relpic_create(grid, C, self.prec, device, stream, self.allocator)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().relpic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchRun(SimOps):
+    """A run of a Batch (the handle belongs to the batch)."""
+
+    def __init__(self, batch, index, grid):
+        self._init_geometry(grid, batch.prec)
+        self.batch = batch
+        self.index = index
+        h = ctypes.c_void_p()
+        check(load().relpic_batch_run(batch.h, index, ctypes.byref(h)))
+        self.h = h
+
+
+class Batch:
+    """Many independent 2D periodic runs advanced together (relpic_batch_*).
+    grids: list of grid dicts; Cs: list of coefficient arrays (None = Yee)."""
+
+    def __init__(self, grids, Cs=None, precision="fp32", device=0):
+        n = len(grids)
+        self.prec = RELPIC_FP64 if precision in ("fp64", RELPIC_FP64) else RELPIC_FP32
+        self.allocator, self.torch_stream = _torch_binding(device)
+        garr = (Grid * n)()
+        sarr = (Solver * n)()
+        keep = []
+        for r, g in enumerate(grids):
+            _grid_struct(g, garr[r])
+            _, Carr = _solver_struct(None if Cs is None else Cs[r], sarr[r])
+            keep.append(Carr)
+        dev = _device_struct(device, self.torch_stream.cuda_stream, self.allocator)
+        h = ctypes.c_void_p()
+        check(load().relpic_batch_create(n, garr, sarr, self.prec, ctypes.byref(dev), ctypes.byref(h)))
+        self.h = h
+        self.runs = [BatchRun(self, r, g) for r, g in enumerate(grids)]
+
+    def __len__(self):
+        return len(self.runs)
+
+    def step(self, nsteps=1):
+        check(load().relpic_batch_step(self.h, int(nsteps)))
+
+    def sync(self):
+        check(load().relpic_batch_sync(self.h))
+
+    def set_graph_steps(self, steps):
+        check(load().relpic_batch_set_graph_steps(self.h, int(steps)))
+
+    def set_tiling(self, shapes=None, grid_workgroups=0):
+        arr = None
+        if shapes is not None:
+            a = np.ascontiguousarray(shapes, dtype=np.int32)
+            arr = a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        check(load().relpic_batch_set_tiling(self.h, arr, int(grid_workgroups)))
+
+    def tiling(self):
+        a = np.zeros(len(self.runs), dtype=np.int32)
+        g = ctypes.c_int()
+        check(load().relpic_batch_get_tiling(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                             ctypes.byref(g)))
+        return a, g.value
+
+    def autotune(self, reps=10):
+        t = BatchTune()
+        check(load().relpic_batch_autotune(self.h, int(reps), ctypes.byref(t)))
+        return t.as_dict()
+
+    def field(self, run, name):
+        r = self.runs[run]
+        out = np.empty(r.N)
+        check(load().relpic_batch_read_field(self.h, run, FIELDS.index(name), _dp(out), r.N))
+        return out.reshape(r.shape)
+
+    def close(self):
+        if getattr(self, "h", None):
+            for r in self.runs:
+                r.h = None
+            load().relpic_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

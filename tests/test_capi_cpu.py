@@ -79,3 +79,41 @@ def test_courant_limit_matches_dispersion_oracle():
     dt_lim = 0.5 / cn
     with pytest.raises(relpic.RelpicError):
         relpic.relpic_create(_grid(dt=dt_lim * 1.001), solver_C=TABLE1)
+
+
+def _grid_array(specs):
+    from paper_1910_13529_amd.relpic import Grid
+    arr = (Grid * len(specs))()
+    for g, (ndim, bc1) in zip(arr, specs):
+        g.ndim = ndim
+        for d in range(3):
+            g.n[d] = 64 if d < ndim else 1
+            g.dx[d] = 0.05 if d < ndim else 1.0
+        g.dt = 0.02
+        g.bc1 = bc1
+        g.window_speed = 1.0
+    return arr
+
+
+@pytest.mark.parametrize("specs", [[(3, 0)], [(2, 0), (2, 1)], [(2, 0), (3, 0)]])
+def test_batch_create_rejects_non_2d_periodic_runs(specs):
+    """The batch takes 2D runs with a periodic x1 boundary only; the check
+    comes before any device call."""
+    import ctypes
+    from paper_1910_13529_amd import relpic
+    L = relpic.load()
+    h = ctypes.c_void_p()
+    st = L.relpic_batch_create(len(specs), _grid_array(specs), None, relpic.RELPIC_FP32, None, ctypes.byref(h))
+    assert st == relpic.RELPIC_EINVAL and not h.value
+    assert b"periodic" in L.relpic_last_error()
+
+
+def test_batch_calls_reject_null_handle():
+    import ctypes
+    from paper_1910_13529_amd import relpic
+    L = relpic.load()
+    assert L.relpic_batch_step(None, 1) == relpic.RELPIC_EINVAL
+    assert L.relpic_batch_set_graph_steps(None, 2) == relpic.RELPIC_EINVAL
+    assert L.relpic_batch_create(0, _grid_array([(2, 0)]), None, 0, None, ctypes.byref(ctypes.c_void_p())) == \
+        relpic.RELPIC_EINVAL
+    assert L.relpic_batch_destroy(None) == relpic.RELPIC_OK
