@@ -138,7 +138,10 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
 relpic_status relpic_destroy(relpic_sim *sim);
 
 /* Add a particle species with charge-to-mass ratio q_over_m (electrons: -1),
- * charge Q of one macro-particle and room for `capacity` particles. */
+ * charge Q of one macro-particle and room for `capacity` particles.
+ * q_over_m = 0 gives a ballistic species: its momenta never change (no
+ * force), it still deposits current, and its kinetic energy is not counted
+ * in the diagnostics. */
 relpic_status relpic_add_species(relpic_sim *sim, double q_over_m, double Q, int64_t capacity, int *species_id);
 
 /* Append n particles (host arrays): cell [n][ndim] int32, offset [n][ndim]
@@ -291,6 +294,57 @@ relpic_status relpic_batch_autotune(relpic_batch *batch, int reps, relpic_batch_
 
 /* relpic_read_field on one run. */
 relpic_status relpic_batch_read_field(relpic_batch *batch, int run, relpic_field f, double *host, int64_t count);
+
+/* ---- Adjoint of the field advance ------------------------------------------
+ *
+ * Gradient of a field loss with respect to the axial coefficients C_1..C_M
+ * (customized operator of Sec. 3 / App. C; M = 1 is Yee's C_1), by
+ * reverse-mode differentiation of the field advance (Eq. 1 with the axial
+ * operators) and of the J1 correction G = K^-1, with time-step checkpoints.
+ *
+ * The run: a 2D periodic grid, fields zero at t = 0, one ballistic species
+ * (constant momenta, so the deposited current does not depend on C), nsteps
+ * steps.  With b_n = B^{n-1/2}, e_n = E^n and B^n = (b_n + b_{n+1}) / 2:
+ *   L = sum_{n=1..nsteps} dx1 dx2 dt * sum over points outside the box of
+ *       E1^2 (at E1's points) + (E2 - B3c)^2 (at E2's points (i1, i2 + 1/2)),
+ * where B3c(i1) = (B^n_3(i1 - 1) + B^n_3(i1)) / 2 is B3 moved onto E2's point
+ * and the box of step n has centre (x1 + v1 n dt, x2) and half-widths
+ * (half1, half2), physical units, not wrapped.  E2 - B3 is the transverse
+ * force on a beta = 1 particle, zero for the bunch's own field in the
+ * continuum; outside the box it measures the numerical field. */
+typedef struct {
+  double x1, x2;       /* box centre at t = 0 */
+  double v1;           /* box velocity along x1 (units of c) */
+  double half1, half2; /* half-widths */
+} relpic_loss_box;
+
+typedef struct relpic_adj relpic_adj;
+
+/* grid: 2D, bc1 periodic.  C0: M coefficients used to validate the set-up
+ * (M in 1..8).  checkpoint_every: steps between stored field states (the
+ * backward pass recomputes each segment from its checkpoint). */
+relpic_status relpic_adj_create(const relpic_grid *grid, int M, const double *C0, relpic_precision prec,
+                                const relpic_device *dev, int64_t nsteps, int checkpoint_every,
+                                const relpic_loss_box *box, relpic_adj **out);
+relpic_status relpic_adj_destroy(relpic_adj *adj);
+
+/* The ballistic species: n particles of charge Q each (layout as in
+ * relpic_load_particles).  Once per adjoint object. */
+relpic_status relpic_adj_load_particles(relpic_adj *adj, double Q, int64_t n, const int32_t *cell,
+                                        const double *offset, const double *u);
+
+/* Run the nsteps forward with coefficients C[M] from the initial state and
+ * return the loss (synchronizing).  RELPIC_EUNSTABLE if C breaks the Courant
+ * limit. */
+relpic_status relpic_adj_forward(relpic_adj *adj, const double *C, double *loss);
+
+/* dL/dC_l, l = 1..M, at the coefficients of the last forward call
+ * (synchronizing); RELPIC_ESTATE without a forward call. */
+relpic_status relpic_adj_backward(relpic_adj *adj, double *dLdC);
+
+/* The simulation the adjoint runs on (owned by it): fields after the last
+ * forward call. */
+relpic_status relpic_adj_sim(relpic_adj *adj, relpic_sim **sim);
 
 const char *relpic_last_error(void);
 

@@ -15,4 +15,7 @@ Contents
                          App. D) and the self-force (Eqs. 19, 25)
   dispersion.py          closed-form vacuum dispersion of the discrete
                          Maxwell operators (Eq. 4)
+  field_loss.py          field loss around a moving bunch on the oracle's
+                         fields and its central-difference gradient in the
+                         axial coefficients
 """

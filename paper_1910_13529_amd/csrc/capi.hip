@@ -274,7 +274,9 @@ relpic_status do_diag(relpic_sim *s, relpic_diag *out) {
   launch_diag_field_energy<Real>(g, f, s->dbuf + 0, s->st);
   const double dV = cell_volume(s);
   for (auto &sp : s->sp) {
-    launch_diag_kinetic<Real>(parts<Real>(sp), sp.Q / sp.qm, s->dbuf + 1, (unsigned long long *)(s->dbuf + 5), s->st);
+    // a ballistic species (q/m = 0) has no mass in the model: its kinetic energy is not counted
+    launch_diag_kinetic<Real>(parts<Real>(sp), sp.qm != 0.0 ? sp.Q / sp.qm : 0.0, s->dbuf + 1,
+                              (unsigned long long *)(s->dbuf + 5), s->st);
     launch_diag_rho<Real>(s->ndim, g, parts<Real>(sp), sp.Q / dV, s->rho, s->st);
   }
   Axial<double> c1{};
@@ -477,7 +479,7 @@ relpic_status relpic_destroy(relpic_sim *sim) {
 
 relpic_status relpic_add_species(relpic_sim *s, double q_over_m, double Q, int64_t capacity, int *species_id) {
   if (relpic_status r = check_sim(s)) return r;
-  if (!(q_over_m != 0.0) || !std::isfinite(q_over_m) || !std::isfinite(Q) || capacity < 0 || capacity > (1LL << 31))
+  if (!std::isfinite(q_over_m) || !std::isfinite(Q) || capacity < 0 || capacity > (1LL << 31))
     return fail(RELPIC_EINVAL, "add_species: bad q/m, charge or capacity");
   Species sp;
   sp.qm = q_over_m;

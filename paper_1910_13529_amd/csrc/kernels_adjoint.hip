@@ -1,0 +1,206 @@
+// Kernels of the adjoint (reverse-mode) field advance on a 2D periodic grid:
+// the loss on the fields around a moving bunch, its gradient with respect to
+// E and B, and the FP64 reductions that give dL/dC_l (the axial coefficients
+// enter both curl operators and the J1 correction G = K^-1 of Sec. 3).
+//
+// Loss at step n (E^n; B^n = (B^{n-1/2} + B^{n+1/2}) / 2):
+//   l_n = w * sum over points outside the bunch box of
+//         E1^2 (at E1's point)  +  (E2 - B3c)^2 (at E2's point),
+// with B3c the two-point x1 average of B^n_3 onto E2's point (i1, i2 + 1/2).
+// The reverse-mode steps reuse the forward curl kernels: the transposes of
+// the discrete operators satisfy (curl+)^T = curl-, so the adjoint state
+// advances with the forward update and a negated time step.
+#include "adjoint_kernels.h"
+#include "relpic_internal.h"
+
+namespace relpic {
+
+namespace {
+
+// Whether the point ((i1 + o1) dx1, (i2 + o2) dx2) lies outside the box.
+// Rounded products and differences (no fused multiply-add), so that a point
+// on the box's edge falls on the same side as in plain double arithmetic.
+__device__ __forceinline__ bool outside(const LossBox &b, int i1, double o1, int i2, double o2) {
+  const double x1 = __dmul_rn(i1 + o1, b.dx1), x2 = __dmul_rn(i2 + o2, b.dx2);
+  return fabs(__dsub_rn(x1, b.c1)) > b.h1 || fabs(__dsub_rn(x2, b.c2)) > b.h2;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// FP64 sum over a workgroup of 256 threads, atomically added to *out
+__device__ __forceinline__ void block_add(double v, double *out) {
+  __shared__ double part[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) part[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+// E2 - B3c at E2's point of cell (i1, i2), in FP64 (B3 given as the two
+// half-step buffers a, b)
+template <typename Real>
+__device__ __forceinline__ double e2_minus_b3(const Geo &g, const Real *E2, const Real *B3a, const Real *B3b, int i1,
+                                              long long row) {
+  const int im = wrapi(i1 - 1, g.n1);
+  const double b3 = 0.25 * ((double)B3a[row + im] + (double)B3b[row + im] + (double)B3a[row + i1] +
+                            (double)B3b[row + i1]);
+  return (double)E2[row + i1] - b3;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_adj_loss(Geo g, const Real *E1, const Real *E2, const Real *B3a,
+                                                  const Real *B3b, LossBox lb, double w, double *out) {
+  double acc = 0.0;
+  const long long N = (long long)g.n1 * g.n2;
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < N; id += (long long)gridDim.x * blockDim.x) {
+    const int i1 = (int)(id % g.n1), i2 = (int)(id / g.n1);
+    const long long row = id - i1;
+    if (outside(lb, i1, 0.5, i2, 0.0)) {
+      const double e1 = (double)E1[id];
+      acc += e1 * e1;
+    }
+    if (outside(lb, i1, 0.0, i2, 0.5)) {
+      const double r = e2_minus_b3(g, E2, B3a, B3b, i1, row);
+      acc += r * r;
+    }
+  }
+  block_add(w * acc, out);
+}
+
+// aE1 += fe dl/dE1, aE2 += fe dl/dE2, aB3 += fb dl/dB^n_3.  B3c(i1) averages
+// B^n_3 at i1 - 1 and i1, so dl/dB^n_3(k) = -w (m r)(k) - w (m r)(k + 1), with
+// r = E2 - B3c and m the outside-the-box mask at E2's points.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_adj_loss_grad(Geo g, const Real *E1, const Real *E2, const Real *B3a,
+                                                       const Real *B3b, LossBox lb, double w, double fe, double fb,
+                                                       Real *aE1, Real *aE2, Real *aB3) {
+  const long long N = (long long)g.n1 * g.n2;
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < N; id += (long long)gridDim.x * blockDim.x) {
+    const int i1 = (int)(id % g.n1), i2 = (int)(id / g.n1);
+    const long long row = id - i1;
+    const bool m0 = outside(lb, i1, 0.0, i2, 0.5);
+    const double r0 = m0 ? e2_minus_b3(g, E2, B3a, B3b, i1, row) : 0.0;
+    if (fe != 0.0) {
+      if (outside(lb, i1, 0.5, i2, 0.0)) aE1[id] += (Real)(fe * 2.0 * w * (double)E1[id]);
+      if (m0) aE2[id] += (Real)(fe * 2.0 * w * r0);
+    }
+    if (fb != 0.0) {
+      const int ip = wrapi(i1 + 1, g.n1);
+      const bool m1 = outside(lb, ip, 0.0, i2, 0.5);
+      const double r1 = m1 ? e2_minus_b3(g, E2, B3a, B3b, ip, row) : 0.0;
+      aB3[id] += (Real)(fb * (-w) * (r0 + r1));
+    }
+  }
+}
+
+// blockIdx.y = l - 1.  part 0 (T1): sum  bA2 (E3(i+l) - E3(i-l+1)) - bA3 (E2(i+l) - E2(i-l+1))
+//                      part 1 (T2): sum -eA2 (B3(i+l-1) - B3(i-l)) + eA3 (B2(i+l-1) - B2(i-l))
+// times `scale`, added to out[l - 1].
+template <typename Real>
+__global__ __launch_bounds__(256) void k_adj_grad_curl(Geo g, int part, const Real *A2, const Real *A3,
+                                                       const Real *F2, const Real *F3, double scale, double *out) {
+  const int l = blockIdx.y + 1;
+  double acc = 0.0;
+  const long long N = (long long)g.n1 * g.n2;
+  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < N; id += (long long)gridDim.x * blockDim.x) {
+    const int i1 = (int)(id % g.n1);
+    const long long row = id - i1;
+    if (part == 0) {
+      const int p = wrapi(i1 + l, g.n1), m = wrapi(i1 - l + 1, g.n1);
+      acc += (double)A2[id] * ((double)F3[row + p] - (double)F3[row + m]) -
+             (double)A3[id] * ((double)F2[row + p] - (double)F2[row + m]);
+    } else {
+      const int p = wrapi(i1 + l - 1, g.n1), m = wrapi(i1 - l, g.n1);
+      acc += -(double)A2[id] * ((double)F3[row + p] - (double)F3[row + m]) +
+             (double)A3[id] * ((double)F2[row + p] - (double)F2[row + m]);
+    }
+  }
+  block_add(scale * acc, out + (l - 1));
+}
+
+// blockIdx.y = l - 1.  T3_l = scale * sum_i J1c(i) sum_{|k| < l} (G aE1)(i + k)
+// over the support of J1c (its deposit box widened along x1 by ng), with
+// (G v)(j) = sum_{|m| <= ng} g_|m| v(j - m).
+template <typename Real>
+__global__ __launch_bounds__(256) void k_adj_grad_jcorr(Geo g, const Real *aE1, const Real *J1c, const Real *taps,
+                                                        int ng, const JBox *box, double scale, double *out) {
+  const int l = blockIdx.y + 1;
+  const JBox b = *box;
+  double acc = 0.0;
+  if (b.hi[0] >= b.lo[0]) {
+    int lo1 = b.lo[0] - ng, hi1 = b.hi[0] + ng;
+    if (hi1 - lo1 + 1 >= g.n1) {
+      lo1 = 0;
+      hi1 = g.n1 - 1;
+    }
+    const long long w1 = hi1 - lo1 + 1, w2 = b.hi[1] - b.lo[1] + 1;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < w1 * w2;
+         t += (long long)gridDim.x * blockDim.x) {
+      const int i1 = wrapi(lo1 + (int)(t % w1), g.n1);
+      const int i2 = b.lo[1] + (int)(t / w1);
+      const long long row = (long long)g.n1 * i2;
+      const double j = (double)J1c[row + i1];
+      if (j == 0.0) continue;
+      double s = 0.0;
+      for (int k = -(l - 1); k <= l - 1; ++k) {
+        const int c = i1 + k;
+        double ge = (double)taps[0] * (double)aE1[row + wrapi(c, g.n1)];
+        for (int m = 1; m <= ng; ++m)
+          ge += (double)taps[m] * ((double)aE1[row + wrapi(c - m, g.n1)] + (double)aE1[row + wrapi(c + m, g.n1)]);
+        s += ge;
+      }
+      acc += j * s;
+    }
+  }
+  block_add(scale * acc, out + (l - 1));
+}
+
+constexpr int kAdjGrid = 1024;
+
+}  // namespace
+
+template <typename Real>
+void launch_adj_loss(const Geo &g, const Real *E1, const Real *E2, const Real *B3a, const Real *B3b,
+                     const LossBox &lb, double w, double *out, hipStream_t st) {
+  k_adj_loss<Real><<<kAdjGrid, 256, 0, st>>>(g, E1, E2, B3a, B3b, lb, w, out);
+}
+
+template <typename Real>
+void launch_adj_loss_grad(const Geo &g, const Real *E1, const Real *E2, const Real *B3a, const Real *B3b,
+                          const LossBox &lb, double w, double fe, double fb, Real *aE1, Real *aE2, Real *aB3,
+                          hipStream_t st) {
+  k_adj_loss_grad<Real><<<kAdjGrid, 256, 0, st>>>(g, E1, E2, B3a, B3b, lb, w, fe, fb, aE1, aE2, aB3);
+}
+
+template <typename Real>
+void launch_adj_grad_curl(const Geo &g, int part, int M, const Real *A2, const Real *A3, const Real *F2, const Real *F3,
+                          double scale, double *out, hipStream_t st) {
+  k_adj_grad_curl<Real><<<dim3(kAdjGrid / 4, M), 256, 0, st>>>(g, part, A2, A3, F2, F3, scale, out);
+}
+
+template <typename Real>
+void launch_adj_grad_jcorr(const Geo &g, int M, const Real *aE1, const Real *J1c, const Real *taps, int ng,
+                           const JBox *box, double scale, double *out, hipStream_t st) {
+  k_adj_grad_jcorr<Real><<<dim3(64, M), 256, 0, st>>>(g, aE1, J1c, taps, ng, box, scale, out);
+}
+
+#define RELPIC_INST_ADJ(Real)                                                                                      \
+  template void launch_adj_loss<Real>(const Geo &, const Real *, const Real *, const Real *, const Real *,         \
+                                      const LossBox &, double, double *, hipStream_t);                            \
+  template void launch_adj_loss_grad<Real>(const Geo &, const Real *, const Real *, const Real *, const Real *,    \
+                                           const LossBox &, double, double, double, Real *, Real *, Real *,       \
+                                           hipStream_t);                                                          \
+  template void launch_adj_grad_curl<Real>(const Geo &, int, int, const Real *, const Real *, const Real *,        \
+                                           const Real *, double, double *, hipStream_t);                           \
+  template void launch_adj_grad_jcorr<Real>(const Geo &, int, const Real *, const Real *, const Real *, int,       \
+                                            const JBox *, double, double *, hipStream_t);
+
+RELPIC_INST_ADJ(float)
+RELPIC_INST_ADJ(double)
+
+}  // namespace relpic

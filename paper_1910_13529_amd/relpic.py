@@ -28,7 +28,8 @@ EXPORTS = (
     "relpic_sort_particles", "relpic_set_sort_interval", "relpic_batch_create", "relpic_batch_destroy",
     "relpic_batch_run", "relpic_batch_step", "relpic_batch_sync", "relpic_batch_set_graph_steps",
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
-    "relpic_last_error",
+    "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
+    "relpic_adj_backward", "relpic_adj_sim", "relpic_last_error",
 )
 KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes")
 
@@ -80,6 +81,11 @@ class BatchTune(ctypes.Structure):
         return {"ms_uniform": list(self.ms_uniform), "ms_model": self.ms_model,
                 "ms_persistent": list(self.ms_persistent), "ms_chosen": self.ms_chosen, "choice": self.choice,
                 "grid_workgroups": self.grid_workgroups, "runs_per_shape": list(self.runs_per_shape)}
+
+
+class LossBox(ctypes.Structure):
+    _fields_ = [("x1", ctypes.c_double), ("x2", ctypes.c_double), ("v1", ctypes.c_double),
+                ("half1", ctypes.c_double), ("half2", ctypes.c_double)]
 
 
 _lib = None
@@ -141,6 +147,13 @@ def load():
     L.relpic_batch_get_tiling.argtypes = [P, ip, ip]
     L.relpic_batch_autotune.argtypes = [P, ctypes.c_int, ctypes.POINTER(BatchTune)]
     L.relpic_batch_read_field.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, I64]
+    L.relpic_adj_create.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, dp, ctypes.c_int, ctypes.POINTER(Device), I64,
+                                    ctypes.c_int, ctypes.POINTER(LossBox), ctypes.POINTER(P)]
+    L.relpic_adj_destroy.argtypes = [P]
+    L.relpic_adj_load_particles.argtypes = [P, D, I64, ctypes.POINTER(ctypes.c_int32), dp, dp]
+    L.relpic_adj_forward.argtypes = [P, dp, dp]
+    L.relpic_adj_backward.argtypes = [P, dp]
+    L.relpic_adj_sim.argtypes = [P, ctypes.POINTER(P)]
     L.relpic_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "relpic_last_error":
@@ -470,3 +483,83 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Adjoint:
+    """Loss of the fields around a ballistic bunch and its gradient with
+    respect to the axial coefficients (relpic_adj_*).  grid: 2D periodic grid
+    dict; C0: initial coefficients (length M); box: dict(x1, x2, v1, half1,
+    half2) of the excluded region."""
+
+    def __init__(self, grid, C0, nsteps, box, checkpoint_every=20, precision="fp32", device=0):
+        self.prec = RELPIC_FP64 if precision in ("fp64", RELPIC_FP64) else RELPIC_FP32
+        self.allocator, self.torch_stream = _torch_binding(device)
+        self.M = len(C0)
+        g = _grid_struct(grid)
+        C = np.ascontiguousarray(C0, dtype=np.float64)
+        lb = LossBox(*(float(box[k]) for k in ("x1", "x2", "v1", "half1", "half2")))
+        dev = _device_struct(device, self.torch_stream.cuda_stream, self.allocator)
+        h = ctypes.c_void_p()
+        check(load().relpic_adj_create(ctypes.byref(g), self.M, _dp(C), self.prec, ctypes.byref(dev), int(nsteps),
+                                       int(checkpoint_every), ctypes.byref(lb), ctypes.byref(h)))
+        self.h = h
+        self.grid = grid
+
+    def load_particles(self, Q, cell, offset, u):
+        cell = np.ascontiguousarray(cell, dtype=np.int32).reshape(-1, 2)
+        offset = np.ascontiguousarray(offset, dtype=np.float64).reshape(-1, 2)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+        check(load().relpic_adj_load_particles(self.h, float(Q), cell.shape[0],
+                                               cell.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(offset),
+                                               _dp(u)))
+
+    def forward(self, C):
+        C = np.ascontiguousarray(C, dtype=np.float64)
+        assert C.size == self.M
+        out = np.zeros(1)
+        check(load().relpic_adj_forward(self.h, _dp(C), _dp(out)))
+        return float(out[0])
+
+    def backward(self):
+        g = np.zeros(self.M)
+        check(load().relpic_adj_backward(self.h, _dp(g)))
+        return g
+
+    def sim(self):
+        """The simulation the adjoint runs on (fields of the last forward pass)."""
+        h = ctypes.c_void_p()
+        check(load().relpic_adj_sim(self.h, ctypes.byref(h)))
+        v = SimOps()
+        v._init_geometry(self.grid, self.prec)
+        v.h = h
+        return v
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().relpic_adj_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def adjoint_loss(adj, C):
+    """torch.autograd.Function: loss(C) with dL/dC from the adjoint pass.
+    C: a 1-D float64 CPU tensor of length adj.M (requires_grad for training)."""
+    import torch
+
+    class _AdjointLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, c):
+            loss = adj.forward(c.detach().cpu().numpy().astype(np.float64))
+            return torch.tensor(loss, dtype=c.dtype)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = torch.from_numpy(adj.backward()).to(grad_out.dtype)
+            return grad_out * g
+
+    return _AdjointLoss.apply(C)

@@ -61,3 +61,28 @@ def batch_workload(nruns=256, seed=4, solver="mixed", npart=4096, M=16, fit=None
         runs.append({"grid": grid, "C": C, "cell": cell, "offset": off, "u": u, "Q": Q, "sigma1": sigma1,
                      "draw": d})
     return runs
+
+
+def adjoint_workload(n=(1024, 256), npart=1 << 16, nsteps=200, M=4, fit=None):
+    """The differentiable case: 2D periodic grid, dx = 0.05, dt = dx/4
+    (kappa = 4), a ballistic bunch of npart particles with gamma = 1e4
+    (sigma_z = 0.1, sigma_r = 0.05, centred on the middle node), M axial
+    coefficients initialized by the App. C fit (p = 2, w = 0.6, n = 10), the
+    loss box 3 sigma around the bunch moving at beta."""
+    if fit is None:
+        from .relpic import relpic_fit_coefficients
+
+        def fit(kappa, M):
+            return relpic_fit_coefficients(kappa, M)[0]
+    dx = 0.05
+    dt = dx / 4.0
+    gamma = 1e4
+    sz, sr = 0.1, 0.05
+    center = (n[0] // 2, n[1] // 2)
+    cell, off, u = inputs.gaussian_bunch(11, npart, center, (sz / dx, sr / dx), gamma, ndim=2, clip_sigmas=4.0)
+    beta = math.sqrt(1.0 - 1.0 / (gamma * gamma))
+    Q = -2.0 * math.pi * sz * sr / npart  # peak line density 1
+    box = dict(x1=center[0] * dx, x2=center[1] * dx, v1=beta, half1=3 * sz, half2=3 * sr)
+    grid = dict(ndim=2, n=(n[0], n[1], 1), dx=(dx, dx, 1.0), dt=dt, window=False)
+    C0 = np.asarray(fit(dx / dt, M), dtype=np.float64) if M > 1 else np.ones(1)
+    return {"grid": grid, "C0": C0, "cell": cell, "offset": off, "u": u, "Q": Q, "box": box, "nsteps": nsteps}
