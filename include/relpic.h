@@ -346,6 +346,39 @@ relpic_status relpic_adj_backward(relpic_adj *adj, double *dLdC);
  * forward call. */
 relpic_status relpic_adj_sim(relpic_adj *adj, relpic_sim **sim);
 
+/* ---- k-space field of a streaming charge (FP64, on the GPU) -----------------
+ *
+ * Sec. 2, Eq. 13 (general beta through Eqs. 8-9): the on-axis E1 of a point
+ * charge q moving at beta along x1 through a 2D grid with the Yee transverse
+ * operator and the axial operator C_1..C_M (Yee: M = 1, C = NULL or {1}),
+ * particle on a node, in the steady state of an infinite grid.  The k1
+ * integral runs over the zones nu = -nu_max..nu_max of the aliased density
+ * (App. A) with the k2 integral in closed form (App. D, causal pole
+ * prescription).  Computed in FP64 by quadrature on the device. */
+typedef struct {
+  int M;
+  const double *C;
+  double kappa;    /* dx1 / dt (> 1) */
+  double r;        /* dx2 / dx1 */
+  double beta;     /* 0 < beta <= 1 */
+  int shape_order; /* B-spline order of the deposit along x1 (2: quadratic) */
+  int tpow;        /* power of the transverse density factor 1 - sin^2(k2 dx2/2)/2:
+                      0 for the paper's linear transverse shape, 1 for a quadratic
+                      deposit, 2 for a quadratic deposit and gather */
+  int nu_max;      /* alias zones (the paper uses 1) */
+} relpic_kspace;
+
+/* out[i] = E1 dx1 / q at the E1 point i1_rel[i] cells ahead of the particle
+ * (E1 sits at i1 + 1/2, so i1_rel = 0 is half a cell ahead, -1 half a cell
+ * behind).  Synchronizing; dev may be NULL (device 0, null stream, hipMalloc). */
+relpic_status relpic_kspace_e1(const relpic_kspace *q, const relpic_device *dev, int64_t npts, const double *i1_rel,
+                               double *out);
+
+/* Self-force F1 dx1 / q^2 in the paper's convention (Eqs. 19, 25): the field
+ * weighted by the gather's unaliased shape of order gather_order. */
+relpic_status relpic_kspace_self_force(const relpic_kspace *q, const relpic_device *dev, int gather_order,
+                                       double *out);
+
 const char *relpic_last_error(void);
 
 #ifdef __cplusplus

@@ -29,7 +29,7 @@ EXPORTS = (
     "relpic_batch_run", "relpic_batch_step", "relpic_batch_sync", "relpic_batch_set_graph_steps",
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
     "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
-    "relpic_adj_backward", "relpic_adj_sim", "relpic_last_error",
+    "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_self_force", "relpic_last_error",
 )
 KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes")
 
@@ -86,6 +86,12 @@ class BatchTune(ctypes.Structure):
 class LossBox(ctypes.Structure):
     _fields_ = [("x1", ctypes.c_double), ("x2", ctypes.c_double), ("v1", ctypes.c_double),
                 ("half1", ctypes.c_double), ("half2", ctypes.c_double)]
+
+
+class KSpaceParams(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("C", ctypes.POINTER(ctypes.c_double)), ("kappa", ctypes.c_double),
+                ("r", ctypes.c_double), ("beta", ctypes.c_double), ("shape_order", ctypes.c_int),
+                ("tpow", ctypes.c_int), ("nu_max", ctypes.c_int)]
 
 
 _lib = None
@@ -154,6 +160,8 @@ def load():
     L.relpic_adj_forward.argtypes = [P, dp, dp]
     L.relpic_adj_backward.argtypes = [P, dp]
     L.relpic_adj_sim.argtypes = [P, ctypes.POINTER(P)]
+    L.relpic_kspace_e1.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), I64, dp, dp]
+    L.relpic_kspace_self_force.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), ctypes.c_int, dp]
     L.relpic_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "relpic_last_error":
@@ -563,3 +571,34 @@ def adjoint_loss(adj, C):
             return grad_out * g
 
     return _AdjointLoss.apply(C)
+
+
+def _kspace_struct(C, kappa, r, beta, order, tpow, nu_max):
+    q = KSpaceParams()
+    Carr = np.ascontiguousarray([1.0] if C is None else C, dtype=np.float64)
+    q.M = Carr.size
+    q.C = _dp(Carr)
+    q.kappa, q.r, q.beta = float(kappa), float(r), float(beta)
+    q.shape_order, q.tpow, q.nu_max = int(order), int(tpow), int(nu_max)
+    return q, Carr
+
+
+def kspace_e1(i1_rel, C=None, kappa=4.0, r=1.0, beta=1.0, order=2, tpow=0, nu_max=1, device=0):
+    """On-axis E1 dx1 / q of a streaming charge at E1 points i1_rel cells
+    ahead of it (relpic_kspace_e1; FP64 quadrature on the GPU)."""
+    q, keep = _kspace_struct(C, kappa, r, beta, order, tpow, nu_max)
+    x = np.ascontiguousarray(np.atleast_1d(i1_rel), dtype=np.float64)
+    out = np.zeros(x.size)
+    dev = _device_struct(device, None, None)
+    check(load().relpic_kspace_e1(ctypes.byref(q), ctypes.byref(dev), x.size, _dp(x), _dp(out)))
+    return out
+
+
+def kspace_self_force(C=None, kappa=4.0, r=1.0, beta=1.0, order=2, tpow=0, nu_max=1, gather_order=None, device=0):
+    """Self-force F1 dx1 / q^2 (relpic_kspace_self_force)."""
+    q, keep = _kspace_struct(C, kappa, r, beta, order, tpow, nu_max)
+    out = np.zeros(1)
+    dev = _device_struct(device, None, None)
+    check(load().relpic_kspace_self_force(ctypes.byref(q), ctypes.byref(dev),
+                                          int(order if gather_order is None else gather_order), _dp(out)))
+    return float(out[0])
