@@ -149,3 +149,27 @@ def test_plasma_injection_window_fp64():
     assert (alive == ao[sl]).all()
     assert np.abs(xg[alive] - xo[sl][ao[sl]]).max() < 1e-12
     assert np.abs(u[alive] - uo[sl][ao[sl]]).max() < 1e-12 * 1e-4 * 10
+
+
+@pytest.mark.parametrize("ndim", [3, 2])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_dense_bunch(ndim, precision, tol):
+    """A bunch packed into one transverse cell and a few x1 cells (thousands
+    of particles per cell, as in the core of a dense beam): whole wavefronts
+    share one cell and deposit through the wavefront reduce-scatter."""
+    n = (64, 12, 12)[:ndim]
+    dx = (0.02, 0.05, 0.05)[:ndim]
+    dt = 0.005
+    center = [0.5 * n[0]] + [n[d] // 2 for d in range(1, ndim)]
+    cell, off, u = inputs.gaussian_bunch(21, 12000, center, (0.6,) + (0.08,) * (ndim - 1), 1e4, 0.01, 1e-3,
+                                         ndim=ndim, clip_sigmas=4.0)
+    sp = (-1e-4, -1.0, cell, off, u, len(cell))
+    g, o, ids = make_pair(ndim, n, dx, dt, TABLE1, False, [sp], precision=precision)
+    g.step(30)
+    o.step(30)
+    errs = field_errors(g, o)
+    log("dense bunch %dD %s: %s" % (ndim, precision, errs))
+    assert max(errs.values()) < tol, errs
+    dxp, dup = particle_errors(g, o, ids[0], len(cell))
+    assert dxp < (1e-12 if precision == "fp64" else 1e-4) and dup < tol * 2
+    g.sync()
