@@ -217,16 +217,14 @@ __device__ __forceinline__ void reduce_scatter(Real *v, int lane, int &off) {
   }
 }
 
-// Reduce an N1 x N2 x N3 box of per-lane values over the wavefront and add
-// the totals (one per lane) to the sink at box origin (x1, x2, x3).
-template <typename Real, int N1, int N2, int N3, typename F>
-__device__ __forceinline__ void box_reduce_add(const Sink<Real> &sk, int comp, int lane, bool fits, int x1, int x2,
-                                               int x3, F val) {
+// Sum an N1 x N2 x N3 box of per-lane values v over the wavefront and add the
+// totals (one per lane) to the sink at box origin (x1, x2, x3); v is
+// overwritten.
+template <typename Real, int N1, int N2, int N3>
+__device__ __forceinline__ void box_reduce_add(const Sink<Real> &sk, int comp, int lane, int x1, int x2, int x3,
+                                               Real *v) {
   constexpr int S = N1 * N2 * N3;
   static_assert(S <= 64, "box larger than a wavefront");
-  Real v[S];
-#pragma unroll
-  for (int k = 0; k < S; ++k) v[k] = fits ? val(k % N1, (k / N1) % N2, k / (N1 * N2)) : Real(0);
   int off = 0;
   reduce_scatter<Real, S, 32>(v, lane, off);
   if (off < S) sk.add(comp, x1 + off % N1, x2 + (off / N1) % N2, x3 + off / (N1 * N2), v[0]);
@@ -316,12 +314,13 @@ __device__ __forceinline__ Real ext5(const Real *in, int o, int b) {
 // most one node after the wave's leftmost one.  Its exact supports are then
 // J1: 4 x 3 x 3 half/node points, J2: 5 x 2 x 3, J3: 5 x 3 x 2 (2D: 4 x 3,
 // 5 x 2, 5 x 3), all inside boxes that every such lane shares.
+// Returns whether this lane's particle still has to be deposited directly.
 template <typename Real, int DIM>
-__device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, const PushParams<Real> &q,
+__device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, const PushParams<Real> &q,
                                              const Sink<Real> &sk) {
   const int lane = threadIdx.x & 63;
   const unsigned long long act = __ballot(active);
-  if (act == 0ULL) return;
+  if (act == 0ULL) return false;
   const int first = __ffsll((long long)act) - 1;
   const int c2w = __shfl(m.c[1], first, 64);
   const int c3w = __shfl(m.c[2], first, 64);
@@ -336,7 +335,12 @@ __device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, 
   const bool fits = inrow && (o1 == 0 || o1 == 1) && flat2 && flat3;
   const unsigned long long fm = __ballot(fits);
   if (__popcll(fm) >= 4) {
+    // Branch-free separable form of the exact supports: each box value is an
+    // x1 factor (or x2/x3 running sum) times a transverse Esirkepov weight
+    //   S0a S0b + DSa S0b/2 + S0a DSb/2 + DSa DSb/3 = S0a P_b + DSa Q_b,
+    // P = S0 + DS/2, Q = S0/2 + DS/3; lanes that do not fit contribute 0.
     const int oo = fits ? o1 : 0;
+    const Real z = fits ? Real(1) : Real(0);
     Real e1S0[5], e1DS[5];
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
@@ -344,37 +348,88 @@ __device__ __forceinline__ void deposit_wave(bool active, const Moved<Real> &m, 
       e1DS[b] = ext5(m.DS[0], oo, b);
     }
     // J1 at x1 half points: running sum of DS1 (three entries) shifted by oo
-    auto cum1 = [&](int b) -> Real {
+    Real c1[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
       const Real lo = (b <= 2) ? m.cum[0][b] : Real(0);
       const Real hi = (b >= 1 && b <= 3) ? m.cum[0][b - 1] : Real(0);
-      return oo ? hi : lo;
-    };
+      c1[b] = z * q.f1 * (oo ? hi : lo);
+    }
+    Real P2[3], Q2[3], P3[3], Q3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      P2[k] = m.S0[1][k] + Real(0.5) * m.DS[1][k];
+      Q2[k] = Real(0.5) * m.S0[1][k] + Real(1.0 / 3.0) * m.DS[1][k];
+      P3[k] = m.S0[2][k] + Real(0.5) * m.DS[2][k];
+      Q3[k] = Real(0.5) * m.S0[2][k] + Real(1.0 / 3.0) * m.DS[2][k];
+    }
     const int x1 = cmin - 1, x2 = c2w - 1, x3 = DIM == 3 ? c3w - 1 : 0;
     if (DIM == 3) {
-      box_reduce_add<Real, 4, 3, 3>(sk, 0, lane, fits, x1, x2, x3, [&](int b, int a2, int a3) {
-        return q.f1 * cum1(b) * wperp(m.S0[1], m.DS[1], m.S0[2], m.DS[2], a2, a3);
-      });
-      box_reduce_add<Real, 5, 2, 3>(sk, 1, lane, fits, x1, x2, x3, [&](int b, int a2, int a3) {
-        return q.f2 * m.cum[1][a2] * wperp(e1S0, e1DS, m.S0[2], m.DS[2], b, a3);
-      });
-      box_reduce_add<Real, 5, 3, 2>(sk, 2, lane, fits, x1, x2, x3, [&](int b, int a2, int a3) {
-        return q.f3 * m.cum[2][a3] * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2);
-      });
+      {
+        Real v[36];
+#pragma unroll
+        for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+          for (int a2 = 0; a2 < 3; ++a2) {
+            const Real w = m.S0[1][a2] * P3[a3] + m.DS[1][a2] * Q3[a3];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v[b + 4 * (a2 + 3 * a3)] = c1[b] * w;
+          }
+        box_reduce_add<Real, 4, 3, 3>(sk, 0, lane, x1, x2, x3, v);
+      }
+      {
+        Real v[30];
+#pragma unroll
+        for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+          for (int b = 0; b < 5; ++b) {
+            const Real w = e1S0[b] * P3[a3] + e1DS[b] * Q3[a3];
+#pragma unroll
+            for (int a2 = 0; a2 < 2; ++a2) v[b + 5 * (a2 + 2 * a3)] = z * q.f2 * m.cum[1][a2] * w;
+          }
+        box_reduce_add<Real, 5, 2, 3>(sk, 1, lane, x1, x2, x3, v);
+      }
+      {
+        Real v[30];
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+          for (int b = 0; b < 5; ++b) {
+            const Real w = e1S0[b] * P2[a2] + e1DS[b] * Q2[a2];
+#pragma unroll
+            for (int a3 = 0; a3 < 2; ++a3) v[b + 5 * (a2 + 3 * a3)] = z * q.f3 * m.cum[2][a3] * w;
+          }
+        box_reduce_add<Real, 5, 3, 2>(sk, 2, lane, x1, x2, x3, v);
+      }
     } else {
-      box_reduce_add<Real, 4, 3, 1>(sk, 0, lane, fits, x1, x2, 0, [&](int b, int a2, int) {
-        return q.f1 * cum1(b) * (m.S0[1][a2] + Real(0.5) * m.DS[1][a2]);
-      });
-      box_reduce_add<Real, 5, 2, 1>(sk, 1, lane, fits, x1, x2, 0, [&](int b, int a2, int) {
-        return q.f2 * m.cum[1][a2] * (e1S0[b] + Real(0.5) * e1DS[b]);
-      });
-      box_reduce_add<Real, 5, 3, 1>(sk, 2, lane, fits, x1, x2, 0, [&](int b, int a2, int) {
-        return m.jz * wperp(e1S0, e1DS, m.S0[1], m.DS[1], b, a2);
-      });
+      {
+        Real v[12];
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) v[b + 4 * a2] = c1[b] * P2[a2];
+        box_reduce_add<Real, 4, 3, 1>(sk, 0, lane, x1, x2, 0, v);
+      }
+      {
+        Real v[10];
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int b = 0; b < 5; ++b) v[b + 5 * a2] = z * q.f2 * m.cum[1][a2] * (e1S0[b] + Real(0.5) * e1DS[b]);
+        box_reduce_add<Real, 5, 2, 1>(sk, 1, lane, x1, x2, 0, v);
+      }
+      {
+        Real v[15];
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+          for (int b = 0; b < 5; ++b) v[b + 5 * a2] = z * m.jz * (e1S0[b] * P2[a2] + e1DS[b] * Q2[a2]);
+        box_reduce_add<Real, 5, 3, 1>(sk, 2, lane, x1, x2, 0, v);
+      }
     }
-    if (active && !fits) deposit_direct<Real, DIM>(m, q, sk);
-  } else if (active) {
-    deposit_direct<Real, DIM>(m, q, sk);
+    return active && !fits;
   }
+  return active;
 }
 
 // One workgroup's share of the particle phase: chunk `chunk` of K * 256
@@ -672,7 +727,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
         p.u3[i] = un3;
       }
     }
-    deposit_wave<Real, DIM>(active, m, q, sk);
+    if (deposit_wave<Real, DIM>(active, m, q, sk)) deposit_direct<Real, DIM>(m, q, sk);
   }
 
   // ---- flush the tile to HBM: one atomic per non-zero point
