@@ -34,6 +34,178 @@ __global__ __launch_bounds__(kSeg) void k_curl_b(Geo g, Fields<Real> f, Axial<Re
   curl_b_tile<Real, DIM, MM, kSeg, 1>(g, f.E1, f.E2, f.E3, f.B1, f.B2, f.B3, ax, e2, e3, l0, i2, i3, sB2, sB3);
 }
 
+// 3D: each workgroup takes one 256-cell x1 segment of one x2 row and marches
+// through kPlanes consecutive x3 planes, carrying the x3 neighbour it has
+// already loaded in registers (E at i3 + 1 becomes the next plane's own E for
+// the B update; B at i3 becomes the next plane's i3 - 1 for the E update), so
+// every array is read from HBM once per launch.
+constexpr int kPlanes = 8;
+
+__device__ __forceinline__ bool column_of(const Geo &g, int nseg, int &l0, int &i2, int &z0, int &z1) {
+  const int nz = (g.n3 + kPlanes - 1) / kPlanes;
+  const long long nb = (long long)nseg * g.n2 * nz;
+  const long long per = (nb + kNumXcd - 1) / kNumXcd;
+  const long long bid = blockIdx.x;
+  const long long lin = (bid % kNumXcd) * per + bid / kNumXcd;
+  if (lin >= nb) return false;
+  const int seg = (int)(lin % nseg);
+  const long long r = lin / nseg;
+  i2 = (int)(r % g.n2);
+  const int zc = (int)(r / g.n2);
+  l0 = seg * kSeg;
+  z0 = zc * kPlanes;
+  z1 = min(z0 + kPlanes, g.n3);
+  return true;
+}
+
+__host__ inline unsigned column_blocks(const Geo &g) {
+  const long long nseg = (g.n1 + kSeg - 1) / kSeg;
+  const long long nb = nseg * g.n2 * ((g.n3 + kPlanes - 1) / kPlanes);
+  const long long per = (nb + kNumXcd - 1) / kNumXcd;
+  return (unsigned)(per * kNumXcd);
+}
+
+// Bout = Bin - curl+ E, marching over x3 (coefficients as in curl_e_tile)
+template <typename Real, int MM>
+__global__ __launch_bounds__(kSeg) void k_curl_e_col(Geo g, Fields<Real> f, const Real *Bin1, const Real *Bin2,
+                                                     const Real *Bin3, Real *Bout1, Real *Bout2, Real *Bout3,
+                                                     Axial<Real> ax, Real h2, Real h3) {
+  __shared__ Real sE2[stage_pitch<kSeg>()], sE3[stage_pitch<kSeg>()];
+  int l0, i2, z0, z1;
+  if (!column_of(g, (g.n1 + kSeg - 1) / kSeg, l0, i2, z0, z1)) return;
+  const int M = MM > 0 ? MM : ax.M;
+  const int l1 = l0 + threadIdx.x;
+  const bool live = l1 < g.n1;
+  const int s1 = live ? col_near(g, l1) : -1;
+  const bool own = live && s1 >= 0;
+  const long long plane = (long long)g.n1 * g.n2;
+  const long long r2 = (long long)g.n1 * i2, r2p = (long long)g.n1 * wrap_near(i2 + 1, g.n2);
+  const int c = threadIdx.x + M - 1;  // LDS index of cell l1
+  Real e1 = own ? f.E1[r2 + plane * z0 + s1] : Real(0);
+  // the staged row (cells l0 - M + 1 .. l0 + 255 + M) is at most two values
+  // per thread and array; the next plane's values are loaded into registers
+  // while the current plane is computed
+  const int ta = threadIdx.x, tb = threadIdx.x + kSeg;
+  const bool hb = tb < kSeg + 2 * M;
+  const int ca = col_of(g, l0 - M + 1 + ta), cb = hb ? col_of(g, l0 - M + 1 + tb) : -1;
+  Real pa2 = ldc(f.E2, r2 + plane * z0, ca), pa3 = ldc(f.E3, r2 + plane * z0, ca);
+  Real pb2 = ldc(f.E2, r2 + plane * z0, cb), pb3 = ldc(f.E3, r2 + plane * z0, cb);
+  for (int i3 = z0; i3 < z1; ++i3) {
+    const long long row = r2 + plane * i3;
+    sE2[ta] = pa2;
+    sE3[ta] = pa3;
+    if (hb) {
+      sE2[tb] = pb2;
+      sE3[tb] = pb3;
+    }
+    __syncthreads();
+    if (i3 + 1 < z1) {
+      const long long nrow = row + plane;
+      pa2 = ldc(f.E2, nrow, ca);
+      pa3 = ldc(f.E3, nrow, ca);
+      pb2 = ldc(f.E2, nrow, cb);
+      pb3 = ldc(f.E3, nrow, cb);
+    }
+    if (own) {
+      const long long id = row + s1;
+      const long long up = r2 + plane * wrap_near(i3 + 1, g.n3) + s1;
+      const Real e1n = f.E1[up], e2n = f.E2[up];
+      Real d1E2 = 0, d1E3 = 0;
+      auto term = [&](int l) {
+        d1E2 += ax.c[l - 1] * (sE2[c + l] - sE2[c - l + 1]);
+        d1E3 += ax.c[l - 1] * (sE3[c + l] - sE3[c - l + 1]);
+      };
+      if (MM > 0) {
+#pragma unroll
+        for (int l = 1; l <= MM; ++l) term(l);
+      } else {
+        for (int l = 1; l <= M; ++l) term(l);
+      }
+      const long long id2 = r2p + plane * i3 + s1;
+      const Real e2 = sE2[c], e3 = sE3[c];
+      const Real d2E3 = h2 * (f.E3[id2] - e3);
+      const Real d2E1 = h2 * (f.E1[id2] - e1);
+      const Real d3E2 = h3 * (e2n - e2);
+      const Real d3E1 = h3 * (e1n - e1);
+      Bout1[id] = Bin1[id] - (d2E3 - d3E2);
+      Bout2[id] = Bin2[id] - (d3E1 - d1E3);
+      Bout3[id] = Bin3[id] - (d1E2 - d2E1);
+      e1 = e1n;
+    }
+    __syncthreads();
+  }
+}
+
+// E += curl- B, marching over x3 (coefficients as in curl_b_tile)
+template <typename Real, int MM>
+__global__ __launch_bounds__(kSeg) void k_curl_b_col(Geo g, Fields<Real> f, Axial<Real> ax, Real e2c, Real e3c) {
+  __shared__ Real sB2[stage_pitch<kSeg>()], sB3[stage_pitch<kSeg>()];
+  int l0, i2, z0, z1;
+  if (!column_of(g, (g.n1 + kSeg - 1) / kSeg, l0, i2, z0, z1)) return;
+  const int M = MM > 0 ? MM : ax.M;
+  const int l1 = l0 + threadIdx.x;
+  const bool live = l1 < g.n1;
+  const int s1 = live ? col_near(g, l1) : -1;
+  const bool own = live && s1 >= 0;
+  const long long plane = (long long)g.n1 * g.n2;
+  const long long r2 = (long long)g.n1 * i2, r2m = (long long)g.n1 * wrap_near(i2 - 1, g.n2);
+  const int c = threadIdx.x + M;  // LDS index of cell l1
+  Real b1m = Real(0), b2m = Real(0);
+  if (own) {
+    const long long dn = r2 + plane * wrap_near(z0 - 1, g.n3) + s1;
+    b1m = f.B1[dn];
+    b2m = f.B2[dn];
+  }
+  const int ta = threadIdx.x, tb = threadIdx.x + kSeg;
+  const bool hb = tb < kSeg + 2 * M;
+  const int ca = col_of(g, l0 - M + ta), cb = hb ? col_of(g, l0 - M + tb) : -1;
+  Real pa2 = ldc(f.B2, r2 + plane * z0, ca), pa3 = ldc(f.B3, r2 + plane * z0, ca);
+  Real pb2 = ldc(f.B2, r2 + plane * z0, cb), pb3 = ldc(f.B3, r2 + plane * z0, cb);
+  for (int i3 = z0; i3 < z1; ++i3) {
+    const long long row = r2 + plane * i3;
+    sB2[ta] = pa2;
+    sB3[ta] = pa3;
+    if (hb) {
+      sB2[tb] = pb2;
+      sB3[tb] = pb3;
+    }
+    __syncthreads();
+    if (i3 + 1 < z1) {
+      const long long nrow = row + plane;
+      pa2 = ldc(f.B2, nrow, ca);
+      pa3 = ldc(f.B3, nrow, ca);
+      pb2 = ldc(f.B2, nrow, cb);
+      pb3 = ldc(f.B3, nrow, cb);
+    }
+    if (own) {
+      const long long id = row + s1;
+      Real d1B3 = 0, d1B2 = 0;
+      auto term = [&](int l) {
+        d1B3 += ax.c[l - 1] * (sB3[c + l - 1] - sB3[c - l]);
+        d1B2 += ax.c[l - 1] * (sB2[c + l - 1] - sB2[c - l]);
+      };
+      if (MM > 0) {
+#pragma unroll
+        for (int l = 1; l <= MM; ++l) term(l);
+      } else {
+        for (int l = 1; l <= M; ++l) term(l);
+      }
+      const long long id2 = r2m + plane * i3 + s1;
+      const Real b1 = f.B1[id], b2 = sB2[c], b3 = sB3[c];
+      const Real d2B3 = e2c * (b3 - f.B3[id2]);
+      const Real d2B1 = e2c * (b1 - f.B1[id2]);
+      const Real d3B2 = e3c * (b2 - b2m);
+      const Real d3B1 = e3c * (b1 - b1m);
+      f.E1[id] += d2B3 - d3B2;
+      f.E2[id] += d3B1 - d1B3;
+      f.E3[id] += d1B2 - d2B1;
+      b1m = b1;
+      b2m = b2;
+    }
+    __syncthreads();
+  }
+}
+
 // E -= dt J over the box of deposited current (x1 widened by `pad` for the
 // J1 correction's spread), J cleared there; one thread resets the box used
 // by the next step's deposit.
@@ -115,6 +287,16 @@ __global__ void k_reset_box(JBox *b) {
 template <typename Real, int DIM>
 static void curl_e_dispatch(const Geo &g, const Fields<Real> &f, Real *const Bin[3], Real *const Bout[3],
                             const Axial<Real> &ax, Real h2, Real h3, hipStream_t st) {
+  if (DIM == 3) {
+    const unsigned nc = column_blocks(g);
+    if (ax.M == 1)
+      k_curl_e_col<Real, 1><<<nc, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, h3);
+    else if (ax.M == 16)
+      k_curl_e_col<Real, 16><<<nc, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, h3);
+    else
+      k_curl_e_col<Real, 0><<<nc, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, h3);
+    return;
+  }
   const unsigned nb = tile_blocks(g);
   if (ax.M == 1)
     k_curl_e<Real, DIM, 1><<<nb, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, h3);
@@ -127,6 +309,16 @@ static void curl_e_dispatch(const Geo &g, const Fields<Real> &f, Real *const Bin
 template <typename Real, int DIM>
 static void curl_b_dispatch(const Geo &g, const Fields<Real> &f, const Axial<Real> &ax, Real e2, Real e3,
                             hipStream_t st) {
+  if (DIM == 3) {
+    const unsigned nc = column_blocks(g);
+    if (ax.M == 1)
+      k_curl_b_col<Real, 1><<<nc, kSeg, 0, st>>>(g, f, ax, e2, e3);
+    else if (ax.M == 16)
+      k_curl_b_col<Real, 16><<<nc, kSeg, 0, st>>>(g, f, ax, e2, e3);
+    else
+      k_curl_b_col<Real, 0><<<nc, kSeg, 0, st>>>(g, f, ax, e2, e3);
+    return;
+  }
   const unsigned nb = tile_blocks(g);
   if (ax.M == 1)
     k_curl_b<Real, DIM, 1><<<nb, kSeg, 0, st>>>(g, f, ax, e2, e3);
