@@ -37,6 +37,36 @@ def algorithmic_bytes(kernel, ncells, npart, esz):
     return 0
 
 
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def push_flops_per_particle(ndim):
+    """Algorithmic floating-point operations of one particle's gather + Boris
+    push + move + charge-conserving quadratic deposit (multiply-add = 2),
+    counted from the method, not from the kernel's instructions:
+      shape weights    3 (2D: 2) axes x 2 staggerings x 3 quadratic weights x 6
+      gather           6 components, tensor-product interpolation over 3^d points
+                       (3D: 27*2 + 9*2 + 3*2 = 78 per component; 2D: 9*2 + 3*2 = 24)
+      Boris            75 (half kicks, gamma, t, s, two cross products, sqrt, divides)
+      move             4 per axis
+      deposit          1D shapes at x^n and x^{n+1} (2 x axes x 3 x 6), DS and running
+                       sums, transverse Esirkepov weights S0a P_b + DSa Q_b over the
+                       exact supports, one product and one add per current point
+                       (3D: 36 + 30 + 30 points; 2D: 12 + 10 + 15)."""
+    if ndim == 3:
+        shapes = 3 * 2 * 3 * 6
+        gather = 6 * 78
+        move = 3 * 4
+        deposit = 2 * 3 * 3 * 6 + 3 * 4 + 3 * 3 + 3 * 3 * 2 * 2 + (9 + 15 + 15) * 3 + (36 + 30 + 30) * 2
+    else:
+        shapes = 2 * 2 * 3 * 6
+        gather = 6 * 24
+        move = 2 * 4
+        deposit = 2 * 2 * 3 * 6 + 2 * 4 + 2 * 3 + 2 * 3 * 2 + (3 + 5 + 15) * 2 + (12 + 10 + 15) * 2
+    return shapes + gather + 75 + move + deposit
+
+
 def make_workload(args):
     from paper_1910_13529_amd import inputs
     n = tuple(int(v) for v in args.grid.split(","))
@@ -202,6 +232,60 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_main(args):
+    """Gradient of the field loss around a ballistic bunch (2D 1024 x 256,
+    2^16 particles, gamma = 1e4, 200 steps, M = 4, checkpoints every 20
+    steps): time per gradient (forward + backward) in FP32, and its error
+    against the FP64 adjoint."""
+    import numpy as np
+    import torch
+    from paper_1910_13529_amd import workloads
+    from paper_1910_13529_amd.relpic import Adjoint
+    w = workloads.adjoint_workload()
+    adj = {}
+    for prec in ("fp32", "fp64"):
+        a = Adjoint(w["grid"], w["C0"], w["nsteps"], w["box"], checkpoint_every=20, precision=prec)
+        a.load_particles(w["Q"], w["cell"], w["offset"], w["u"])
+        adj[prec] = a
+    a = adj["fp32"]
+    for _ in range(max(1, args.warmup // 10)):
+        a.forward(w["C0"])
+        a.backward()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 40)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        L = a.forward(w["C0"])
+        g = a.backward()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    L64 = adj["fp64"].forward(w["C0"])
+    g64 = adj["fp64"].backward()
+    ncells = w["grid"]["n"][0] * w["grid"]["n"][1]
+    out = {
+        "metric": "time per gradient (forward + adjoint) of the field loss in the axial coefficients",
+        "value": ms,
+        "unit": "ms",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "steps": w["nsteps"],
+        "repetitions": reps,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D 1024x256 periodic, dx=0.05, dt=0.0125, 65536 ballistic particles gamma=1e4, "
+                               "M=4 coefficients from the App. C fit, 200 steps, checkpoints every 20", "cells": ncells},
+        "cell_steps_per_s": ncells * w["nsteps"] * 3 / (ms * 1e-3),
+        "loss_fp32": L,
+        "loss_fp64": L64,
+        "grad_fp32": [float(v) for v in g],
+        "grad_fp64": [float(v) for v in g64],
+        "grad_rel_err_fp32_vs_fp64": float(np.abs(g - g64).max() / np.abs(g64).max()),
+    }
+    for k in adj:
+        adj[k].close()
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(args, w, cell, off, u, Q, solver):
     """The FP64 oracle on the host: a bounded sample of the same workload.
 
@@ -256,8 +340,9 @@ def main():
     ap.add_argument("--npart", type=int, default=1 << 22)
     ap.add_argument("--solvers", default="custom,yee")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="beam3d", choices=["beam3d", "batch"],
-                    help="beam3d: the 3D beam (default); batch: the 256-run batched workload")
+    ap.add_argument("--workload", default="beam3d", choices=["beam3d", "batch", "adjoint"],
+                    help="beam3d: the 3D beam (default); batch: the 256-run batched workload; "
+                         "adjoint: time per gradient of the differentiable case")
     ap.add_argument("--batch-solver", default="mixed", choices=["mixed", "yee", "custom"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
@@ -280,6 +365,9 @@ def main():
     if args.workload == "batch":
         batch_main(args)
         return
+    if args.workload == "adjoint":
+        adjoint_main(args)
+        return
     w, cell, off, u, Q = make_workload(args)
     ncells = int(math.prod(w.n))
     npart = len(cell)
@@ -297,13 +385,16 @@ def main():
     part_rate = npart * args.steps / r["wall_s"]
     step_bytes = ncells * 18 * esz + npart * 2 * (4 + 6 * esz)  # E, B read + written; particle state
 
-    # dominant kernel and its roofline
+    # dominant kernel and its roofline: the push is bound by instruction issue
+    # (ALU roofline, algorithmic flops), the field updates by HBM
     prof = r["prof"]
     dom = max((k for k in prof if prof[k][0] > 0), key=lambda k: prof[k][1])
     launches, tot = prof[dom]
     avg_ms = tot / launches
     alg = algorithmic_bytes(dom, ncells, npart, esz)
     achieved = alg / (avg_ms * 1e-3) / 1e9
+    flops = push_flops_per_particle(3) * npart
+    peak_alu = FP32_VECTOR_PEAK_TFLOPS if args.precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
@@ -340,7 +431,20 @@ def main():
             "particles": npart,
             "parallelism": "single GPU",
         },
-        "roofline": {
+        "roofline": ({
+            "bound": "alu",
+            "kernel": dom,
+            "achieved": flops / (avg_ms * 1e-3) / 1e12,
+            "peak": peak_alu,
+            "unit": "TFLOP/s",
+            "frac": flops / (avg_ms * 1e-3) / 1e12 / peak_alu,
+            "traffic": traffic,
+            "avg_launch_ms": avg_ms,
+            "algorithmic_flops_per_launch": flops,
+            "flops_per_particle": push_flops_per_particle(3),
+            "hbm_achieved_gbs": achieved,
+            "algorithmic_bytes_per_launch": alg,
+        } if dom == "push_deposit" else {
             "bound": "hbm",
             "kernel": dom,
             "achieved": achieved,
@@ -350,7 +454,14 @@ def main():
             "traffic": traffic,
             "avg_launch_ms": avg_ms,
             "algorithmic_bytes_per_launch": alg,
-        },
+        }),
+        "roofline_fields": {
+            k: {"bound": "hbm", "achieved": algorithmic_bytes(k, ncells, npart, esz) / (prof[k][1] / prof[k][0] * 1e-3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": algorithmic_bytes(k, ncells, npart, esz) / (prof[k][1] / prof[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "avg_launch_ms": prof[k][1] / prof[k][0],
+                "algorithmic_bytes_per_launch": algorithmic_bytes(k, ncells, npart, esz)}
+            for k in ("curl_e", "curl_b") if prof.get(k, (0, 0))[0] > 0},
         "kernel_ms_per_step": {k: prof[k][1] / r["nprof"] for k in prof if prof[k][0]},
         "diag": {k: r["diag"][k] for k in ("step", "window_start", "n_alive", "w_field", "w_kin", "error_word")},
     }

@@ -171,8 +171,10 @@ bool slots_match(const relpic_batch *b) {
 
 template <typename Real>
 relpic_status build_tiles(relpic_batch *b) {
+  // tiles in run order: the XCD bands then cut the table into contiguous
+  // ranges with a balanced mix of cheap (Yee) and costly (customized) runs
   std::vector<BatchTile> t;
-  for (size_t r = 0; r < b->runs.size(); ++r) {
+  for (int r = 0; r < (int)b->runs.size(); ++r) {
     const relpic_sim *s = b->runs[r];
     const int seg = kShapeSeg[b->shape[r]], rows = kShapeRows[b->shape[r]];
     for (int i2 = 0; i2 < s->n[1]; i2 += rows)

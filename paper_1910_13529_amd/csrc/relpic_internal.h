@@ -54,7 +54,9 @@ __device__ __forceinline__ int col_of(const Geo &g, int l) {
     int s = l + g.ws_mod;
     return s >= g.n1 ? s - g.n1 : s;
   }
-  int s = (l + g.ws_mod) % g.n1;
+  int s = l + g.ws_mod;
+  if (s >= -g.n1 && s < 2 * g.n1) return s < 0 ? s + g.n1 : (s >= g.n1 ? s - g.n1 : s);
+  s %= g.n1;  // far outside: general wrap
   return s < 0 ? s + g.n1 : s;
 }
 
