@@ -236,10 +236,9 @@ relpic_status relpic_profile_read(relpic_sim *sim, relpic_profile *out);
  * batch notices and rebuilds its tables at its next step.  Runs may not use
  * plasma injection.
  *
- * Field kernels work on tiles of SEG x1 cells times ROWS x2 rows (256
- * threads): shape 0 = 256 x 1, 1 = 128 x 2, 2 = 64 x 4, chosen per run.  The
- * default gives every run the shape with the fewest tiles;
- * relpic_batch_autotune measures and picks. */
+ * Field kernels work on tiles of 128 x1 cells (one thread each) that march
+ * through a range of x2 rows: shape 0, 1, 2 = 4, 8, 16 rows per tile, chosen
+ * per run.  The default is 8 rows; relpic_batch_autotune measures and picks. */
 typedef struct relpic_batch relpic_batch;
 
 /* Create nruns runs from grids[nruns] and solvers[nruns] (NULL: all Yee),
@@ -277,7 +276,7 @@ relpic_status relpic_batch_get_tiling(relpic_batch *batch, int *shape, int *grid
 typedef struct {
   double ms_uniform[3];    /* every run on shape 0, 1, 2; one workgroup per tile */
   double ms_model;         /* per-run shapes from the fitted per-tile cost of each shape */
-  double ms_persistent[2]; /* best assignment on 2048 and 4096 persistent workgroups (0: not tried) */
+  double ms_persistent[2]; /* best assignment on 4096 and 8192 persistent workgroups (0: not tried) */
   double ms_chosen;
   int choice;              /* 0..2: uniform shape, 3: per-run model */
   int grid_workgroups;     /* field-kernel grid chosen */

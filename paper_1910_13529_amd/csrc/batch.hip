@@ -126,18 +126,13 @@ int bits_for(long long v) {  // smallest k with 2^k > v
 }
 
 long long shape_tiles(const relpic_sim *s, int shape) {
-  const long long nseg = (s->n[0] + kShapeSeg[shape] - 1) / kShapeSeg[shape];
+  const long long nseg = (s->n[0] + kBatchSeg - 1) / kBatchSeg;
   const long long nrow = (s->n[1] + kShapeRows[shape] - 1) / kShapeRows[shape];
   return nseg * nrow;
 }
 
-// shape with the fewest tiles (ties: the longest x1 segment)
-int fewest_tiles_shape(const relpic_sim *s) {
-  int best = 0;
-  for (int k = 1; k < kNumShapes; ++k)
-    if (shape_tiles(s, k) < shape_tiles(s, best)) best = k;
-  return best;
-}
+// default tile shape before any autotuning: the middle row count
+constexpr int kDefaultShape = 1;
 
 // state of the sub-simulations that the device tables depend on
 std::vector<const void *> signature(const relpic_batch *b) {
@@ -176,9 +171,11 @@ relpic_status build_tiles(relpic_batch *b) {
   std::vector<BatchTile> t;
   for (int r = 0; r < (int)b->runs.size(); ++r) {
     const relpic_sim *s = b->runs[r];
-    const int seg = kShapeSeg[b->shape[r]], rows = kShapeRows[b->shape[r]];
-    for (int i2 = 0; i2 < s->n[1]; i2 += rows)
-      for (int l0 = 0; l0 < s->n[0]; l0 += seg) t.push_back(BatchTile{(int)r, l0, i2, 0});
+    const int rows = kShapeRows[b->shape[r]];
+    for (int r0 = 0; r0 < s->n[1]; r0 += rows) {
+      const int r1 = std::min(r0 + rows, (int)s->n[1]);
+      for (int l0 = 0; l0 < s->n[0]; l0 += kBatchSeg) t.push_back(BatchTile{r, l0, r0, r1});
+    }
   }
   if (t.size() >= (size_t)INT32_MAX / 2) return fail(RELPIC_EINVAL, "batch: too many field tiles");
   if (!ensure(b, b->d_tiles, b->tiles_cap, t.size())) return fail(RELPIC_ENOMEM, "batch: tile table allocation failed");
@@ -540,7 +537,7 @@ relpic_status do_autotune(relpic_batch *b, int reps, relpic_batch_tune *out) {
   b->shape = best_shape;
   if (relpic_status e = build_tiles<Real>(b)) return e;
   int best_grid = 0;
-  const int grids[2] = {256 * 8, 256 * 16};
+  const int grids[2] = {256 * 16, 256 * 32};
   for (int k = 0; k < 2; ++k) {
     if (grids[k] >= b->ntiles) continue;
     b->grid_wg = grids[k];
@@ -602,7 +599,7 @@ relpic_status relpic_batch_create(int nruns, const relpic_grid *grids, const rel
       return fail(e, msg);
     }
     b->runs.push_back(s);
-    b->shape.push_back(fewest_tiles_shape(s));
+    b->shape.push_back(kDefaultShape);
   }
   *out = b;
   return RELPIC_OK;

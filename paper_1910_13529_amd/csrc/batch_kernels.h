@@ -8,11 +8,11 @@
 
 namespace relpic {
 
-// Tile shapes of the field kernels: SEG cells along x1 times ROWS rows of x2,
-// 256 threads each.
+// Field tiles: a kBatchSeg-cell x1 segment (one thread per cell) marching
+// through kShapeRows[shape] consecutive x2 rows.
+constexpr int kBatchSeg = 128;
 constexpr int kNumShapes = 3;
-constexpr int kShapeSeg[kNumShapes] = {256, 128, 64};
-constexpr int kShapeRows[kNumShapes] = {1, 2, 4};
+constexpr int kShapeRows[kNumShapes] = {4, 8, 16};
 
 // Per-run constants and device pointers (one entry per run).
 template <typename Real>
@@ -42,7 +42,7 @@ struct BatchPart {
 };
 
 struct BatchTile {
-  int run, l0, i2, pad_;
+  int run, l0, r0, r1;  // x1 segment start, rows r0 .. r1 - 1
 };
 
 struct BatchChunk {
@@ -50,8 +50,8 @@ struct BatchChunk {
 };
 
 // Field tables selected per launch: which = 0 full step, 1 the -dt/2
-// half step, 2 the +dt/2 half step.  Bout = Bin - curl+ E with Bin = slot
-// `bin` and Bout = slot 1 - bin.
+// half step, 2 the +dt/2 half step; workgroups of kBatchSeg threads.
+// Bout = Bin - curl+ E with Bin = slot `bin` and Bout = slot 1 - bin.
 template <typename Real>
 void launch_batch_curl_e(const BatchRun<Real> *runs, const BatchTile *tiles, int ntiles, int grid, int bin, int which,
                          hipStream_t st);

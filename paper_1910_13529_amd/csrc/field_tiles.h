@@ -14,146 +14,140 @@ __device__ __forceinline__ Real ldc(const Real *f, long long row, int col) {
   return col >= 0 ? f[row + col] : Real(0);
 }
 
-// Workgroup -> (x1 segment, i2, i3), XCD-contiguous.  Returns false for the
-// padding workgroups of the last band.
-__device__ __forceinline__ bool tile_of(const Geo &g, int nseg, int &l0, int &i2, int &i3) {
-  const long long nb = (long long)nseg * g.n2 * g.n3;
-  const long long per = (nb + kNumXcd - 1) / kNumXcd;
-  const long long bid = blockIdx.x;
-  const long long lin = (bid % kNumXcd) * per + bid / kNumXcd;
-  if (lin >= nb) return false;
-  const int seg = (int)(lin % nseg);
-  const long long r = lin / nseg;
-  i2 = (int)(r % g.n2);
-  i3 = (int)(r / g.n2);
-  l0 = seg * kSeg;
-  return true;
-}
-
-__host__ __device__ inline unsigned tile_blocks(const Geo &g) {
-  const long long nseg = (g.n1 + kSeg - 1) / kSeg;
-  const long long nb = nseg * g.n2 * g.n3;
-  const long long per = (nb + kNumXcd - 1) / kNumXcd;
-  return (unsigned)(per * kNumXcd);
-}
-
 // LDS pitch of one staged row of a SEG-cell tile (cells plus the axial halo)
 template <int SEG>
 constexpr int stage_pitch() {
   return SEG + 2 * kMaxM;
 }
 
-// Bout = Bin - curl+ E on a tile of ROWS x1-segments [l0, l0 + SEG) of rows
-// i2 .. i2 + ROWS - 1 (those below n2) in plane i3; blockDim.x == SEG * ROWS,
-// thread t takes cell l0 + t % SEG of row i2 + t / SEG.  Coefficients carry
-// the time factor: ax.c[l] = C_l c / dx1, h2 = c / dx2, h3 = c / dx3.  sE2,
-// sE3: LDS of ROWS * stage_pitch<SEG>() values.  Contains one barrier that
-// every thread of the workgroup reaches.
-template <typename Real, int DIM, int MM, int SEG, int ROWS>
-__device__ __forceinline__ void curl_e_tile(const Geo &g, const Real *E1, const Real *E2, const Real *E3,
+// 2D updates that march along x2: one x1 segment [l0, l0 + SEG) of rows
+// r0 .. r1 - 1, one thread per x1 cell (blockDim.x == SEG).  The x2
+// neighbour the previous row already loaded is carried in registers (E at
+// i2 + 1 becomes the next row's own E for the B update; B at i2 becomes the
+// next row's i2 - 1 for the E update), and the next row's staged x1 segment
+// is loaded while the current row is computed.  Every barrier is reached by
+// all threads.  The LDS arguments hold stage_pitch<SEG>() values each.
+
+// Bout = Bin - curl+ E (2D; ax.c[l] = C_l c / dx1, h2 = c / dx2)
+template <typename Real, int MM, int SEG>
+__device__ __forceinline__ void curl_e_rows(const Geo &g, const Real *E1, const Real *E2, const Real *E3,
                                             const Real *Bin1, const Real *Bin2, const Real *Bin3, Real *Bout1,
-                                            Real *Bout2, Real *Bout3, const Axial<Real> &ax, Real h2, Real h3, int l0,
-                                            int i2, int i3, Real *sE2, Real *sE3) {
+                                            Real *Bout2, Real *Bout3, const Axial<Real> &ax, Real h2, int l0, int r0,
+                                            int r1, Real *sE2, Real *sE3) {
   const int M = MM > 0 ? MM : ax.M;
-  const int tx = ROWS == 1 ? (int)threadIdx.x : (int)threadIdx.x % SEG;
-  const int ty = ROWS == 1 ? 0 : (int)threadIdx.x / SEG;
-  i2 += ty;
-  const bool live_row = ROWS == 1 || i2 < g.n2;
-  sE2 += ty * stage_pitch<SEG>();
-  sE3 += ty * stage_pitch<SEG>();
-  const long long row = (long long)g.n1 * (i2 + (long long)g.n2 * i3);
-  // stage E2, E3 on window cells [l0 - M + 1, l0 + SEG + M)
-  const int span = SEG + 2 * M;
-  if (live_row)
-    for (int t = tx; t < span; t += SEG) {
-      const int col = col_of(g, l0 - M + 1 + t);
-      sE2[t] = ldc(E2, row, col);
-      sE3[t] = ldc(E3, row, col);
+  const int l1 = l0 + (int)threadIdx.x;
+  const int s1 = l1 < g.n1 ? col_near(g, l1) : -1;
+  const bool own = s1 >= 0;
+  const int c = (int)threadIdx.x + M - 1;  // LDS index of cell l1
+  const int ta = threadIdx.x, tb = threadIdx.x + SEG;
+  const bool hb = tb < SEG + 2 * M;
+  const int ca = col_of(g, l0 - M + 1 + ta), cb = hb ? col_of(g, l0 - M + 1 + tb) : -1;
+  long long row = (long long)g.n1 * r0;
+  Real pa2 = ldc(E2, row, ca), pa3 = ldc(E3, row, ca), pb2 = ldc(E2, row, cb), pb3 = ldc(E3, row, cb);
+  Real e1 = own ? E1[row + s1] : Real(0);
+  for (int i2 = r0; i2 < r1; ++i2) {
+    sE2[ta] = pa2;
+    sE3[ta] = pa3;
+    if (hb) {
+      sE2[tb] = pb2;
+      sE3[tb] = pb3;
     }
-  __syncthreads();
-  const int l1 = l0 + tx;
-  if (!live_row || l1 >= g.n1) return;
-  const int s1 = col_near(g, l1);
-  const long long id = row + s1;
-  const int c = tx + M - 1;  // LDS index of cell l1
-  Real d1E2 = 0, d1E3 = 0;
-  auto term = [&](int l) {
-    d1E2 += ax.c[l - 1] * (sE2[c + l] - sE2[c - l + 1]);
-    d1E3 += ax.c[l - 1] * (sE3[c + l] - sE3[c - l + 1]);
-  };
-  if (MM > 0) {
+    __syncthreads();
+    const long long rowp = (long long)g.n1 * wrap_near(i2 + 1, g.n2);
+    if (i2 + 1 < r1) {
+      pa2 = ldc(E2, rowp, ca);
+      pa3 = ldc(E3, rowp, ca);
+      pb2 = ldc(E2, rowp, cb);
+      pb3 = ldc(E3, rowp, cb);
+    }
+    if (own) {
+      const long long id = row + s1, up = rowp + s1;
+      const Real e1n = E1[up], e3n = E3[up];
+      Real d1E2 = 0, d1E3 = 0;
+      auto term = [&](int l) {
+        d1E2 += ax.c[l - 1] * (sE2[c + l] - sE2[c - l + 1]);
+        d1E3 += ax.c[l - 1] * (sE3[c + l] - sE3[c - l + 1]);
+      };
+      if (MM > 0) {
 #pragma unroll
-    for (int l = 1; l <= MM; ++l) term(l);
-  } else {
-    for (int l = 1; l <= M; ++l) term(l);
+        for (int l = 1; l <= MM; ++l) term(l);
+      } else {
+        for (int l = 1; l <= M; ++l) term(l);
+      }
+      const Real e3 = sE3[c];
+      const Real d2E3 = h2 * (e3n - e3);
+      const Real d2E1 = h2 * (e1n - e1);
+      Bout1[id] = Bin1[id] - d2E3;
+      Bout2[id] = Bin2[id] + d1E3;
+      Bout3[id] = Bin3[id] - (d1E2 - d2E1);
+      e1 = e1n;
+    }
+    __syncthreads();
+    row = rowp;
   }
-  const long long row2p = (long long)g.n1 * (wrap_near(i2 + 1, g.n2) + (long long)g.n2 * i3);
-  const Real e1 = E1[id], e2 = sE2[c], e3 = sE3[c];
-  const Real d2E3 = h2 * (E3[row2p + s1] - e3);
-  const Real d2E1 = h2 * (E1[row2p + s1] - e1);
-  Real d3E2 = 0, d3E1 = 0;
-  if (DIM == 3) {
-    const long long row3p = (long long)g.n1 * (i2 + (long long)g.n2 * wrap_near(i3 + 1, g.n3));
-    d3E2 = h3 * (E2[row3p + s1] - e2);
-    d3E1 = h3 * (E1[row3p + s1] - e1);
-  }
-  Bout1[id] = Bin1[id] - (d2E3 - d3E2);
-  Bout2[id] = Bin2[id] - (d3E1 - d1E3);
-  Bout3[id] = Bin3[id] - (d1E2 - d2E1);
 }
 
-// E += curl- B on a tile laid out as in curl_e_tile (ax.c[l] = C_l dt / dx1;
-// e2 = dt / dx2; e3 = dt / dx3).  sB2, sB3: LDS of ROWS * stage_pitch<SEG>().
-template <typename Real, int DIM, int MM, int SEG, int ROWS>
-__device__ __forceinline__ void curl_b_tile(const Geo &g, Real *E1, Real *E2, Real *E3, const Real *B1,
-                                            const Real *B2, const Real *B3, const Axial<Real> &ax, Real e2, Real e3,
-                                            int l0, int i2, int i3, Real *sB2, Real *sB3) {
+// E += curl- B (2D; ax.c[l] = C_l dt / dx1, e2 = dt / dx2)
+template <typename Real, int MM, int SEG>
+__device__ __forceinline__ void curl_b_rows(const Geo &g, Real *E1, Real *E2, Real *E3, const Real *B1,
+                                            const Real *B2, const Real *B3, const Axial<Real> &ax, Real e2, int l0,
+                                            int r0, int r1, Real *sB2, Real *sB3) {
   const int M = MM > 0 ? MM : ax.M;
-  const int tx = ROWS == 1 ? (int)threadIdx.x : (int)threadIdx.x % SEG;
-  const int ty = ROWS == 1 ? 0 : (int)threadIdx.x / SEG;
-  i2 += ty;
-  const bool live_row = ROWS == 1 || i2 < g.n2;
-  sB2 += ty * stage_pitch<SEG>();
-  sB3 += ty * stage_pitch<SEG>();
-  const long long row = (long long)g.n1 * (i2 + (long long)g.n2 * i3);
-  // stage B2, B3 on window cells [l0 - M, l0 + SEG + M)
-  const int span = SEG + 2 * M;
-  if (live_row)
-    for (int t = tx; t < span; t += SEG) {
-      const int col = col_of(g, l0 - M + t);
-      sB2[t] = ldc(B2, row, col);
-      sB3[t] = ldc(B3, row, col);
+  const int l1 = l0 + (int)threadIdx.x;
+  const int s1 = l1 < g.n1 ? col_near(g, l1) : -1;
+  const bool own = s1 >= 0;
+  const int c = (int)threadIdx.x + M;  // LDS index of cell l1
+  const int ta = threadIdx.x, tb = threadIdx.x + SEG;
+  const bool hb = tb < SEG + 2 * M;
+  const int ca = col_of(g, l0 - M + ta), cb = hb ? col_of(g, l0 - M + tb) : -1;
+  long long row = (long long)g.n1 * r0;
+  Real pa2 = ldc(B2, row, ca), pa3 = ldc(B3, row, ca), pb2 = ldc(B2, row, cb), pb3 = ldc(B3, row, cb);
+  Real b1m = Real(0), b3m = Real(0);
+  if (own) {
+    const long long dn = (long long)g.n1 * wrap_near(r0 - 1, g.n2) + s1;
+    b1m = B1[dn];
+    b3m = B3[dn];
+  }
+  for (int i2 = r0; i2 < r1; ++i2) {
+    sB2[ta] = pa2;
+    sB3[ta] = pa3;
+    if (hb) {
+      sB2[tb] = pb2;
+      sB3[tb] = pb3;
     }
-  __syncthreads();
-  const int l1 = l0 + tx;
-  if (!live_row || l1 >= g.n1) return;
-  const int s1 = col_near(g, l1);
-  const long long id = row + s1;
-  const int c = tx + M;  // LDS index of cell l1
-  Real d1B3 = 0, d1B2 = 0;
-  auto term = [&](int l) {
-    d1B3 += ax.c[l - 1] * (sB3[c + l - 1] - sB3[c - l]);
-    d1B2 += ax.c[l - 1] * (sB2[c + l - 1] - sB2[c - l]);
-  };
-  if (MM > 0) {
+    __syncthreads();
+    const long long rowp = (long long)g.n1 * wrap_near(i2 + 1, g.n2);
+    if (i2 + 1 < r1) {
+      pa2 = ldc(B2, rowp, ca);
+      pa3 = ldc(B3, rowp, ca);
+      pb2 = ldc(B2, rowp, cb);
+      pb3 = ldc(B3, rowp, cb);
+    }
+    if (own) {
+      const long long id = row + s1;
+      Real d1B3 = 0, d1B2 = 0;
+      auto term = [&](int l) {
+        d1B3 += ax.c[l - 1] * (sB3[c + l - 1] - sB3[c - l]);
+        d1B2 += ax.c[l - 1] * (sB2[c + l - 1] - sB2[c - l]);
+      };
+      if (MM > 0) {
 #pragma unroll
-    for (int l = 1; l <= MM; ++l) term(l);
-  } else {
-    for (int l = 1; l <= M; ++l) term(l);
+        for (int l = 1; l <= MM; ++l) term(l);
+      } else {
+        for (int l = 1; l <= M; ++l) term(l);
+      }
+      const Real b1 = B1[id], b3 = sB3[c];
+      const Real d2B3 = e2 * (b3 - b3m);
+      const Real d2B1 = e2 * (b1 - b1m);
+      E1[id] += d2B3;
+      E2[id] -= d1B3;
+      E3[id] += d1B2 - d2B1;
+      b1m = b1;
+      b3m = b3;
+    }
+    __syncthreads();
+    row = rowp;
   }
-  const long long row2m = (long long)g.n1 * (wrap_near(i2 - 1, g.n2) + (long long)g.n2 * i3);
-  const Real b1 = B1[id], b2 = sB2[c], b3 = sB3[c];
-  const Real d2B3 = e2 * (b3 - B3[row2m + s1]);
-  const Real d2B1 = e2 * (b1 - B1[row2m + s1]);
-  Real d3B2 = 0, d3B1 = 0;
-  if (DIM == 3) {
-    const long long row3m = (long long)g.n1 * (i2 + (long long)g.n2 * wrap_near(i3 - 1, g.n3));
-    d3B2 = e3 * (b2 - B2[row3m + s1]);
-    d3B1 = e3 * (b1 - B1[row3m + s1]);
-  }
-  E1[id] += d2B3 - d3B2;
-  E2[id] += d3B1 - d1B3;
-  E3[id] += d1B2 - d2B1;
 }
 
 // Window-cell range of the deposit box along x1 widened by pad (clamped to

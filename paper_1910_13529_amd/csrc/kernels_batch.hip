@@ -1,5 +1,5 @@
 // Batched many-run kernels.  Each launch covers every run of the batch: the
-// field kernels walk a table of (run, x1 segment, first row) tiles, the
+// field kernels walk a table of (run, x1 segment, row range) tiles, the
 // particle kernel a table of (run species, chunk) entries, and the small
 // per-box kernels take a fixed number of workgroups per run.  The per-tile
 // and per-chunk work is the device code of the single-run kernels, so a run
@@ -10,8 +10,7 @@
 
 namespace relpic {
 
-constexpr int kStage = 4 * stage_pitch<64>();  // largest staged tile (64 x 4)
-static_assert(kStage >= stage_pitch<256>() && kStage >= 2 * stage_pitch<128>(), "stage buffer too small");
+constexpr int kStage = stage_pitch<kBatchSeg>();
 constexpr int kBoxWorkgroups = 4;  // workgroups per run of the deposit-box kernels
 
 // The tiles [band * per, (band + 1) * per) of the table go to the workgroups
@@ -26,84 +25,52 @@ __device__ __forceinline__ void band_range(int ntiles, int &first, int &end, int
   step = (int)(gridDim.x / kNumXcd);
 }
 
-template <typename Real, int MM>
-__device__ __forceinline__ void batch_curl_e_tile(const BatchRun<Real> &r, const BatchTile &tl, int bin, int which,
-                                                  Real *s2, Real *s3) {
-  Real *const *Bi = r.B[bin];
-  Real *const *Bo = r.B[bin ^ 1];
-  const Axial<Real> &ax = r.ax[which];
-  const Real h2 = r.h2[which];
-  switch (r.shape) {
-    case 0:
-      curl_e_tile<Real, 2, MM, 256, 1>(r.g, r.E1, r.E2, r.E3, Bi[0], Bi[1], Bi[2], Bo[0], Bo[1], Bo[2], ax, h2,
-                                       Real(0), tl.l0, tl.i2, 0, s2, s3);
-      break;
-    case 1:
-      curl_e_tile<Real, 2, MM, 128, 2>(r.g, r.E1, r.E2, r.E3, Bi[0], Bi[1], Bi[2], Bo[0], Bo[1], Bo[2], ax, h2,
-                                       Real(0), tl.l0, tl.i2, 0, s2, s3);
-      break;
-    default:
-      curl_e_tile<Real, 2, MM, 64, 4>(r.g, r.E1, r.E2, r.E3, Bi[0], Bi[1], Bi[2], Bo[0], Bo[1], Bo[2], ax, h2,
-                                      Real(0), tl.l0, tl.i2, 0, s2, s3);
-  }
-}
-
-template <typename Real, int MM>
-__device__ __forceinline__ void batch_curl_b_tile(const BatchRun<Real> &r, const BatchTile &tl, int bsel, Real *s2,
-                                                  Real *s3) {
-  Real *const *B = r.B[bsel];
-  switch (r.shape) {
-    case 0:
-      curl_b_tile<Real, 2, MM, 256, 1>(r.g, r.E1, r.E2, r.E3, B[0], B[1], B[2], r.ax[0], r.h2[0], Real(0), tl.l0,
-                                       tl.i2, 0, s2, s3);
-      break;
-    case 1:
-      curl_b_tile<Real, 2, MM, 128, 2>(r.g, r.E1, r.E2, r.E3, B[0], B[1], B[2], r.ax[0], r.h2[0], Real(0), tl.l0,
-                                       tl.i2, 0, s2, s3);
-      break;
-    default:
-      curl_b_tile<Real, 2, MM, 64, 4>(r.g, r.E1, r.E2, r.E3, B[0], B[1], B[2], r.ax[0], r.h2[0], Real(0), tl.l0,
-                                      tl.i2, 0, s2, s3);
-  }
-}
-
 template <typename Real>
-__global__ __launch_bounds__(256) void k_batch_curl_e(const BatchRun<Real> *__restrict__ runs,
-                                                      const BatchTile *__restrict__ tiles, int ntiles, int bin,
-                                                      int which) {
+__global__ __launch_bounds__(kBatchSeg) void k_batch_curl_e(const BatchRun<Real> *__restrict__ runs,
+                                                            const BatchTile *__restrict__ tiles, int ntiles, int bin,
+                                                            int which) {
   __shared__ Real s2[kStage], s3[kStage];
   int t, end, step;
   band_range(ntiles, t, end, step);
   for (; t < end; t += step) {
     const BatchTile tl = tiles[t];
     const BatchRun<Real> &r = runs[tl.run];
-    // the branch is uniform over the workgroup
+    Real *const *Bi = r.B[bin];
+    Real *const *Bo = r.B[bin ^ 1];
+    const Axial<Real> &ax = r.ax[which];
+    // the branch is uniform over the workgroup; each call ends with a barrier
     if (r.M == 1)
-      batch_curl_e_tile<Real, 1>(r, tl, bin, which, s2, s3);
+      curl_e_rows<Real, 1, kBatchSeg>(r.g, r.E1, r.E2, r.E3, Bi[0], Bi[1], Bi[2], Bo[0], Bo[1], Bo[2], ax,
+                                      r.h2[which], tl.l0, tl.r0, tl.r1, s2, s3);
     else if (r.M == 16)
-      batch_curl_e_tile<Real, 16>(r, tl, bin, which, s2, s3);
+      curl_e_rows<Real, 16, kBatchSeg>(r.g, r.E1, r.E2, r.E3, Bi[0], Bi[1], Bi[2], Bo[0], Bo[1], Bo[2], ax,
+                                       r.h2[which], tl.l0, tl.r0, tl.r1, s2, s3);
     else
-      batch_curl_e_tile<Real, 0>(r, tl, bin, which, s2, s3);
-    __syncthreads();  // the next tile restages the LDS rows
+      curl_e_rows<Real, 0, kBatchSeg>(r.g, r.E1, r.E2, r.E3, Bi[0], Bi[1], Bi[2], Bo[0], Bo[1], Bo[2], ax,
+                                      r.h2[which], tl.l0, tl.r0, tl.r1, s2, s3);
   }
 }
 
 template <typename Real>
-__global__ __launch_bounds__(256) void k_batch_curl_b(const BatchRun<Real> *__restrict__ runs,
-                                                      const BatchTile *__restrict__ tiles, int ntiles, int bsel) {
+__global__ __launch_bounds__(kBatchSeg) void k_batch_curl_b(const BatchRun<Real> *__restrict__ runs,
+                                                            const BatchTile *__restrict__ tiles, int ntiles,
+                                                            int bsel) {
   __shared__ Real s2[kStage], s3[kStage];
   int t, end, step;
   band_range(ntiles, t, end, step);
   for (; t < end; t += step) {
     const BatchTile tl = tiles[t];
     const BatchRun<Real> &r = runs[tl.run];
+    Real *const *B = r.B[bsel];
     if (r.M == 1)
-      batch_curl_b_tile<Real, 1>(r, tl, bsel, s2, s3);
+      curl_b_rows<Real, 1, kBatchSeg>(r.g, r.E1, r.E2, r.E3, B[0], B[1], B[2], r.ax[0], r.h2[0], tl.l0, tl.r0, tl.r1,
+                                      s2, s3);
     else if (r.M == 16)
-      batch_curl_b_tile<Real, 16>(r, tl, bsel, s2, s3);
+      curl_b_rows<Real, 16, kBatchSeg>(r.g, r.E1, r.E2, r.E3, B[0], B[1], B[2], r.ax[0], r.h2[0], tl.l0, tl.r0,
+                                       tl.r1, s2, s3);
     else
-      batch_curl_b_tile<Real, 0>(r, tl, bsel, s2, s3);
-    __syncthreads();
+      curl_b_rows<Real, 0, kBatchSeg>(r.g, r.E1, r.E2, r.E3, B[0], B[1], B[2], r.ax[0], r.h2[0], tl.l0, tl.r0, tl.r1,
+                                      s2, s3);
   }
 }
 
@@ -252,13 +219,13 @@ __global__ void k_batch_copy_back(const BatchPart<Real> *__restrict__ parts, int
 template <typename Real>
 void launch_batch_curl_e(const BatchRun<Real> *runs, const BatchTile *tiles, int ntiles, int grid, int bin, int which,
                          hipStream_t st) {
-  k_batch_curl_e<Real><<<grid, 256, 0, st>>>(runs, tiles, ntiles, bin, which);
+  k_batch_curl_e<Real><<<grid, kBatchSeg, 0, st>>>(runs, tiles, ntiles, bin, which);
 }
 
 template <typename Real>
 void launch_batch_curl_b(const BatchRun<Real> *runs, const BatchTile *tiles, int ntiles, int grid, int bsel,
                          hipStream_t st) {
-  k_batch_curl_b<Real><<<grid, 256, 0, st>>>(runs, tiles, ntiles, bsel);
+  k_batch_curl_b<Real><<<grid, kBatchSeg, 0, st>>>(runs, tiles, ntiles, bsel);
 }
 
 template <typename Real>

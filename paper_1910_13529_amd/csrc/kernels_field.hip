@@ -7,31 +7,61 @@
 //   E^{n+1}   = E^n + dt d- x B^{n+1/2}                    (k_curl_b)
 //   E^{n+1}  -= dt J^{n+1/2} inside the deposit's box       (k_add_j)
 // which is the leapfrog of the split B half steps; the gather takes
-// B^n = (B^{n-1/2} + B^{n+1/2}) / 2.  Each launch maps one workgroup to a
-// 256-cell segment of one x1 row; the row and its 2M-cell halo are staged
-// in LDS for the axial stencil, and workgroups are renumbered so that each
-// XCD sweeps a contiguous band of rows (neighbouring rows share its L2).
+// B^n = (B^{n-1/2} + B^{n+1/2}) / 2.  Each workgroup takes a 256-cell x1
+// segment and marches through consecutive rows (2D: x2) or planes (3D: x3),
+// staging each row and its 2M-cell halo in LDS for the axial stencil;
+// workgroups are renumbered so that each XCD sweeps a contiguous band of
+// rows (neighbouring rows share its L2).
 #include "field_tiles.h"
 
 namespace relpic {
 
-template <typename Real, int DIM, int MM>
-__global__ __launch_bounds__(kSeg) void k_curl_e(Geo g, Fields<Real> f, const Real *Bin1, const Real *Bin2,
-                                                 const Real *Bin3, Real *Bout1, Real *Bout2, Real *Bout3,
-                                                 Axial<Real> ax, Real h2, Real h3) {
-  __shared__ Real sE2[stage_pitch<kSeg>()], sE3[stage_pitch<kSeg>()];
-  int l0, i2, i3;
-  if (!tile_of(g, (g.n1 + kSeg - 1) / kSeg, l0, i2, i3)) return;
-  curl_e_tile<Real, DIM, MM, kSeg, 1>(g, f.E1, f.E2, f.E3, Bin1, Bin2, Bin3, Bout1, Bout2, Bout3, ax, h2, h3, l0, i2, i3,
-                                   sE2, sE3);
+// 2D: each workgroup takes one 256-cell x1 segment and marches through
+// `rows` consecutive x2 rows (curl_e_rows / curl_b_rows); rows shrinks on
+// small grids so that the launch still has about 2048 workgroups.
+constexpr int kMaxRows = 8;
+
+__host__ inline int rows_per_tile(const Geo &g) {
+  const long long nseg = (g.n1 + kSeg - 1) / kSeg;
+  const long long r = nseg * g.n2 / 2048;
+  return (int)(r < 1 ? 1 : (r > kMaxRows ? kMaxRows : r));
 }
 
-template <typename Real, int DIM, int MM>
-__global__ __launch_bounds__(kSeg) void k_curl_b(Geo g, Fields<Real> f, Axial<Real> ax, Real e2, Real e3) {
+__device__ __forceinline__ bool rows_of(const Geo &g, int nseg, int rows, int &l0, int &r0, int &r1) {
+  const int nr = (g.n2 + rows - 1) / rows;
+  const long long nb = (long long)nseg * nr;
+  const long long per = (nb + kNumXcd - 1) / kNumXcd;
+  const long long bid = blockIdx.x;
+  const long long lin = (bid % kNumXcd) * per + bid / kNumXcd;
+  if (lin >= nb) return false;
+  l0 = (int)(lin % nseg) * kSeg;
+  r0 = (int)(lin / nseg) * rows;
+  r1 = min(r0 + rows, g.n2);
+  return true;
+}
+
+__host__ inline unsigned rows_blocks(const Geo &g, int rows) {
+  const long long nb = (long long)((g.n1 + kSeg - 1) / kSeg) * ((g.n2 + rows - 1) / rows);
+  return (unsigned)((nb + kNumXcd - 1) / kNumXcd * kNumXcd);
+}
+
+template <typename Real, int MM>
+__global__ __launch_bounds__(kSeg) void k_curl_e_2d(Geo g, Fields<Real> f, const Real *Bin1, const Real *Bin2,
+                                                    const Real *Bin3, Real *Bout1, Real *Bout2, Real *Bout3,
+                                                    Axial<Real> ax, Real h2, int rows) {
+  __shared__ Real sE2[stage_pitch<kSeg>()], sE3[stage_pitch<kSeg>()];
+  int l0, r0, r1;
+  if (!rows_of(g, (g.n1 + kSeg - 1) / kSeg, rows, l0, r0, r1)) return;
+  curl_e_rows<Real, MM, kSeg>(g, f.E1, f.E2, f.E3, Bin1, Bin2, Bin3, Bout1, Bout2, Bout3, ax, h2, l0, r0, r1, sE2,
+                              sE3);
+}
+
+template <typename Real, int MM>
+__global__ __launch_bounds__(kSeg) void k_curl_b_2d(Geo g, Fields<Real> f, Axial<Real> ax, Real e2, int rows) {
   __shared__ Real sB2[stage_pitch<kSeg>()], sB3[stage_pitch<kSeg>()];
-  int l0, i2, i3;
-  if (!tile_of(g, (g.n1 + kSeg - 1) / kSeg, l0, i2, i3)) return;
-  curl_b_tile<Real, DIM, MM, kSeg, 1>(g, f.E1, f.E2, f.E3, f.B1, f.B2, f.B3, ax, e2, e3, l0, i2, i3, sB2, sB3);
+  int l0, r0, r1;
+  if (!rows_of(g, (g.n1 + kSeg - 1) / kSeg, rows, l0, r0, r1)) return;
+  curl_b_rows<Real, MM, kSeg>(g, f.E1, f.E2, f.E3, f.B1, f.B2, f.B3, ax, e2, l0, r0, r1, sB2, sB3);
 }
 
 // 3D: each workgroup takes one 256-cell x1 segment of one x2 row and marches
@@ -297,13 +327,14 @@ static void curl_e_dispatch(const Geo &g, const Fields<Real> &f, Real *const Bin
       k_curl_e_col<Real, 0><<<nc, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, h3);
     return;
   }
-  const unsigned nb = tile_blocks(g);
+  const int rows = rows_per_tile(g);
+  const unsigned nb = rows_blocks(g, rows);
   if (ax.M == 1)
-    k_curl_e<Real, DIM, 1><<<nb, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, h3);
+    k_curl_e_2d<Real, 1><<<nb, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, rows);
   else if (ax.M == 16)
-    k_curl_e<Real, DIM, 16><<<nb, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, h3);
+    k_curl_e_2d<Real, 16><<<nb, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, rows);
   else
-    k_curl_e<Real, DIM, 0><<<nb, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, h3);
+    k_curl_e_2d<Real, 0><<<nb, kSeg, 0, st>>>(g, f, Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], ax, h2, rows);
 }
 
 template <typename Real, int DIM>
@@ -319,13 +350,14 @@ static void curl_b_dispatch(const Geo &g, const Fields<Real> &f, const Axial<Rea
       k_curl_b_col<Real, 0><<<nc, kSeg, 0, st>>>(g, f, ax, e2, e3);
     return;
   }
-  const unsigned nb = tile_blocks(g);
+  const int rows = rows_per_tile(g);
+  const unsigned nb = rows_blocks(g, rows);
   if (ax.M == 1)
-    k_curl_b<Real, DIM, 1><<<nb, kSeg, 0, st>>>(g, f, ax, e2, e3);
+    k_curl_b_2d<Real, 1><<<nb, kSeg, 0, st>>>(g, f, ax, e2, rows);
   else if (ax.M == 16)
-    k_curl_b<Real, DIM, 16><<<nb, kSeg, 0, st>>>(g, f, ax, e2, e3);
+    k_curl_b_2d<Real, 16><<<nb, kSeg, 0, st>>>(g, f, ax, e2, rows);
   else
-    k_curl_b<Real, DIM, 0><<<nb, kSeg, 0, st>>>(g, f, ax, e2, e3);
+    k_curl_b_2d<Real, 0><<<nb, kSeg, 0, st>>>(g, f, ax, e2, rows);
 }
 
 template <typename Real>
