@@ -187,10 +187,11 @@ relpic_status relpic_read_particles(relpic_sim *sim, int species, int64_t cap, i
                                     double *u, uint8_t *alive, int64_t *id, int64_t *n_out);
 
 /* Particle sort (a2).  The push kernel deposits through per-workgroup LDS
- * tiles, which pays off when particles are stored in cell order.  Species
- * are sorted by cell (dropped particles removed) before the first step after
- * a load, and every `interval` steps if interval > 0 (default 0).  Sorting
- * synchronizes the stream. */
+ * tiles and sums wavefronts of particles that share a cell, which pays off
+ * when particles are stored in cell order.  Species are sorted by cell
+ * (dropped particles removed) before the first step after a load, and every
+ * `interval` steps if interval > 0 (default 25: particles that drift into
+ * other cells slowly break the order up).  Sorting synchronizes the stream. */
 relpic_status relpic_sort_particles(relpic_sim *sim);
 relpic_status relpic_set_sort_interval(relpic_sim *sim, int64_t interval);
 

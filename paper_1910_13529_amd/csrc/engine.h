@@ -63,7 +63,7 @@ struct relpic_sim {
   int ng = 0;
   std::vector<Species> sp;
   long long step = 0, ws = 0;
-  long long sort_interval = 0;  // re-sort every this many steps (0: only after loads)
+  long long sort_interval = 25;  // re-sort every this many steps (0: only after loads)
   int *err = nullptr;
   double *dbuf = nullptr;      // diagnostics accumulators (8 doubles)
   double *rho = nullptr;       // FP64 scratch for the Gauss diagnostic

@@ -103,7 +103,10 @@ __global__ void k_permute(Particles<Real> src, Particles<Real> dst, const int *i
   dst.u2[j] = src.u2[i];
   dst.u3[j] = src.u3[i];
   id_dst[j] = id_src[i];
-  if (c >= 0) atomicAdd(alive, 1ULL);
+  // one atomic per wavefront (its first active lane) for the alive count
+  const unsigned long long live = __ballot(c >= 0);
+  const unsigned long long act = __ballot(1);
+  if ((threadIdx.x & 63) == __ffsll((long long)act) - 1) atomicAdd(alive, (unsigned long long)__popcll(live));
 }
 
 // number of distinct alive cells in a sorted key array (density estimate)
