@@ -2,6 +2,8 @@
 // injection for the moving window.  Diagnostics accumulate in FP64 whatever
 // the field precision, so FP32 runs report energy and charge conservation at
 // FP64 resolution.
+#include <climits>
+
 #include "kernels.h"
 
 namespace relpic {
@@ -70,39 +72,18 @@ __global__ __launch_bounds__(kRedBlock) void k_kinetic(Particles<Real> p, double
   }
 }
 
-// rho of the particles (FP64).  Lanes of a wavefront that share the first
-// active lane's cell (the common case for cell-sorted particles) sum their
-// 3 x 3 (x 3) node weights across the wavefront first, one atomic per node.
-template <typename Real, int DIM>
-__global__ __launch_bounds__(kRedBlock) void k_rho(Geo g, Particles<Real> p, double qdv, double *rho) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const int packed = (i < p.n) ? p.cell[i] : -1;
-  const bool active = packed >= 0;
-  int c1 = 0, c2 = 0, c3 = 0;
-  double w[3][3] = {{0, 0, 0}, {0, 0, 0}, {1, 0, 0}};
-  if (active) {
-    const int s1 = packed % g.n1;
-    const int rest = packed / g.n1;
-    c2 = rest % g.n2;
-    c3 = DIM == 3 ? rest / g.n2 : 0;
-    c1 = s1 - g.ws_mod;
-    if (c1 < 0) c1 += g.n1;
-    const double o[3] = {(double)p.o1[i], (double)p.o2[i], DIM == 3 ? (double)p.o3[i] : 0.0};
-    for (int d = 0; d < DIM; ++d) {
-      const double a = 0.5 - o[d], b = 0.5 + o[d];
-      w[d][0] = 0.5 * a * a;
-      w[d][1] = 0.75 - o[d] * o[d];
-      w[d][2] = 0.5 * b * b;
-    }
-  }
-  const unsigned long long act = __ballot(active);
-  if (act == 0ULL) return;
-  const int first = __ffsll((long long)act) - 1;
-  const int k1 = __shfl(c1, first, 64), k2 = __shfl(c2, first, 64), k3 = __shfl(c3, first, 64);
-  const bool same = active && c1 == k1 && c2 == k2 && c3 == k3;
-  constexpr int S = DIM == 3 ? 27 : 9;
-  double v[S];
-  for (int k = 0; k < S; ++k) v[k] = same ? qdv * w[0][k % 3] * w[1][(k / 3) % 3] * (DIM == 3 ? w[2][k / 9] : 1.0) : 0.0;
+// rho of the particles (FP64).  Each wavefront walks kRhoGroups consecutive
+// groups of 64 cell-sorted particles.  Lanes whose particle sits in the
+// wavefront's current cell (the first active lane's cell) add its 3 x 3 (x 3)
+// node weights to per-lane FP64 accumulators; when the group's cell changes,
+// the accumulators are summed across the wavefront (recursive halving, one
+// node per lane) and added to rho with one atomic per node.  Lanes in another
+// cell add their weights directly.  A dense bunch then costs one atomic per
+// node per 64 x kRhoGroups particles instead of per 64.
+constexpr int kRhoGroups = 16;
+
+template <int S>
+__device__ __forceinline__ void rho_flush(const Geo &g, double *v, int k1, int k2, int k3, int dim, double *rho) {
   const int lane = threadIdx.x & 63;
   int off = 0;
   int size = S;
@@ -122,23 +103,72 @@ __global__ __launch_bounds__(kRedBlock) void k_rho(Geo g, Particles<Real> p, dou
     const int a = off % 3, b = (off / 3) % 3, c = off / 9;
     const int col = col_of(g, k1 - 1 + a);
     if (col >= 0) {
-      const long long row = (long long)g.n1 * (wrap(k2 - 1 + b, g.n2) + (long long)g.n2 * (DIM == 3 ? wrap(k3 - 1 + c, g.n3) : 0));
+      const long long row =
+          (long long)g.n1 * (wrap(k2 - 1 + b, g.n2) + (long long)g.n2 * (dim == 3 ? wrap(k3 - 1 + c, g.n3) : 0));
       atomicAdd(rho + row + col, v[0]);
     }
   }
-  if (!active || same) return;
-  for (int cc = 0; cc < (DIM == 3 ? 3 : 1); ++cc) {
-    const int i3 = DIM == 3 ? wrap(c3 - 1 + cc, g.n3) : 0;
-    const double w3 = DIM == 3 ? w[2][cc] : 1.0;
-    for (int bb = 0; bb < 3; ++bb) {
-      const long long row = (long long)g.n1 * (wrap(c2 - 1 + bb, g.n2) + (long long)g.n2 * i3);
-      for (int aa = 0; aa < 3; ++aa) {
-        const int col = col_of(g, c1 - 1 + aa);
-        if (col < 0) continue;
-        atomicAdd(rho + row + col, qdv * w[0][aa] * w[1][bb] * w3);
+}
+
+template <typename Real, int DIM>
+__global__ __launch_bounds__(kRedBlock) void k_rho(Geo g, Particles<Real> p, double qdv, double *rho) {
+  constexpr int S = DIM == 3 ? 27 : 9;
+  const int lane = threadIdx.x & 63;
+  const long long base = ((blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6) * 64LL * kRhoGroups;
+  double acc[S];
+  for (int k = 0; k < S; ++k) acc[k] = 0.0;
+  int a1 = INT_MIN, a2 = 0, a3 = 0;  // the accumulators' cell (uniform over the wavefront)
+  for (int grp = 0; grp < kRhoGroups; ++grp) {
+    const long long i = base + 64LL * grp + lane;
+    const int packed = (i < p.n) ? p.cell[i] : -1;
+    const bool active = packed >= 0;
+    int c1 = 0, c2 = 0, c3 = 0;
+    double w[3][3] = {{0, 0, 0}, {0, 0, 0}, {1, 0, 0}};
+    if (active) {
+      const int s1 = packed % g.n1;
+      const int rest = packed / g.n1;
+      c2 = rest % g.n2;
+      c3 = DIM == 3 ? rest / g.n2 : 0;
+      c1 = s1 - g.ws_mod;
+      if (c1 < 0) c1 += g.n1;
+      const double o[3] = {(double)p.o1[i], (double)p.o2[i], DIM == 3 ? (double)p.o3[i] : 0.0};
+      for (int d = 0; d < DIM; ++d) {
+        const double a = 0.5 - o[d], b = 0.5 + o[d];
+        w[d][0] = 0.5 * a * a;
+        w[d][1] = 0.75 - o[d] * o[d];
+        w[d][2] = 0.5 * b * b;
+      }
+    }
+    const unsigned long long act = __ballot(active);
+    if (act == 0ULL) continue;
+    const int first = __ffsll((long long)act) - 1;
+    const int k1 = __shfl(c1, first, 64), k2 = __shfl(c2, first, 64), k3 = __shfl(c3, first, 64);
+    if (k1 != a1 || k2 != a2 || k3 != a3) {
+      if (a1 != INT_MIN) rho_flush<S>(g, acc, a1, a2, a3, DIM, rho);
+      for (int k = 0; k < S; ++k) acc[k] = 0.0;
+      a1 = k1;
+      a2 = k2;
+      a3 = k3;
+    }
+    const bool same = active && c1 == a1 && c2 == a2 && c3 == a3;
+    if (same) {
+      for (int k = 0; k < S; ++k) acc[k] += qdv * w[0][k % 3] * w[1][(k / 3) % 3] * (DIM == 3 ? w[2][k / 9] : 1.0);
+    } else if (active) {
+      for (int cc = 0; cc < (DIM == 3 ? 3 : 1); ++cc) {
+        const int i3 = DIM == 3 ? wrap(c3 - 1 + cc, g.n3) : 0;
+        const double w3 = DIM == 3 ? w[2][cc] : 1.0;
+        for (int bb = 0; bb < 3; ++bb) {
+          const long long row = (long long)g.n1 * (wrap(c2 - 1 + bb, g.n2) + (long long)g.n2 * i3);
+          for (int aa = 0; aa < 3; ++aa) {
+            const int col = col_of(g, c1 - 1 + aa);
+            if (col < 0) continue;
+            atomicAdd(rho + row + col, qdv * w[0][aa] * w[1][bb] * w3);
+          }
+        }
       }
     }
   }
+  if (a1 != INT_MIN) rho_flush<S>(g, acc, a1, a2, a3, DIM, rho);
 }
 
 template <typename Real, int DIM>
@@ -252,7 +282,8 @@ void launch_diag_kinetic(const Particles<Real> &p, double mass, double *acc, uns
 template <typename Real>
 void launch_diag_rho(int ndim, const Geo &g, const Particles<Real> &p, double qdv, double *rho, hipStream_t st) {
   if (p.n <= 0) return;
-  const unsigned blocks = (unsigned)((p.n + kRedBlock - 1) / kRedBlock);
+  const long long per = (long long)kRedBlock * kRhoGroups;
+  const unsigned blocks = (unsigned)((p.n + per - 1) / per);
   if (ndim == 3)
     k_rho<Real, 3><<<blocks, kRedBlock, 0, st>>>(g, p, qdv, rho);
   else
