@@ -396,16 +396,19 @@ def main():
     achieved = alg / (avg_ms * 1e-3) / 1e9
     flops = push_flops_per_particle(3) * npart
     peak_alu = FP32_VECTOR_PEAK_TFLOPS if args.precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    traffic_of = {}
+    if os.path.exists(TRAFFIC_FILE) and args.grid == "512,256,256":
         try:
             tf = json.load(open(TRAFFIC_FILE))
-            ent = tf.get("kernels", {}).get("%s/%s/%s" % (head, args.precision, dom))
             from paper_1910_13529_amd.profiling import kernel_source_hash
-            if ent and tf.get("source_hash") == kernel_source_hash() and args.grid == "512,256,256":
-                traffic = ent["hbm_bytes_per_launch"]
+            if tf.get("source_hash") == kernel_source_hash():
+                for k, ent in tf.get("kernels", {}).items():
+                    sol, prec, cls = k.split("/")
+                    if sol == head and prec == args.precision:
+                        traffic_of[cls] = ent["hbm_bytes_per_launch"]
         except Exception:
-            traffic = None
+            traffic_of = {}
+    traffic = traffic_of.get(dom)
 
     out = {
         "metric": "particle-steps/s + field cell-updates/s per PIC step; % HBM peak; FP32 vs FP64",
@@ -461,6 +464,7 @@ def main():
             k: {"bound": "hbm", "achieved": algorithmic_bytes(k, ncells, npart, esz) / (prof[k][1] / prof[k][0] * 1e-3) / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": algorithmic_bytes(k, ncells, npart, esz) / (prof[k][1] / prof[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "traffic": traffic_of.get(k),
                 "avg_launch_ms": prof[k][1] / prof[k][0],
                 "algorithmic_bytes_per_launch": algorithmic_bytes(k, ncells, npart, esz)}
             for k in ("curl_e", "curl_b") if prof.get(k, (0, 0))[0] > 0},

@@ -342,6 +342,7 @@ relpic_status prepare(relpic_batch *b) {
     int d = 0;
     for (relpic_sim *s : b->runs)
       for (Species &sp : s->sp) {
+        sp.sorted_at = s->step;
         if (sp.n <= 0) {
           sp.dirty = false;
           continue;

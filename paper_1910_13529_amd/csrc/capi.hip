@@ -92,6 +92,7 @@ long long window_target(const relpic_sim *s, long long steps_done) {
 template <typename Real>
 relpic_status do_sort(relpic_sim *s, Species &sp) {
   sp.dirty = false;
+  sp.sorted_at = s->step;
   if (sp.n <= 1) return RELPIC_OK;
   Particles<Real> src = parts<Real>(sp);
   launch_sort_keys<Real>(src, sp.keys, sp.idx, s->st);
@@ -161,7 +162,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
   relpic_status status = RELPIC_OK;
   for (long long it = 0; it < nsteps; ++it) {
     for (auto &sp : s->sp)
-      if (sp.dirty || (s->sort_interval > 0 && s->step % s->sort_interval == 0 && it > 0))
+      if (sp.dirty || (s->sort_interval > 0 && s->step - sp.sorted_at >= s->sort_interval))
         if ((status = do_sort<Real>(s, sp))) break;
     if (status) break;
     int shift = 0;

@@ -29,6 +29,7 @@ struct Species {
   void *sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
   bool dirty = true;   // needs a sort before the next step
+  long long sorted_at = 0;  // step of the last sort
   int K = 1;           // particles per thread in the push kernel
   bool inject = false;
   int ppc[3] = {1, 1, 1};

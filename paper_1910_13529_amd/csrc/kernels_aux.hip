@@ -72,103 +72,110 @@ __global__ __launch_bounds__(kRedBlock) void k_kinetic(Particles<Real> p, double
   }
 }
 
-// rho of the particles (FP64).  Each wavefront walks kRhoGroups consecutive
-// groups of 64 cell-sorted particles.  Lanes whose particle sits in the
-// wavefront's current cell (the first active lane's cell) add its 3 x 3 (x 3)
-// node weights to per-lane FP64 accumulators; when the group's cell changes,
-// the accumulators are summed across the wavefront (recursive halving, one
-// node per lane) and added to rho with one atomic per node.  Lanes in another
-// cell add their weights directly.  A dense bunch then costs one atomic per
-// node per 64 x kRhoGroups particles instead of per 64.
-constexpr int kRhoGroups = 16;
+// rho of the particles (FP64).  A workgroup takes kRhoChunk consecutive
+// particles and finds the bounding box of their cells.  When that box, grown
+// by the one-node reach of the quadratic shape on each side, fits kRhoTile
+// doubles of LDS (always for cell-sorted particles of a bunch), every particle
+// adds its 3 x 3 (x 3) node weights to the LDS tile, and the tile is added to
+// rho with one atomic per non-zero node; hot nodes of a dense bunch then see
+// one global atomic per workgroup instead of one per particle.  Otherwise
+// (scattered or unsorted particles) each weight goes to rho directly.
+constexpr int kRhoChunk = 2048;
+constexpr int kRhoTile = 6144;
 
-template <int S>
-__device__ __forceinline__ void rho_flush(const Geo &g, double *v, int k1, int k2, int k3, int dim, double *rho) {
-  const int lane = threadIdx.x & 63;
-  int off = 0;
-  int size = S;
-  for (int bit = 32; bit >= 1; bit >>= 1) {
-    const int h = (size + 1) / 2;
-    const bool up = (lane & bit) != 0;
-    for (int j = 0; j < h; ++j) {
-      const double lo = v[j];
-      const double hi = (j + h < size) ? v[j + h] : 0.0;
-      const double send = up ? lo : hi;
-      v[j] = (up ? hi : lo) + __shfl_xor(send, bit, 64);
-    }
-    if (up) off += h;
-    size = h;
-  }
-  if (off < S && v[0] != 0.0) {
-    const int a = off % 3, b = (off / 3) % 3, c = off / 9;
-    const int col = col_of(g, k1 - 1 + a);
-    if (col >= 0) {
-      const long long row =
-          (long long)g.n1 * (wrap(k2 - 1 + b, g.n2) + (long long)g.n2 * (dim == 3 ? wrap(k3 - 1 + c, g.n3) : 0));
-      atomicAdd(rho + row + col, v[0]);
-    }
-  }
+template <typename Real, int DIM>
+__device__ __forceinline__ bool rho_cell(const Geo &g, const Particles<Real> &p, long long i, int c[3]) {
+  const int packed = p.cell[i];
+  if (packed < 0) return false;
+  const int s1 = packed % g.n1;
+  const int rest = packed / g.n1;
+  c[1] = rest % g.n2;
+  c[2] = DIM == 3 ? rest / g.n2 : 0;
+  c[0] = s1 - g.ws_mod;  // window-relative x1 cell
+  if (c[0] < 0) c[0] += g.n1;
+  return true;
 }
 
 template <typename Real, int DIM>
 __global__ __launch_bounds__(kRedBlock) void k_rho(Geo g, Particles<Real> p, double qdv, double *rho) {
-  constexpr int S = DIM == 3 ? 27 : 9;
-  const int lane = threadIdx.x & 63;
-  const long long base = ((blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6) * 64LL * kRhoGroups;
-  double acc[S];
-  for (int k = 0; k < S; ++k) acc[k] = 0.0;
-  int a1 = INT_MIN, a2 = 0, a3 = 0;  // the accumulators' cell (uniform over the wavefront)
-  for (int grp = 0; grp < kRhoGroups; ++grp) {
-    const long long i = base + 64LL * grp + lane;
-    const int packed = (i < p.n) ? p.cell[i] : -1;
-    const bool active = packed >= 0;
-    int c1 = 0, c2 = 0, c3 = 0;
+  __shared__ double tile[kRhoTile];
+  __shared__ int wlo[3][kRedBlock / 64], whi[3][kRedBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long base = blockIdx.x * (long long)kRhoChunk;
+  const long long end = base + kRhoChunk < p.n ? base + kRhoChunk : p.n;
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+  for (long long i = base + threadIdx.x; i < end; i += kRedBlock) {
+    int c[3];
+    if (!rho_cell<Real, DIM>(g, p, i, c)) continue;
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], c[d]);
+      hi[d] = max(hi[d], c[d]);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
+    }
+  if (lane == 0)
+    for (int d = 0; d < 3; ++d) {
+      wlo[d][wave] = lo[d];
+      whi[d][wave] = hi[d];
+    }
+  __syncthreads();
+  for (int d = 0; d < 3; ++d)
+    for (int w = 0; w < kRedBlock / 64; ++w) {
+      lo[d] = min(lo[d], wlo[d][w]);
+      hi[d] = max(hi[d], whi[d][w]);
+    }
+  if (lo[0] == INT_MAX) return;  // no live particle in the chunk (uniform over the workgroup)
+  // tile index (a, b, c) <-> node (lo1 - 1 + a, lo2 - 1 + b, lo3 - 1 + c)
+  const int w1 = hi[0] - lo[0] + 3, w2 = hi[1] - lo[1] + 3;
+  const long long vol = (long long)w1 * w2 * (DIM == 3 ? hi[2] - lo[2] + 3 : 1);
+  const bool fits = vol <= kRhoTile;
+  if (fits)
+    for (int t = threadIdx.x; t < vol; t += kRedBlock) tile[t] = 0.0;
+  __syncthreads();
+  for (long long i = base + threadIdx.x; i < end; i += kRedBlock) {
+    int c[3];
+    if (!rho_cell<Real, DIM>(g, p, i, c)) continue;
+    const double o[3] = {(double)p.o1[i], (double)p.o2[i], DIM == 3 ? (double)p.o3[i] : 0.0};
     double w[3][3] = {{0, 0, 0}, {0, 0, 0}, {1, 0, 0}};
-    if (active) {
-      const int s1 = packed % g.n1;
-      const int rest = packed / g.n1;
-      c2 = rest % g.n2;
-      c3 = DIM == 3 ? rest / g.n2 : 0;
-      c1 = s1 - g.ws_mod;
-      if (c1 < 0) c1 += g.n1;
-      const double o[3] = {(double)p.o1[i], (double)p.o2[i], DIM == 3 ? (double)p.o3[i] : 0.0};
-      for (int d = 0; d < DIM; ++d) {
-        const double a = 0.5 - o[d], b = 0.5 + o[d];
-        w[d][0] = 0.5 * a * a;
-        w[d][1] = 0.75 - o[d] * o[d];
-        w[d][2] = 0.5 * b * b;
-      }
+    for (int d = 0; d < DIM; ++d) {
+      const double a = 0.5 - o[d], b = 0.5 + o[d];
+      w[d][0] = 0.5 * a * a;
+      w[d][1] = 0.75 - o[d] * o[d];
+      w[d][2] = 0.5 * b * b;
     }
-    const unsigned long long act = __ballot(active);
-    if (act == 0ULL) continue;
-    const int first = __ffsll((long long)act) - 1;
-    const int k1 = __shfl(c1, first, 64), k2 = __shfl(c2, first, 64), k3 = __shfl(c3, first, 64);
-    if (k1 != a1 || k2 != a2 || k3 != a3) {
-      if (a1 != INT_MIN) rho_flush<S>(g, acc, a1, a2, a3, DIM, rho);
-      for (int k = 0; k < S; ++k) acc[k] = 0.0;
-      a1 = k1;
-      a2 = k2;
-      a3 = k3;
-    }
-    const bool same = active && c1 == a1 && c2 == a2 && c3 == a3;
-    if (same) {
-      for (int k = 0; k < S; ++k) acc[k] += qdv * w[0][k % 3] * w[1][(k / 3) % 3] * (DIM == 3 ? w[2][k / 9] : 1.0);
-    } else if (active) {
-      for (int cc = 0; cc < (DIM == 3 ? 3 : 1); ++cc) {
-        const int i3 = DIM == 3 ? wrap(c3 - 1 + cc, g.n3) : 0;
-        const double w3 = DIM == 3 ? w[2][cc] : 1.0;
-        for (int bb = 0; bb < 3; ++bb) {
-          const long long row = (long long)g.n1 * (wrap(c2 - 1 + bb, g.n2) + (long long)g.n2 * i3);
+    for (int cc = 0; cc < (DIM == 3 ? 3 : 1); ++cc) {
+      const double w3 = qdv * w[2][cc];
+      for (int bb = 0; bb < 3; ++bb) {
+        const double w23 = w3 * w[1][bb];
+        if (fits) {
+          const int t0 = ((DIM == 3 ? c[2] - lo[2] + cc : 0) * w2 + c[1] - lo[1] + bb) * w1 + c[0] - lo[0];
+          for (int aa = 0; aa < 3; ++aa) atomicAdd(&tile[t0 + aa], w23 * w[0][aa]);
+        } else {
+          const int i3 = DIM == 3 ? wrap(c[2] - 1 + cc, g.n3) : 0;
+          const long long row = (long long)g.n1 * (wrap(c[1] - 1 + bb, g.n2) + (long long)g.n2 * i3);
           for (int aa = 0; aa < 3; ++aa) {
-            const int col = col_of(g, c1 - 1 + aa);
-            if (col < 0) continue;
-            atomicAdd(rho + row + col, qdv * w[0][aa] * w[1][bb] * w3);
+            const int col = col_of(g, c[0] - 1 + aa);
+            if (col >= 0) atomicAdd(rho + row + col, w23 * w[0][aa]);
           }
         }
       }
     }
   }
-  if (a1 != INT_MIN) rho_flush<S>(g, acc, a1, a2, a3, DIM, rho);
+  if (!fits) return;
+  __syncthreads();
+  for (int t = threadIdx.x; t < vol; t += kRedBlock) {
+    const double v = tile[t];
+    if (v == 0.0) continue;
+    const int a = t % w1, b = (t / w1) % w2, cz = t / (w1 * w2);
+    const int col = col_of(g, lo[0] - 1 + a);
+    if (col < 0) continue;
+    const int i3 = DIM == 3 ? wrap(lo[2] - 1 + cz, g.n3) : 0;
+    atomicAdd(rho + (long long)g.n1 * (wrap(lo[1] - 1 + b, g.n2) + (long long)g.n2 * i3) + col, v);
+  }
 }
 
 template <typename Real, int DIM>
@@ -282,8 +289,7 @@ void launch_diag_kinetic(const Particles<Real> &p, double mass, double *acc, uns
 template <typename Real>
 void launch_diag_rho(int ndim, const Geo &g, const Particles<Real> &p, double qdv, double *rho, hipStream_t st) {
   if (p.n <= 0) return;
-  const long long per = (long long)kRedBlock * kRhoGroups;
-  const unsigned blocks = (unsigned)((p.n + per - 1) / per);
+  const unsigned blocks = (unsigned)((p.n + kRhoChunk - 1) / kRhoChunk);
   if (ndim == 3)
     k_rho<Real, 3><<<blocks, kRedBlock, 0, st>>>(g, p, qdv, rho);
   else

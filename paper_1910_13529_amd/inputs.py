@@ -80,6 +80,18 @@ def plasma_lattice(seed, lo, hi, ppc, uth, ndim=3):
     return cell, off, u
 
 
+def uniform_particles(seed, npart, n, uth, ndim=3):
+    """npart positions uniform over the grid (cell units; cell i covers
+    [i - 1/2, i + 1/2), i = 0 .. n[d] - 1), u ~ uth * N(0, 1) per component,
+    in the order drawn (not cell-sorted)."""
+    rng = np.random.default_rng(seed)
+    nn = np.asarray(n[:ndim], dtype=np.float64)[None, :]
+    X = np.minimum(rng.uniform(0.0, 1.0, (npart, ndim)) * nn - 0.5, nn - 0.5 - 1e-6)
+    u = uth * rng.standard_normal((npart, 3))
+    cell, off = split_positions(X)
+    return cell, off, u
+
+
 def random_fields(seed, shape, scale=1.0, ncomp=6):
     rng = np.random.default_rng(seed)
     return [scale * rng.standard_normal(shape) for _ in range(ncomp)]

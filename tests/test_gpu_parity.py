@@ -119,6 +119,36 @@ def test_gauss_and_energy_diagnostics_fp64():
     assert d["n_alive"] == 400 and d["error_word"] == 0
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("layout", ["bunch_sorted", "bunch_unsorted", "scattered"])
+def test_rho_diagnostic_layouts_fp64(ndim, layout):
+    # the diagnostic's charge density node by node against the oracle's: with
+    # zero fields and the background set to minus the oracle's rho, the Gauss
+    # residual is rho_gpu - rho_oracle.  A sorted or unsorted bunch sums in the
+    # workgroups' LDS tiles; particles scattered over the whole grid (chunk
+    # boxes larger than the tile) add to rho directly.
+    if ndim == 3:
+        n, dx, window = (72, 16, 16), (0.02, 0.05, 0.05), layout != "scattered"
+    else:
+        n, dx, window = (256, 64), (1.0, 1.0), False
+    if layout == "scattered":
+        cell, off, u = inputs.uniform_particles(13, 30000, n, 1e-3, ndim=ndim)
+        sp = (-1e-3, -1.0, cell, off, u, len(cell))
+    else:
+        sp = beam_species(11, 30000, n, dx, 100.0, Q=-1e-3, sigma_cells=(5.0, 2.0, 2.0)[:ndim], center_frac=0.5)
+    npart = len(sp[2])
+    # Yee operator: the window's excluded edge (2M + 2 cells) is then 4 cells
+    g, o, ids = make_pair(ndim, n, dx, 0.005, (1.0,), window, [sp])
+    if layout == "bunch_sorted":
+        g.sort_particles()
+    g.set_background_rho(-o.rho())
+    log("rho diagnostic %dD %s" % (ndim, layout))
+    d = g.diagnostics()
+    assert d["rho_max"] > 0 and d["gauss_max"] < 1e-13 * d["rho_max"], d
+    assert abs(d["charge"] - npart * -1e-3) < 1e-12 * npart * 1e-3
+    g.sync()
+
+
 def test_plasma_injection_window_fp64():
     # cold plasma ahead of a beam in the moving window: the window injects a
     # slab of 2x2x2 particles per cell at each shift, momenta from the shared
