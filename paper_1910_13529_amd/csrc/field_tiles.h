@@ -25,8 +25,9 @@ constexpr int stage_pitch() {
 // neighbour the previous row already loaded is carried in registers (E at
 // i2 + 1 becomes the next row's own E for the B update; B at i2 becomes the
 // next row's i2 - 1 for the E update), and the next row's staged x1 segment
-// is loaded while the current row is computed.  Every barrier is reached by
-// all threads.  The LDS arguments hold stage_pitch<SEG>() values each.
+// and the own cell's operands are loaded while the current row is computed.
+// Every barrier is reached by all threads.  The LDS arguments hold
+// stage_pitch<SEG>() values each.
 
 // Bout = Bin - curl+ E (2D; ax.c[l] = C_l c / dx1, h2 = c / dx2)
 template <typename Real, int MM, int SEG>
@@ -42,9 +43,25 @@ __device__ __forceinline__ void curl_e_rows(const Geo &g, const Real *E1, const 
   const int ta = threadIdx.x, tb = threadIdx.x + SEG;
   const bool hb = tb < SEG + 2 * M;
   const int ca = col_of(g, l0 - M + 1 + ta), cb = hb ? col_of(g, l0 - M + 1 + tb) : -1;
-  long long row = (long long)g.n1 * r0;
-  Real pa2 = ldc(E2, row, ca), pa3 = ldc(E3, row, ca), pb2 = ldc(E2, row, cb), pb3 = ldc(E3, row, cb);
-  Real e1 = own ? E1[row + s1] : Real(0);
+  Real pa2, pa3, pb2, pb3;                           // staged E2, E3 of the row
+  Real e1u = 0, e3u = 0, q1 = 0, q2 = 0, q3 = 0;     // own cell's operands
+  auto fetch = [&](int i2) {
+    const long long row = (long long)g.n1 * i2;
+    pa2 = ldc(E2, row, ca);
+    pa3 = ldc(E3, row, ca);
+    pb2 = ldc(E2, row, cb);
+    pb3 = ldc(E3, row, cb);
+    if (own) {
+      const long long id = row + s1, up = (long long)g.n1 * wrap_near(i2 + 1, g.n2) + s1;
+      e1u = E1[up];
+      e3u = E3[up];
+      q1 = Bin1[id];
+      q2 = Bin2[id];
+      q3 = Bin3[id];
+    }
+  };
+  Real e1 = own ? E1[(long long)g.n1 * r0 + s1] : Real(0);
+  fetch(r0);
   for (int i2 = r0; i2 < r1; ++i2) {
     sE2[ta] = pa2;
     sE3[ta] = pa3;
@@ -52,17 +69,11 @@ __device__ __forceinline__ void curl_e_rows(const Geo &g, const Real *E1, const 
       sE2[tb] = pb2;
       sE3[tb] = pb3;
     }
+    const Real ce1u = e1u, ce3u = e3u, cq1 = q1, cq2 = q2, cq3 = q3;
     __syncthreads();
-    const long long rowp = (long long)g.n1 * wrap_near(i2 + 1, g.n2);
-    if (i2 + 1 < r1) {
-      pa2 = ldc(E2, rowp, ca);
-      pa3 = ldc(E3, rowp, ca);
-      pb2 = ldc(E2, rowp, cb);
-      pb3 = ldc(E3, rowp, cb);
-    }
+    if (i2 + 1 < r1) fetch(i2 + 1);
     if (own) {
-      const long long id = row + s1, up = rowp + s1;
-      const Real e1n = E1[up], e3n = E3[up];
+      const long long id = (long long)g.n1 * i2 + s1;
       Real d1E2 = 0, d1E3 = 0;
       auto term = [&](int l) {
         d1E2 += ax.c[l - 1] * (sE2[c + l] - sE2[c - l + 1]);
@@ -75,15 +86,14 @@ __device__ __forceinline__ void curl_e_rows(const Geo &g, const Real *E1, const 
         for (int l = 1; l <= M; ++l) term(l);
       }
       const Real e3 = sE3[c];
-      const Real d2E3 = h2 * (e3n - e3);
-      const Real d2E1 = h2 * (e1n - e1);
-      Bout1[id] = Bin1[id] - d2E3;
-      Bout2[id] = Bin2[id] + d1E3;
-      Bout3[id] = Bin3[id] - (d1E2 - d2E1);
-      e1 = e1n;
+      const Real d2E3 = h2 * (ce3u - e3);
+      const Real d2E1 = h2 * (ce1u - e1);
+      Bout1[id] = cq1 - d2E3;
+      Bout2[id] = cq2 + d1E3;
+      Bout3[id] = cq3 - (d1E2 - d2E1);
+      e1 = ce1u;
     }
     __syncthreads();
-    row = rowp;
   }
 }
 
@@ -100,14 +110,29 @@ __device__ __forceinline__ void curl_b_rows(const Geo &g, Real *E1, Real *E2, Re
   const int ta = threadIdx.x, tb = threadIdx.x + SEG;
   const bool hb = tb < SEG + 2 * M;
   const int ca = col_of(g, l0 - M + ta), cb = hb ? col_of(g, l0 - M + tb) : -1;
-  long long row = (long long)g.n1 * r0;
-  Real pa2 = ldc(B2, row, ca), pa3 = ldc(B3, row, ca), pb2 = ldc(B2, row, cb), pb3 = ldc(B3, row, cb);
+  Real pa2, pa3, pb2, pb3;                           // staged B2, B3 of the row
+  Real b1 = 0, x1 = 0, x2 = 0, x3 = 0;               // own cell's operands
+  auto fetch = [&](int i2) {
+    const long long row = (long long)g.n1 * i2;
+    pa2 = ldc(B2, row, ca);
+    pa3 = ldc(B3, row, ca);
+    pb2 = ldc(B2, row, cb);
+    pb3 = ldc(B3, row, cb);
+    if (own) {
+      const long long id = row + s1;
+      b1 = B1[id];
+      x1 = E1[id];
+      x2 = E2[id];
+      x3 = E3[id];
+    }
+  };
   Real b1m = Real(0), b3m = Real(0);
   if (own) {
     const long long dn = (long long)g.n1 * wrap_near(r0 - 1, g.n2) + s1;
     b1m = B1[dn];
     b3m = B3[dn];
   }
+  fetch(r0);
   for (int i2 = r0; i2 < r1; ++i2) {
     sB2[ta] = pa2;
     sB3[ta] = pa3;
@@ -115,16 +140,11 @@ __device__ __forceinline__ void curl_b_rows(const Geo &g, Real *E1, Real *E2, Re
       sB2[tb] = pb2;
       sB3[tb] = pb3;
     }
+    const Real cb1 = b1, cx1 = x1, cx2 = x2, cx3 = x3;
     __syncthreads();
-    const long long rowp = (long long)g.n1 * wrap_near(i2 + 1, g.n2);
-    if (i2 + 1 < r1) {
-      pa2 = ldc(B2, rowp, ca);
-      pa3 = ldc(B3, rowp, ca);
-      pb2 = ldc(B2, rowp, cb);
-      pb3 = ldc(B3, rowp, cb);
-    }
+    if (i2 + 1 < r1) fetch(i2 + 1);
     if (own) {
-      const long long id = row + s1;
+      const long long id = (long long)g.n1 * i2 + s1;
       Real d1B3 = 0, d1B2 = 0;
       auto term = [&](int l) {
         d1B3 += ax.c[l - 1] * (sB3[c + l - 1] - sB3[c - l]);
@@ -136,17 +156,16 @@ __device__ __forceinline__ void curl_b_rows(const Geo &g, Real *E1, Real *E2, Re
       } else {
         for (int l = 1; l <= M; ++l) term(l);
       }
-      const Real b1 = B1[id], b3 = sB3[c];
+      const Real b3 = sB3[c];
       const Real d2B3 = e2 * (b3 - b3m);
-      const Real d2B1 = e2 * (b1 - b1m);
-      E1[id] += d2B3;
-      E2[id] -= d1B3;
-      E3[id] += d1B2 - d2B1;
-      b1m = b1;
+      const Real d2B1 = e2 * (cb1 - b1m);
+      E1[id] = cx1 + d2B3;
+      E2[id] = cx2 - d1B3;
+      E3[id] = cx3 + (d1B2 - d2B1);
+      b1m = cb1;
       b3m = b3;
     }
     __syncthreads();
-    row = rowp;
   }
 }
 

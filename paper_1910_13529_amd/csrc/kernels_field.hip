@@ -95,7 +95,9 @@ __host__ inline unsigned column_blocks(const Geo &g) {
   return (unsigned)(per * kNumXcd);
 }
 
-// Bout = Bin - curl+ E, marching over x3 (coefficients as in curl_e_tile)
+// Bout = Bin - curl+ E, marching over x3 (coefficients as in curl_e_tile).
+// Every global operand of plane i3 + 1 (the staged row, the own cell's Bin,
+// its x3 and x2 neighbours' E) is loaded while plane i3 is computed.
 template <typename Real, int MM>
 __global__ __launch_bounds__(kSeg) void k_curl_e_col(Geo g, Fields<Real> f, const Real *Bin1, const Real *Bin2,
                                                      const Real *Bin3, Real *Bout1, Real *Bout2, Real *Bout3,
@@ -111,35 +113,44 @@ __global__ __launch_bounds__(kSeg) void k_curl_e_col(Geo g, Fields<Real> f, cons
   const long long plane = (long long)g.n1 * g.n2;
   const long long r2 = (long long)g.n1 * i2, r2p = (long long)g.n1 * wrap_near(i2 + 1, g.n2);
   const int c = threadIdx.x + M - 1;  // LDS index of cell l1
-  Real e1 = own ? f.E1[r2 + plane * z0 + s1] : Real(0);
   // the staged row (cells l0 - M + 1 .. l0 + 255 + M) is at most two values
-  // per thread and array; the next plane's values are loaded into registers
-  // while the current plane is computed
+  // per thread and array
   const int ta = threadIdx.x, tb = threadIdx.x + kSeg;
   const bool hb = tb < kSeg + 2 * M;
   const int ca = col_of(g, l0 - M + 1 + ta), cb = hb ? col_of(g, l0 - M + 1 + tb) : -1;
-  Real pa2 = ldc(f.E2, r2 + plane * z0, ca), pa3 = ldc(f.E3, r2 + plane * z0, ca);
-  Real pb2 = ldc(f.E2, r2 + plane * z0, cb), pb3 = ldc(f.E3, r2 + plane * z0, cb);
-  for (int i3 = z0; i3 < z1; ++i3) {
+  Real a2, a3, b2, b3;                                            // staged E2, E3
+  Real e1u = 0, e2u = 0, e1r = 0, e3r = 0, q1 = 0, q2 = 0, q3 = 0;  // own cell's operands
+  auto fetch = [&](int i3) {
     const long long row = r2 + plane * i3;
-    sE2[ta] = pa2;
-    sE3[ta] = pa3;
-    if (hb) {
-      sE2[tb] = pb2;
-      sE3[tb] = pb3;
-    }
-    __syncthreads();
-    if (i3 + 1 < z1) {
-      const long long nrow = row + plane;
-      pa2 = ldc(f.E2, nrow, ca);
-      pa3 = ldc(f.E3, nrow, ca);
-      pb2 = ldc(f.E2, nrow, cb);
-      pb3 = ldc(f.E3, nrow, cb);
-    }
+    a2 = ldc(f.E2, row, ca);
+    a3 = ldc(f.E3, row, ca);
+    b2 = ldc(f.E2, row, cb);
+    b3 = ldc(f.E3, row, cb);
     if (own) {
-      const long long id = row + s1;
-      const long long up = r2 + plane * wrap_near(i3 + 1, g.n3) + s1;
-      const Real e1n = f.E1[up], e2n = f.E2[up];
+      const long long id = row + s1, up = r2 + plane * wrap_near(i3 + 1, g.n3) + s1, id2 = r2p + plane * i3 + s1;
+      e1u = f.E1[up];
+      e2u = f.E2[up];
+      e1r = f.E1[id2];
+      e3r = f.E3[id2];
+      q1 = Bin1[id];
+      q2 = Bin2[id];
+      q3 = Bin3[id];
+    }
+  };
+  Real e1 = own ? f.E1[r2 + plane * z0 + s1] : Real(0);
+  fetch(z0);
+  for (int i3 = z0; i3 < z1; ++i3) {
+    sE2[ta] = a2;
+    sE3[ta] = a3;
+    if (hb) {
+      sE2[tb] = b2;
+      sE3[tb] = b3;
+    }
+    const Real ce1u = e1u, ce2u = e2u, ce1r = e1r, ce3r = e3r, cq1 = q1, cq2 = q2, cq3 = q3;
+    __syncthreads();
+    if (i3 + 1 < z1) fetch(i3 + 1);
+    if (own) {
+      const long long id = r2 + plane * i3 + s1;
       Real d1E2 = 0, d1E3 = 0;
       auto term = [&](int l) {
         d1E2 += ax.c[l - 1] * (sE2[c + l] - sE2[c - l + 1]);
@@ -151,22 +162,22 @@ __global__ __launch_bounds__(kSeg) void k_curl_e_col(Geo g, Fields<Real> f, cons
       } else {
         for (int l = 1; l <= M; ++l) term(l);
       }
-      const long long id2 = r2p + plane * i3 + s1;
       const Real e2 = sE2[c], e3 = sE3[c];
-      const Real d2E3 = h2 * (f.E3[id2] - e3);
-      const Real d2E1 = h2 * (f.E1[id2] - e1);
-      const Real d3E2 = h3 * (e2n - e2);
-      const Real d3E1 = h3 * (e1n - e1);
-      Bout1[id] = Bin1[id] - (d2E3 - d3E2);
-      Bout2[id] = Bin2[id] - (d3E1 - d1E3);
-      Bout3[id] = Bin3[id] - (d1E2 - d2E1);
-      e1 = e1n;
+      const Real d2E3 = h2 * (ce3r - e3);
+      const Real d2E1 = h2 * (ce1r - e1);
+      const Real d3E2 = h3 * (ce2u - e2);
+      const Real d3E1 = h3 * (ce1u - e1);
+      Bout1[id] = cq1 - (d2E3 - d3E2);
+      Bout2[id] = cq2 - (d3E1 - d1E3);
+      Bout3[id] = cq3 - (d1E2 - d2E1);
+      e1 = ce1u;
     }
     __syncthreads();
   }
 }
 
-// E += curl- B, marching over x3 (coefficients as in curl_b_tile)
+// E += curl- B, marching over x3 (coefficients as in curl_b_tile), operands
+// of the next plane loaded while the current one is computed
 template <typename Real, int MM>
 __global__ __launch_bounds__(kSeg) void k_curl_b_col(Geo g, Fields<Real> f, Axial<Real> ax, Real e2c, Real e3c) {
   __shared__ Real sB2[stage_pitch<kSeg>()], sB3[stage_pitch<kSeg>()];
@@ -189,26 +200,37 @@ __global__ __launch_bounds__(kSeg) void k_curl_b_col(Geo g, Fields<Real> f, Axia
   const int ta = threadIdx.x, tb = threadIdx.x + kSeg;
   const bool hb = tb < kSeg + 2 * M;
   const int ca = col_of(g, l0 - M + ta), cb = hb ? col_of(g, l0 - M + tb) : -1;
-  Real pa2 = ldc(f.B2, r2 + plane * z0, ca), pa3 = ldc(f.B3, r2 + plane * z0, ca);
-  Real pb2 = ldc(f.B2, r2 + plane * z0, cb), pb3 = ldc(f.B3, r2 + plane * z0, cb);
-  for (int i3 = z0; i3 < z1; ++i3) {
+  Real a2, a3, b2s, b3s;                                           // staged B2, B3
+  Real b1 = 0, b1r = 0, b3r = 0, x1 = 0, x2 = 0, x3 = 0;           // own cell's operands
+  auto fetch = [&](int i3) {
     const long long row = r2 + plane * i3;
-    sB2[ta] = pa2;
-    sB3[ta] = pa3;
-    if (hb) {
-      sB2[tb] = pb2;
-      sB3[tb] = pb3;
-    }
-    __syncthreads();
-    if (i3 + 1 < z1) {
-      const long long nrow = row + plane;
-      pa2 = ldc(f.B2, nrow, ca);
-      pa3 = ldc(f.B3, nrow, ca);
-      pb2 = ldc(f.B2, nrow, cb);
-      pb3 = ldc(f.B3, nrow, cb);
-    }
+    a2 = ldc(f.B2, row, ca);
+    a3 = ldc(f.B3, row, ca);
+    b2s = ldc(f.B2, row, cb);
+    b3s = ldc(f.B3, row, cb);
     if (own) {
-      const long long id = row + s1;
+      const long long id = row + s1, id2 = r2m + plane * i3 + s1;
+      b1 = f.B1[id];
+      b1r = f.B1[id2];
+      b3r = f.B3[id2];
+      x1 = f.E1[id];
+      x2 = f.E2[id];
+      x3 = f.E3[id];
+    }
+  };
+  fetch(z0);
+  for (int i3 = z0; i3 < z1; ++i3) {
+    sB2[ta] = a2;
+    sB3[ta] = a3;
+    if (hb) {
+      sB2[tb] = b2s;
+      sB3[tb] = b3s;
+    }
+    const Real cb1 = b1, cb1r = b1r, cb3r = b3r, cx1 = x1, cx2 = x2, cx3 = x3;
+    __syncthreads();
+    if (i3 + 1 < z1) fetch(i3 + 1);
+    if (own) {
+      const long long id = r2 + plane * i3 + s1;
       Real d1B3 = 0, d1B2 = 0;
       auto term = [&](int l) {
         d1B3 += ax.c[l - 1] * (sB3[c + l - 1] - sB3[c - l]);
@@ -220,17 +242,16 @@ __global__ __launch_bounds__(kSeg) void k_curl_b_col(Geo g, Fields<Real> f, Axia
       } else {
         for (int l = 1; l <= M; ++l) term(l);
       }
-      const long long id2 = r2m + plane * i3 + s1;
-      const Real b1 = f.B1[id], b2 = sB2[c], b3 = sB3[c];
-      const Real d2B3 = e2c * (b3 - f.B3[id2]);
-      const Real d2B1 = e2c * (b1 - f.B1[id2]);
-      const Real d3B2 = e3c * (b2 - b2m);
-      const Real d3B1 = e3c * (b1 - b1m);
-      f.E1[id] += d2B3 - d3B2;
-      f.E2[id] += d3B1 - d1B3;
-      f.E3[id] += d1B2 - d2B1;
-      b1m = b1;
-      b2m = b2;
+      const Real bb2 = sB2[c], bb3 = sB3[c];
+      const Real d2B3 = e2c * (bb3 - cb3r);
+      const Real d2B1 = e2c * (cb1 - cb1r);
+      const Real d3B2 = e3c * (bb2 - b2m);
+      const Real d3B1 = e3c * (cb1 - b1m);
+      f.E1[id] = cx1 + (d2B3 - d3B2);
+      f.E2[id] = cx2 + (d3B1 - d1B3);
+      f.E3[id] = cx3 + (d1B2 - d2B1);
+      b1m = cb1;
+      b2m = bb2;
     }
     __syncthreads();
   }
