@@ -98,6 +98,8 @@ inline Geo make_geo(const relpic_sim *s) {
   g.window = s->grid.bc1 == RELPIC_BC_WINDOW ? 1 : 0;
   g.ws_mod = (int)(((s->ws % s->n[0]) + s->n[0]) % s->n[0]);
   g.N = s->N;
+  g.dv1 = make_fastdiv((unsigned)g.n1);
+  g.dv2 = make_fastdiv((unsigned)g.n2);
   return g;
 }
 

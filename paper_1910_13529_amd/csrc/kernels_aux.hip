@@ -87,10 +87,8 @@ template <typename Real, int DIM>
 __device__ __forceinline__ bool rho_cell(const Geo &g, const Particles<Real> &p, long long i, int c[3]) {
   const int packed = p.cell[i];
   if (packed < 0) return false;
-  const int s1 = packed % g.n1;
-  const int rest = packed / g.n1;
-  c[1] = rest % g.n2;
-  c[2] = DIM == 3 ? rest / g.n2 : 0;
+  int s1;
+  unpack_cell(g, packed, s1, c[1], c[2]);
   c[0] = s1 - g.ws_mod;  // window-relative x1 cell
   if (c[0] < 0) c[0] += g.n1;
   return true;

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kPushBlock) void k_batch_push(const BatchRun<Real> 
                                                            const BatchChunk *__restrict__ chunks, int bnew,
                                                            JBox *chunkbox, int *err) {
   __shared__ __align__(16) unsigned char tile_raw[kTileBytes];
-  __shared__ int box[6];
+  __shared__ int box[kChunkBoxInts];
   const BatchChunk c = chunks[blockIdx.x];
   const BatchPart<Real> &pd = parts[c.part];
   const BatchRun<Real> &r = runs[pd.run];

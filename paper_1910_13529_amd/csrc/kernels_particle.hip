@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
                                                              Particles<Real> p, PushParams<Real> q, int K,
                                                              JBox *blockbox, int *err) {
   __shared__ __align__(16) unsigned char tile_raw[kTileBytes];
-  __shared__ int box[6];
+  __shared__ int box[kChunkBoxInts];
   push_chunk<Real, DIM>(g, f, Bh, p, q, K, blockIdx.x, blockbox + blockIdx.x, err, tile_raw, box);
 }
 

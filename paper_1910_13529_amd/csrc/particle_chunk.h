@@ -10,6 +10,7 @@ namespace relpic {
 
 constexpr int kPushBlock = 256;
 constexpr int kTileBytes = 49152;  // LDS tile per workgroup: J (3 components) + E, B (6)
+constexpr int kChunkBoxInts = 10;  // LDS words of a chunk's box: min/max per axis, tile dividers
 
 typedef __attribute__((address_space(3))) float lds_f32;
 typedef __attribute__((address_space(3))) double lds_f64;
@@ -433,7 +434,7 @@ __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, 
 }
 
 // One workgroup's share of the particle phase: chunk `chunk` of K * 256
-// particles.  tile_raw: kTileBytes of LDS, box: 6 ints of LDS; *mybox
+// particles.  tile_raw: kTileBytes of LDS, box: kChunkBoxInts ints of LDS; *mybox
 // receives the chunk's deposit box.
 template <typename Real, int DIM>
 __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
@@ -457,10 +458,11 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       if (i >= p.n) break;
       const int packed = p.cell[i];
       if (packed < 0) continue;
-      const int s1 = packed % g.n1, rest = packed / g.n1;
+      int s1, c2, c3;
+      unpack_cell(g, packed, s1, c2, c3);
       int c1 = s1 - g.ws_mod;
       if (c1 < 0) c1 += g.n1;
-      const int cc[3] = {c1, rest % g.n2, DIM == 3 ? rest / g.n2 : 0};
+      const int cc[3] = {c1, c2, c3};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         mn[d] = min(mn[d], cc[d]);
@@ -513,7 +515,16 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       mybox->lo[d] = lo[d];
       mybox->hi[d] = hi[d];
     }
+    // dividers for the tile's x1 and x2 extents (old cells +- 2)
+    if (box[0] != INT_MAX) {
+      const FastDiv a = make_fastdiv((unsigned)(box[1] - box[0] + 5)), b = make_fastdiv((unsigned)(box[3] - box[2] + 5));
+      box[6] = (int)a.m;
+      box[7] = a.L;
+      box[8] = (int)b.m;
+      box[9] = b.L;
+    }
   }
+  __syncthreads();
   Sink<Real> sk;
   sk.g = g;
   sk.J[0] = f.J1;
@@ -534,31 +545,28 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       sk.T3 = (int)T3;
       sk.tn = (int)(T1 * T2 * T3);
       sk.tile = tile;
-      // J part cleared; E and B^n staged for the gather (zero outside the window)
+      // J part cleared; E and B^n staged for the gather (zero outside the
+      // window), one tile cell per thread and pass
       const int tn = sk.tn;
-      for (int t = tid; t < 9 * tn; t += kPushBlock) {
-        const int comp = t / tn;
-        Real v = Real(0);
-        if (comp >= 3) {
-          int r = t - comp * tn;
-          const int a = r % sk.T1;
-          r /= sk.T1;
-          const int b = r % sk.T2;
-          const int c = r / sk.T2;
-          const int col = col_of(g, sk.t1 + a);
-          if (col >= 0) {
-            const long long id = (long long)g.n1 * (wrap(sk.t2 + b, g.n2) + (long long)g.n2 * wrap(sk.t3 + c, g.n3)) + col;
-            switch (comp) {
-              case 3: v = f.E1[id]; break;
-              case 4: v = f.E2[id]; break;
-              case 5: v = f.E3[id]; break;
-              case 6: v = Real(0.5) * (f.B1[id] + Bh.B1[id]); break;
-              case 7: v = Real(0.5) * (f.B2[id] + Bh.B2[id]); break;
-              default: v = Real(0.5) * (f.B3[id] + Bh.B3[id]); break;
-            }
-          }
+      const FastDiv d1{(unsigned)box[6], box[7]}, d2{(unsigned)box[8], box[9]};
+      for (int r = tid; r < tn; r += kPushBlock) {
+        const int q1 = (int)fdiv(d1, (unsigned)r), q2 = (int)fdiv(d2, (unsigned)q1);
+        const int col = col_of(g, sk.t1 + r - q1 * sk.T1);
+        Real v[6] = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0)};
+        if (col >= 0) {
+          const long long id = (long long)g.n1 * (wrap_near(sk.t2 + q1 - q2 * sk.T2, g.n2) +
+                                                  (long long)g.n2 * wrap_near(sk.t3 + q2, g.n3)) + col;
+          v[0] = f.E1[id];
+          v[1] = f.E2[id];
+          v[2] = f.E3[id];
+          v[3] = Real(0.5) * (f.B1[id] + Bh.B1[id]);
+          v[4] = Real(0.5) * (f.B2[id] + Bh.B2[id]);
+          v[5] = Real(0.5) * (f.B3[id] + Bh.B3[id]);
         }
-        tile[t] = v;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) tile[k * tn + r] = Real(0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) tile[(3 + k) * tn + r] = v[k];
       }
     }
   }
@@ -580,10 +588,8 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
     }
     m.jz = 0;
     if (active) {
-      const int s1 = packed % g.n1;
-      const int rest = packed / g.n1;
-      const int c2 = rest % g.n2;
-      const int c3 = DIM == 3 ? rest / g.n2 : 0;
+      int s1, c2, c3;
+      unpack_cell(g, packed, s1, c2, c3);
       int c1 = s1 - g.ws_mod;
       if (c1 < 0) c1 += g.n1;
       m.c[0] = c1;
@@ -667,7 +673,8 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       const Real a = q.half_qmdt;
       const Real um1 = p.u1[i] + a * E1, um2 = p.u2[i] + a * E2, um3 = p.u3[i] + a * E3;
       const Real gm = sqrt(Real(1) + um1 * um1 + um2 * um2 + um3 * um3);
-      const Real t1 = a * B1 / gm, t2 = a * B2 / gm, t3 = a * B3 / gm;
+      const Real ag = a / gm;
+      const Real t1 = ag * B1, t2 = ag * B2, t3 = ag * B3;
       const Real t2s = t1 * t1 + t2 * t2 + t3 * t3;
       const Real f2 = Real(2) / (Real(1) + t2s);
       const Real s1v = f2 * t1, s2v = f2 * t2, s3v = f2 * t3;
@@ -716,8 +723,8 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
         p.cell[i] = -1;
       } else {
         const int ns1 = col_of(g, n1c);
-        const int ns2 = wrap(c2 + sh[1], g.n2);
-        const int ns3 = DIM == 3 ? wrap(c3 + sh[2], g.n3) : 0;
+        const int ns2 = wrap_near(c2 + sh[1], g.n2);
+        const int ns3 = DIM == 3 ? wrap_near(c3 + sh[2], g.n3) : 0;
         p.cell[i] = ns1 + g.n1 * (ns2 + g.n2 * ns3);
         p.o1[i] = on[0];
         p.o2[i] = on[1];
@@ -733,21 +740,18 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
   // ---- flush the tile to HBM: one atomic per non-zero point
   if (sk.tile) {
     __syncthreads();
-    for (int t = tid; t < 3 * sk.tn; t += kPushBlock) {
-      const Real v = tile[t];
-      if (v == Real(0)) continue;
-      const int comp = t / sk.tn;
-      int r = t - comp * sk.tn;
-      const int a = r % sk.T1;
-      r /= sk.T1;
-      const int b = r % sk.T2;
-      const int c = r / sk.T2;
-      const int col = col_near(g, sk.t1 + a);
+    const FastDiv d1{(unsigned)box[6], box[7]}, d2{(unsigned)box[8], box[9]};
+    for (int r = tid; r < sk.tn; r += kPushBlock) {
+      const Real v[3] = {tile[r], tile[sk.tn + r], tile[2 * sk.tn + r]};
+      if (v[0] == Real(0) && v[1] == Real(0) && v[2] == Real(0)) continue;
+      const int q1 = (int)fdiv(d1, (unsigned)r), q2 = (int)fdiv(d2, (unsigned)q1);
+      const int col = col_near(g, sk.t1 + r - q1 * sk.T1);
       if (col < 0) continue;
-      const long long row =
-          (long long)g.n1 * (wrap_near(sk.t2 + b, g.n2) + (long long)g.n2 * wrap_near(sk.t3 + c, g.n3));
-      Real *Jc = comp == 0 ? sk.J[0] : (comp == 1 ? sk.J[1] : sk.J[2]);
-      atomicAdd(Jc + row + col, v);
+      const long long id = (long long)g.n1 * (wrap_near(sk.t2 + q1 - q2 * sk.T2, g.n2) +
+                                              (long long)g.n2 * wrap_near(sk.t3 + q2, g.n3)) + col;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (v[k] != Real(0)) atomicAdd(sk.J[k] + id, v[k]);
     }
   }
 }

@@ -9,6 +9,26 @@ namespace relpic {
 constexpr int kMaxM = 32;      // longest axial stencil (2M points)
 constexpr int kMaxTaps = 64;   // half-width bound of the J1 correction FIR
 
+// Division of n < 2^31 by a fixed divisor d >= 1 as a multiply-high, add
+// and shift (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994): with L = ceil(log2 d) and
+// m = floor(2^32 (2^L - d) / d) + 1 < 2^32, n / d = (mulhi(m, n) + n) >> L.
+struct FastDiv {
+  unsigned m;
+  int L;
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(unsigned d) {
+  int L = 0;
+  while ((1ull << L) < d) ++L;
+  FastDiv f;
+  f.m = (unsigned)((((1ull << 32) * ((1ull << L) - d)) / d) + 1);
+  f.L = L;
+  return f;
+}
+
+__device__ __forceinline__ unsigned fdiv(const FastDiv &f, unsigned n) { return (__umulhi(f.m, n) + n) >> f.L; }
+
 // Grid geometry as the kernels see it.  x1 storage is a ring buffer: the
 // storage column of global cell g is g mod n1, window cell l lives at
 // (l + ws_mod) mod n1.
@@ -18,7 +38,17 @@ struct Geo {
   int window;      // 1: values outside window cells [0, n1) read as zero
   int pad_;
   long long N;     // n1 * n2 * n3
+  FastDiv dv1, dv2;  // division by n1 and by n2
 };
+
+// packed storage index -> (storage column, x2 cell, x3 cell)
+__device__ __forceinline__ void unpack_cell(const Geo &g, int packed, int &s1, int &c2, int &c3) {
+  const unsigned q1 = fdiv(g.dv1, (unsigned)packed);
+  const unsigned q2 = fdiv(g.dv2, q1);
+  s1 = packed - (int)q1 * g.n1;
+  c2 = (int)q1 - (int)q2 * g.n2;
+  c3 = (int)q2;
+}
 
 template <typename Real>
 struct Fields {
