@@ -5,6 +5,7 @@
 #include <climits>
 
 #include "kernels.h"
+#include "xlane.h"
 
 namespace relpic {
 
@@ -192,18 +193,25 @@ struct Sink {
 };
 
 // One level of the reduce-scatter: v[0..S) is summed with the partner lane
-// (lane ^ bit); lanes with the bit set keep the upper half.
-template <typename Real, int S>
-__device__ __forceinline__ void rs_level(Real *v, int lane, int bit, int &off) {
+// (lane ^ BIT); lanes with the bit set keep the upper half.
+template <typename Real, int S, int BIT>
+__device__ __forceinline__ void rs_level(Real *v, int lane, int &off) {
   constexpr int H = (S + 1) / 2;
-  const bool up = (lane & bit) != 0;
+  const bool up = (lane & BIT) != 0;
 #pragma unroll
   for (int j = 0; j < H; ++j) {
-    const Real lo = v[j];
-    const Real hi = (j + H < S) ? v[j + H] : Real(0);
-    const Real send = up ? lo : hi;
-    const Real keep = up ? hi : lo;
-    v[j] = keep + __shfl_xor(send, bit, 64);
+    Real lo = v[j];
+    Real hi = (j + H < S) ? v[j + H] : Real(0);
+    if constexpr (BIT >= 16) {
+      // after the swap a lane holds its own kept half and the partner's copy
+      // of that half, in either order
+      swap_lanes<BIT>(lo, hi);
+      v[j] = lo + hi;
+    } else {
+      const Real send = up ? lo : hi;
+      const Real keep = up ? hi : lo;
+      v[j] = keep + xor_lane<BIT>(send);
+    }
   }
   if (up) off += H;
 }
@@ -213,9 +221,28 @@ __device__ __forceinline__ void rs_level(Real *v, int lane, int bit, int &off) {
 template <typename Real, int S, int BIT>
 __device__ __forceinline__ void reduce_scatter(Real *v, int lane, int &off) {
   if constexpr (BIT >= 1) {
-    rs_level<Real, S>(v, lane, BIT, off);
+    rs_level<Real, S, BIT>(v, lane, off);
     reduce_scatter<Real, (S + 1) / 2, BIT / 2>(v, lane, off);
   }
+}
+
+// minimum / maximum over the wavefront, in every lane
+__device__ __forceinline__ int wave_min(int v) {
+  v = min(v, xor_lane<32>(v));
+  v = min(v, xor_lane<16>(v));
+  v = min(v, xor_lane<8>(v));
+  v = min(v, xor_lane<4>(v));
+  v = min(v, xor_lane<2>(v));
+  return min(v, xor_lane<1>(v));
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+  v = max(v, xor_lane<32>(v));
+  v = max(v, xor_lane<16>(v));
+  v = max(v, xor_lane<8>(v));
+  v = max(v, xor_lane<4>(v));
+  v = max(v, xor_lane<2>(v));
+  return max(v, xor_lane<1>(v));
 }
 
 // Sum an N1 x N2 x N3 box of per-lane values v over the wavefront and add the
@@ -309,128 +336,135 @@ __device__ __forceinline__ Real ext5(const Real *in, int o, int b) {
   return o ? c : a;
 }
 
-// Wavefront-collective deposit (every lane of the wave must call it).
-// A lane joins the reduction when it lies in the wave's (x2, x3) row, does not
-// cross a transverse cell boundary this step, and its x1 stencil starts at
-// most one node after the wave's leftmost one.  Its exact supports are then
+// Wavefront-collective deposit (every lane of the wave must call it), in
+// up to kDepositRounds rounds.  In a round the lanes in the (x2, x3) row of
+// the first lane still pending join the reduction if they do not cross a
+// transverse cell boundary this step and their x1 stencil starts at most one
+// node after the leftmost one among them.  Their exact supports are then
 // J1: 4 x 3 x 3 half/node points, J2: 5 x 2 x 3, J3: 5 x 3 x 2 (2D: 4 x 3,
-// 5 x 2, 5 x 3), all inside boxes that every such lane shares.
-// Returns whether this lane's particle still has to be deposited directly.
+// 5 x 2, 5 x 3), all inside boxes that every such lane shares.  A round costs
+// a fraction of the direct path, which the whole wavefront executes as soon as
+// one lane needs it.  Returns whether this lane's particle still has to be
+// deposited directly.
+constexpr int kDepositRounds = 3;
+
 template <typename Real, int DIM>
 __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, const PushParams<Real> &q,
                                              const Sink<Real> &sk) {
   const int lane = threadIdx.x & 63;
-  const unsigned long long act = __ballot(active);
-  if (act == 0ULL) return false;
-  const int first = __ffsll((long long)act) - 1;
-  const int c2w = __shfl(m.c[1], first, 64);
-  const int c3w = __shfl(m.c[2], first, 64);
-  const bool inrow = active && m.c[1] == c2w && (DIM == 2 || m.c[2] == c3w);
-  int cmin = inrow ? m.c[0] : INT_MAX;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) cmin = min(cmin, __shfl_xor(cmin, o, 64));
-  const int o1 = m.c[0] + m.base[0] - (cmin - 1);
   // no transverse crossing: base -1 and no DS on the fourth node
   const bool flat2 = m.base[1] == -1 && m.DS[1][3] == Real(0);
   const bool flat3 = DIM == 2 || (m.base[2] == -1 && m.DS[2][3] == Real(0));
-  const bool fits = inrow && (o1 == 0 || o1 == 1) && flat2 && flat3;
-  const unsigned long long fm = __ballot(fits);
-  if (__popcll(fm) >= 4) {
-    // Branch-free separable form of the exact supports: each box value is an
-    // x1 factor (or x2/x3 running sum) times a transverse Esirkepov weight
-    //   S0a S0b + DSa S0b/2 + S0a DSb/2 + DSa DSb/3 = S0a P_b + DSa Q_b,
-    // P = S0 + DS/2, Q = S0/2 + DS/3; lanes that do not fit contribute 0.
-    const int oo = fits ? o1 : 0;
-    const Real z = fits ? Real(1) : Real(0);
-    Real e1S0[5], e1DS[5];
+  bool pending = active && flat2 && flat3;  // candidates for a reduction round
+  for (int round = 0; round < kDepositRounds; ++round) {
+    const unsigned long long act = __ballot(pending);
+    if (act == 0ULL) break;
+    const int first = __ffsll((long long)act) - 1;
+    const int c2w = __builtin_amdgcn_readlane(m.c[1], first);
+    const int c3w = __builtin_amdgcn_readlane(m.c[2], first);
+    const bool inrow = pending && m.c[1] == c2w && (DIM == 2 || m.c[2] == c3w);
+    // leftmost x1 stencil start among them; the lane that has it always fits
+    const int smin = wave_min(inrow ? m.c[0] + m.base[0] : INT_MAX);
+    const int o1 = m.c[0] + m.base[0] - smin;
+    const bool fits = inrow && (o1 == 0 || o1 == 1);
+    {
+      // Branch-free separable form of the exact supports: each box value is an
+      // x1 factor (or x2/x3 running sum) times a transverse Esirkepov weight
+      //   S0a S0b + DSa S0b/2 + S0a DSb/2 + DSa DSb/3 = S0a P_b + DSa Q_b,
+      // P = S0 + DS/2, Q = S0/2 + DS/3; lanes that do not fit contribute 0.
+      const int oo = fits ? o1 : 0;
+      const Real z = fits ? Real(1) : Real(0);
+      Real e1S0[5], e1DS[5];
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      e1S0[b] = ext5(m.S0[0], oo, b);
-      e1DS[b] = ext5(m.DS[0], oo, b);
+      for (int b = 0; b < 5; ++b) {
+        e1S0[b] = ext5(m.S0[0], oo, b);
+        e1DS[b] = ext5(m.DS[0], oo, b);
+      }
+      // J1 at x1 half points: running sum of DS1 (three entries) shifted by oo
+      Real c1[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const Real lo = (b <= 2) ? m.cum[0][b] : Real(0);
+        const Real hi = (b >= 1 && b <= 3) ? m.cum[0][b - 1] : Real(0);
+        c1[b] = z * q.f1 * (oo ? hi : lo);
+      }
+      Real P2[3], Q2[3], P3[3], Q3[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        P2[k] = m.S0[1][k] + Real(0.5) * m.DS[1][k];
+        Q2[k] = Real(0.5) * m.S0[1][k] + Real(1.0 / 3.0) * m.DS[1][k];
+        P3[k] = m.S0[2][k] + Real(0.5) * m.DS[2][k];
+        Q3[k] = Real(0.5) * m.S0[2][k] + Real(1.0 / 3.0) * m.DS[2][k];
+      }
+      const int x1 = smin, x2 = c2w - 1, x3 = DIM == 3 ? c3w - 1 : 0;
+      if (DIM == 3) {
+        {
+          Real v[36];
+#pragma unroll
+          for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+            for (int a2 = 0; a2 < 3; ++a2) {
+              const Real w = m.S0[1][a2] * P3[a3] + m.DS[1][a2] * Q3[a3];
+#pragma unroll
+              for (int b = 0; b < 4; ++b) v[b + 4 * (a2 + 3 * a3)] = c1[b] * w;
+            }
+          box_reduce_add<Real, 4, 3, 3>(sk, 0, lane, x1, x2, x3, v);
+        }
+        {
+          Real v[30];
+#pragma unroll
+          for (int a3 = 0; a3 < 3; ++a3)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+              const Real w = e1S0[b] * P3[a3] + e1DS[b] * Q3[a3];
+#pragma unroll
+              for (int a2 = 0; a2 < 2; ++a2) v[b + 5 * (a2 + 2 * a3)] = z * q.f2 * m.cum[1][a2] * w;
+            }
+          box_reduce_add<Real, 5, 2, 3>(sk, 1, lane, x1, x2, x3, v);
+        }
+        {
+          Real v[30];
+#pragma unroll
+          for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+              const Real w = e1S0[b] * P2[a2] + e1DS[b] * Q2[a2];
+#pragma unroll
+              for (int a3 = 0; a3 < 2; ++a3) v[b + 5 * (a2 + 3 * a3)] = z * q.f3 * m.cum[2][a3] * w;
+            }
+          box_reduce_add<Real, 5, 3, 2>(sk, 2, lane, x1, x2, x3, v);
+        }
+      } else {
+        {
+          Real v[12];
+#pragma unroll
+          for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v[b + 4 * a2] = c1[b] * P2[a2];
+          box_reduce_add<Real, 4, 3, 1>(sk, 0, lane, x1, x2, 0, v);
+        }
+        {
+          Real v[10];
+#pragma unroll
+          for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) v[b + 5 * a2] = z * q.f2 * m.cum[1][a2] * (e1S0[b] + Real(0.5) * e1DS[b]);
+          box_reduce_add<Real, 5, 2, 1>(sk, 1, lane, x1, x2, 0, v);
+        }
+        {
+          Real v[15];
+#pragma unroll
+          for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) v[b + 5 * a2] = z * m.jz * (e1S0[b] * P2[a2] + e1DS[b] * Q2[a2]);
+          box_reduce_add<Real, 5, 3, 1>(sk, 2, lane, x1, x2, 0, v);
+        }
+      }
+      pending = pending && !fits;
     }
-    // J1 at x1 half points: running sum of DS1 (three entries) shifted by oo
-    Real c1[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const Real lo = (b <= 2) ? m.cum[0][b] : Real(0);
-      const Real hi = (b >= 1 && b <= 3) ? m.cum[0][b - 1] : Real(0);
-      c1[b] = z * q.f1 * (oo ? hi : lo);
-    }
-    Real P2[3], Q2[3], P3[3], Q3[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      P2[k] = m.S0[1][k] + Real(0.5) * m.DS[1][k];
-      Q2[k] = Real(0.5) * m.S0[1][k] + Real(1.0 / 3.0) * m.DS[1][k];
-      P3[k] = m.S0[2][k] + Real(0.5) * m.DS[2][k];
-      Q3[k] = Real(0.5) * m.S0[2][k] + Real(1.0 / 3.0) * m.DS[2][k];
-    }
-    const int x1 = cmin - 1, x2 = c2w - 1, x3 = DIM == 3 ? c3w - 1 : 0;
-    if (DIM == 3) {
-      {
-        Real v[36];
-#pragma unroll
-        for (int a3 = 0; a3 < 3; ++a3)
-#pragma unroll
-          for (int a2 = 0; a2 < 3; ++a2) {
-            const Real w = m.S0[1][a2] * P3[a3] + m.DS[1][a2] * Q3[a3];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) v[b + 4 * (a2 + 3 * a3)] = c1[b] * w;
-          }
-        box_reduce_add<Real, 4, 3, 3>(sk, 0, lane, x1, x2, x3, v);
-      }
-      {
-        Real v[30];
-#pragma unroll
-        for (int a3 = 0; a3 < 3; ++a3)
-#pragma unroll
-          for (int b = 0; b < 5; ++b) {
-            const Real w = e1S0[b] * P3[a3] + e1DS[b] * Q3[a3];
-#pragma unroll
-            for (int a2 = 0; a2 < 2; ++a2) v[b + 5 * (a2 + 2 * a3)] = z * q.f2 * m.cum[1][a2] * w;
-          }
-        box_reduce_add<Real, 5, 2, 3>(sk, 1, lane, x1, x2, x3, v);
-      }
-      {
-        Real v[30];
-#pragma unroll
-        for (int a2 = 0; a2 < 3; ++a2)
-#pragma unroll
-          for (int b = 0; b < 5; ++b) {
-            const Real w = e1S0[b] * P2[a2] + e1DS[b] * Q2[a2];
-#pragma unroll
-            for (int a3 = 0; a3 < 2; ++a3) v[b + 5 * (a2 + 3 * a3)] = z * q.f3 * m.cum[2][a3] * w;
-          }
-        box_reduce_add<Real, 5, 3, 2>(sk, 2, lane, x1, x2, x3, v);
-      }
-    } else {
-      {
-        Real v[12];
-#pragma unroll
-        for (int a2 = 0; a2 < 3; ++a2)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) v[b + 4 * a2] = c1[b] * P2[a2];
-        box_reduce_add<Real, 4, 3, 1>(sk, 0, lane, x1, x2, 0, v);
-      }
-      {
-        Real v[10];
-#pragma unroll
-        for (int a2 = 0; a2 < 2; ++a2)
-#pragma unroll
-          for (int b = 0; b < 5; ++b) v[b + 5 * a2] = z * q.f2 * m.cum[1][a2] * (e1S0[b] + Real(0.5) * e1DS[b]);
-        box_reduce_add<Real, 5, 2, 1>(sk, 1, lane, x1, x2, 0, v);
-      }
-      {
-        Real v[15];
-#pragma unroll
-        for (int a2 = 0; a2 < 3; ++a2)
-#pragma unroll
-          for (int b = 0; b < 5; ++b) v[b + 5 * a2] = z * m.jz * (e1S0[b] * P2[a2] + e1DS[b] * Q2[a2]);
-        box_reduce_add<Real, 5, 3, 1>(sk, 2, lane, x1, x2, 0, v);
-      }
-    }
-    return active && !fits;
   }
-  return active;
+  // lanes left: crossing a transverse boundary, or beyond the rounds
+  return active && (pending || !(flat2 && flat3));
 }
 
 // One workgroup's share of the particle phase: chunk `chunk` of K * 256
@@ -471,11 +505,8 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        mn[d] = min(mn[d], __shfl_xor(mn[d], o, 64));
-        mx[d] = max(mx[d], __shfl_xor(mx[d], o, 64));
-      }
+      mn[d] = wave_min(mn[d]);
+      mx[d] = wave_max(mx[d]);
     }
     if ((tid & 63) == 0 && mn[0] != INT_MAX) {
 #pragma unroll
