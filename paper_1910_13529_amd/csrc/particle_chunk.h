@@ -337,16 +337,21 @@ __device__ __forceinline__ Real ext5(const Real *in, int o, int b) {
 }
 
 // Wavefront-collective deposit (every lane of the wave must call it), in
-// up to kDepositRounds rounds.  In a round the lanes in the (x2, x3) row of
-// the first lane still pending join the reduction if they do not cross a
-// transverse cell boundary this step and their x1 stencil starts at most one
-// node after the leftmost one among them.  Their exact supports are then
-// J1: 4 x 3 x 3 half/node points, J2: 5 x 2 x 3, J3: 5 x 3 x 2 (2D: 4 x 3,
-// 5 x 2, 5 x 3), all inside boxes that every such lane shares.  A round costs
-// a fraction of the direct path, which the whole wavefront executes as soon as
-// one lane needs it.  Returns whether this lane's particle still has to be
-// deposited directly.
-constexpr int kDepositRounds = 3;
+// rounds.  In a round the pending lanes in the (x2, x3) row of the first
+// pending lane join the reduction if their x1 stencil starts at most one node
+// after the leftmost one among them (that lane always joins, so every round
+// retires at least one lane).  Their exact supports are then J1: 4 x 3 x 3
+// half/node points, J2: 5 x 2 x 3, J3: 5 x 3 x 2 (2D: 4 x 3, 5 x 2, 5 x 3),
+// all inside boxes that every such lane shares.  Lanes that cross a
+// transverse cell boundary this step (a four-node transverse support) are not
+// pending and go to the direct path, which the whole wavefront executes as
+// soon as one lane needs it.  In 3D a round costs a fraction of it (144
+// stencil points against 96 reduced values), so rounds run until no pending
+// lane is left; in 2D (40 points against 37 values) after kDepositRounds2D
+// rounds the rest goes direct.  Returns whether this lane's particle still
+// has to be deposited directly.
+constexpr int kDepositRounds = 64;
+constexpr int kDepositRounds2D = 3;
 
 template <typename Real, int DIM>
 __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, const PushParams<Real> &q,
@@ -356,7 +361,7 @@ __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, 
   const bool flat2 = m.base[1] == -1 && m.DS[1][3] == Real(0);
   const bool flat3 = DIM == 2 || (m.base[2] == -1 && m.DS[2][3] == Real(0));
   bool pending = active && flat2 && flat3;  // candidates for a reduction round
-  for (int round = 0; round < kDepositRounds; ++round) {
+  for (int round = 0; round < (DIM == 3 ? kDepositRounds : kDepositRounds2D); ++round) {
     const unsigned long long act = __ballot(pending);
     if (act == 0ULL) break;
     const int first = __ffsll((long long)act) - 1;
@@ -604,10 +609,28 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
   __syncthreads();
   const bool lds_fields = sk.tile != nullptr;
 
-  // ---- gather, push, move and deposit, K particles per thread
+  // ---- gather, push, move and deposit, K particles per thread; the next
+  // particle's state is loaded while the current one is pushed
+  int nx_cell = -1;
+  Real nx_o[3] = {Real(0), Real(0), Real(0)}, nx_u[3] = {Real(0), Real(0), Real(0)};
+  auto load_state = [&](long long j) {
+    nx_cell = -1;
+    if (j < p.n) {
+      nx_cell = p.cell[j];
+      nx_o[0] = p.o1[j];
+      nx_o[1] = p.o2[j];
+      if (DIM == 3) nx_o[2] = p.o3[j];
+      nx_u[0] = p.u1[j];
+      nx_u[1] = p.u2[j];
+      nx_u[2] = p.u3[j];
+    }
+  };
+  load_state(chunk0 + tid);
   for (int k = 0; k < K; ++k) {
     const long long i = chunk0 + (long long)k * kPushBlock + tid;
-    const int packed = (i < p.n) ? p.cell[i] : -1;
+    const int packed = nx_cell;
+    const Real o[3] = {nx_o[0], nx_o[1], nx_o[2]}, u0[3] = {nx_u[0], nx_u[1], nx_u[2]};
+    if (k + 1 < K) load_state(i + kPushBlock);
     const bool active = packed >= 0;
     Moved<Real> m;
 #pragma unroll
@@ -626,7 +649,6 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       m.c[0] = c1;
       m.c[1] = c2;
       m.c[2] = c3;
-      const Real o[3] = {p.o1[i], p.o2[i], DIM == 3 ? p.o3[i] : Real(0)};
 
       Real E1, E2, E3, B1, B2, B3;
       Stagger<Real> st;
@@ -702,7 +724,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
 
       // relativistic Boris push
       const Real a = q.half_qmdt;
-      const Real um1 = p.u1[i] + a * E1, um2 = p.u2[i] + a * E2, um3 = p.u3[i] + a * E3;
+      const Real um1 = u0[0] + a * E1, um2 = u0[1] + a * E2, um3 = u0[2] + a * E3;
       const Real gm = sqrt(Real(1) + um1 * um1 + um2 * um2 + um3 * um3);
       const Real ag = a / gm;
       const Real t1 = ag * B1, t2 = ag * B2, t3 = ag * B3;
