@@ -35,6 +35,8 @@ def algorithmic_bytes(kernel, ncells, npart, esz):
         return ncells * 9 * esz
     if kernel == "curl_b":         # B read, E read + written
         return ncells * 9 * esz
+    if kernel == "leap":           # fused: E and B read once, E and the next B written once
+        return ncells * 12 * esz
     return 0
 
 
@@ -93,6 +95,10 @@ def run_gpu(args, w, cell, off, u, Q, solver):
     sim = Sim(grid, C=TABLE1_C if solver == "custom" else None, precision=args.precision)
     sid = sim.add_species(-1.0, Q, len(cell))
     sim.load_particles(sid, cell, off, u)
+    try:
+        fused = sim.set_fused_fields(not args.separate_fields)
+    except RuntimeError:
+        fused = False
     stream = torch.cuda.current_stream()
     sim.step(args.warmup)
     sim.sync()
@@ -115,7 +121,7 @@ def run_gpu(args, w, cell, off, u, Q, solver):
     sim.profile_enable(False)
     diag = sim.diagnostics()
     sim.close()
-    return dict(wall_s=wall, event_ms=ev_ms, prof=prof, diag=diag, nprof=nprof)
+    return dict(wall_s=wall, event_ms=ev_ms, prof=prof, diag=diag, nprof=nprof, fused=fused)
 
 
 def run_batch(args):
@@ -341,6 +347,8 @@ def main():
     ap.add_argument("--npart", type=int, default=1 << 22)
     ap.add_argument("--solvers", default="custom,yee")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--separate-fields", action="store_true",
+                    help="3D beam: separate E and B updates instead of the fused one")
     ap.add_argument("--workload", default="beam3d", choices=["beam3d", "batch", "adjoint"],
                     help="beam3d: the 3D beam (default); batch: the 256-run batched workload; "
                          "adjoint: time per gradient of the differentiable case")
@@ -384,7 +392,9 @@ def main():
     ms = 1e3 * r["wall_s"] / args.steps
     cell_rate = ncells * args.steps / r["wall_s"]
     part_rate = npart * args.steps / r["wall_s"]
-    step_bytes = ncells * 18 * esz + npart * 2 * (4 + 6 * esz)  # E, B read + written; particle state
+    # E, B read + written once (fused update: 12 words per cell; separate
+    # updates: 18, the second one reading E and B again); particle state
+    step_bytes = ncells * (12 if r["fused"] else 18) * esz + npart * 2 * (4 + 6 * esz)
 
     # dominant kernel and its roofline: the push is bound by instruction issue
     # (ALU roofline, algorithmic flops), the field updates by HBM
@@ -434,6 +444,7 @@ def main():
             "cells": ncells,
             "particles": npart,
             "particle_sort_interval": 25,
+            "fused_field_update": r["fused"],
             "parallelism": "single GPU",
         },
         "roofline": ({
@@ -467,7 +478,7 @@ def main():
                 "traffic": traffic_of.get(k),
                 "avg_launch_ms": prof[k][1] / prof[k][0],
                 "algorithmic_bytes_per_launch": algorithmic_bytes(k, ncells, npart, esz)}
-            for k in ("curl_e", "curl_b") if prof.get(k, (0, 0))[0] > 0},
+            for k in ("curl_e", "curl_b", "leap") if prof.get(k, (0, 0))[0] > 0},
         "kernel_ms_per_step": {k: prof[k][1] / r["nprof"] for k in prof if prof[k][0]},
         "diag": {k: r["diag"][k] for k in ("step", "window_start", "n_alive", "w_field", "w_kin", "error_word")},
     }

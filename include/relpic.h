@@ -195,6 +195,23 @@ relpic_status relpic_read_particles(relpic_sim *sim, int species, int64_t cap, i
 relpic_status relpic_sort_particles(relpic_sim *sim);
 relpic_status relpic_set_sort_interval(relpic_sim *sim, int64_t interval);
 
+/* Fused field update (a5), 3D grids only.  The leapfrog of Eq. 1 advances E
+ * from step n to n + 1 and B from n + 1/2 to n + 3/2 in one pass over the
+ * grid when no window shift falls between them (and to n + 1 at the end of a
+ * relpic_step call): E^{n+1} = E^n + dt (curl- B^{n+1/2} - J^{n+1/2}), then
+ * B^{n+3/2} = B^{n+1/2} - dt curl+ E^{n+1}, reading and writing each field
+ * once (12 words per cell instead of 18).  The results are those of the
+ * separate updates up to floating-point contraction.  It needs whole x1
+ * lines in one workgroup (n1 <= 512, n1 >= 2 x the staged halo: 2 for Yee,
+ * 32 for M = 16, 64 otherwise), n2 even, and a
+ * second set of E arrays (3 n1 n2 n3 values, allocated at creation when the
+ * grid qualifies; the E buffers alternate between the two sets, so device
+ * pointers from relpic_field_device_ptr for E are valid only until the next
+ * relpic_step).  On by default where supported; enable = 1 on a grid that
+ * does not qualify returns RELPIC_EINVAL.  *active (may be null) receives
+ * whether the fused update is in use. */
+relpic_status relpic_set_fused_fields(relpic_sim *sim, int enable, int *active);
+
 /* FP64 diagnostics (synchronizing). */
 relpic_status relpic_diagnostics(relpic_sim *sim, relpic_diag *out);
 
@@ -207,9 +224,10 @@ relpic_status relpic_correction_halfwidth(relpic_sim *sim, int *halfwidth);
 /* Per-kernel timing with HIP events recorded on the bound stream around every
  * launch (adds a small gap between launches; off by default).  Kernel classes:
  * 0 push+deposit, 1 J1 correction, 2 B update (curl E), 3 E update (curl B),
- * 4 window shift and injection, 5 current added to E inside the deposit box,
- * 6 merge of the push workgroups' deposit boxes. */
-#define RELPIC_NUM_KERNEL_CLASSES 7
+ * 4 window shift and injection, 5 current added to E inside the deposit box
+ * (or, after a fused update, cleared there), 6 merge of the push workgroups'
+ * deposit boxes, 7 fused E and B update. */
+#define RELPIC_NUM_KERNEL_CLASSES 8
 typedef struct {
   int64_t launches[RELPIC_NUM_KERNEL_CLASSES];
   double total_ms[RELPIC_NUM_KERNEL_CLASSES];

@@ -160,6 +160,10 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
   }
   swapB();
   relpic_status status = RELPIC_OK;
+  // With the fused update, the step's E update also produces the next B:
+  // b_ahead = B^{n+1/2} of the coming step is already in Bb, b_final = the
+  // last step produced B^{n+1} (the epilogue) itself.
+  bool b_ahead = false, b_final = false;
   for (long long it = 0; it < nsteps; ++it) {
     for (auto &sp : s->sp)
       if (sp.dirty || (s->sort_interval > 0 && s->step - sp.sorted_at >= s->sort_interval))
@@ -178,10 +182,11 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
     JBox *box = s->jbox + (s->step & 1);
     JBox *next = s->jbox + ((s->step + 1) & 1);
     // B^{n+1/2} = B^{n-1/2} - dt curl+ E^n
-    {
+    if (!b_ahead) {
       ProfScope ps(s, 2);
       curl_e<Real>(s, g, Ba, Bb, dt);
     }
+    b_ahead = false;
     Fields<Real> f = fields<Real>(s);
     f.B1 = Ba[0];
     f.B2 = Ba[1];
@@ -216,13 +221,34 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
     f.B1 = Bb[0];
     f.B2 = Bb[1];
     f.B3 = Bb[2];
-    {
-      ProfScope ps(s, 3);
-      launch_curl_b<Real>(s->ndim, g, f, axE, e2, e3, s->st);
-    }
-    {
-      ProfScope ps(s, 5);
-      launch_add_j<Real>(g, f, J1src, (Real)dt, box, s->M > 1 ? s->ng : 0, next, s->st);
+    if (s->fuse && !shift) {
+      // fused: also B^{n+3/2} (or B^{n+1} after the last step) into Ba,
+      // which held B^{n-1/2}; E^{n+1} into the second E buffer
+      const bool last = it + 1 == nsteps;
+      const double fb = last ? 0.5 * dt : dt;
+      Real *Ein[3] = {f.E1, f.E2, f.E3};
+      Real *Eout[3] = {(Real *)s->Ex[0], (Real *)s->Ex[1], (Real *)s->Ex[2]};
+      {
+        ProfScope ps(s, 7);
+        launch_leap<Real>(g, Ein, Eout, Bb, Ba, J1src, f.J2, f.J3, box, s->M > 1 ? s->ng : 0, (Real)dt, axE, e2, e3,
+                          axial_scaled<Real>(s, fb), (Real)(fb / s->dx[1]), (Real)(fb / s->dx[2]), s->st);
+      }
+      {
+        ProfScope ps(s, 5);
+        launch_clear_j<Real>(g, f, box, s->M > 1 ? s->ng : 0, next, s->st);
+      }
+      for (int d = 0; d < 3; ++d) std::swap(s->F[d], s->Ex[d]);
+      b_ahead = !last;
+      b_final = last;
+    } else {
+      {
+        ProfScope ps(s, 3);
+        launch_curl_b<Real>(s->ndim, g, f, axE, e2, e3, s->st);
+      }
+      {
+        ProfScope ps(s, 5);
+        launch_add_j<Real>(g, f, J1src, (Real)dt, box, s->M > 1 ? s->ng : 0, next, s->st);
+      }
     }
     swapB();
     s->step += 1;
@@ -252,7 +278,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
     }
   }
   // epilogue: B^{n+1} = B^{n+1/2} - (dt/2) curl+ E^{n+1}, back in the canonical buffer
-  {
+  if (!b_final) {
     ProfScope ps(s, 2);
     curl_e<Real>(s, make_geo(s), Ba, Bb, 0.5 * dt);
   }
@@ -426,6 +452,16 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
       return fail(RELPIC_ENOMEM, "create: field allocation failed");
     }
   }
+  // second E buffer for the fused update, where the grid qualifies (the
+  // separate updates remain if it cannot be allocated)
+  if (grid->ndim == 3 && (prec == RELPIC_FP32 ? leap_supported<float>(make_geo(s), M)
+                                              : leap_supported<double>(make_geo(s), M))) {
+    bool ok = true;
+    for (int d = 0; d < 3 && ok; ++d) ok = (s->Ex[d] = dev_alloc(s, s->esz * N)) != nullptr;
+    s->fuse = ok;
+    if (!ok)
+      for (int d = 0; d < 3; ++d) s->Ex[d] = nullptr;
+  }
   s->jbox = (JBox *)dev_alloc(s, 2 * sizeof(JBox));
   s->err = (int *)dev_alloc(s, 64);
   s->dbuf = (double *)dev_alloc(s, 8 * sizeof(double));
@@ -440,6 +476,8 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
   for (int k = 0; k < 10 && e == hipSuccess; ++k)
     if (s->F[k]) e = hipMemsetAsync(s->F[k], 0, s->esz * N, s->st);
   for (int d = 0; d < 3 && e == hipSuccess; ++d) e = hipMemsetAsync(s->Bx[d], 0, s->esz * N, s->st);
+  for (int d = 0; d < 3 && e == hipSuccess; ++d)
+    if (s->Ex[d]) e = hipMemsetAsync(s->Ex[d], 0, s->esz * N, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->err, 0, 64, s->st);
   if (e == hipSuccess) {
     launch_reset_box(s->jbox, s->st);
@@ -764,6 +802,18 @@ relpic_status relpic_set_sort_interval(relpic_sim *s, int64_t interval) {
   if (relpic_status r = check_sim(s)) return r;
   if (interval < 0) return fail(RELPIC_EINVAL, "sort interval must be >= 0");
   s->sort_interval = interval;
+  return RELPIC_OK;
+}
+
+relpic_status relpic_set_fused_fields(relpic_sim *s, int enable, int *active) {
+  if (relpic_status r = check_sim(s)) return r;
+  if (enable && !s->Ex[0]) {
+    if (active) *active = 0;
+    return fail(RELPIC_EINVAL, "fused field update: not available on this grid (3D, n1 <= 512, n2 even, n1 at "
+                               "least twice the staged halo)");
+  }
+  s->fuse = enable != 0;
+  if (active) *active = s->fuse ? 1 : 0;
   return RELPIC_OK;
 }
 

@@ -57,6 +57,8 @@ struct relpic_sim {
   long long N = 0;
   void *F[10] = {};  // E1 E2 E3 B1 B2 B3 J1 J2 J3 J1c; B holds B^n between calls
   void *Bx[3] = {};  // second B buffer (B at the other half-integer time inside a call)
+  void *Ex[3] = {};  // second E buffer for the fused update (3D grids that qualify)
+  bool fuse = false; // fused E and B update in use
   relpic::JBox *jbox = nullptr;  // two deposit boxes, alternating by step parity
   relpic::JBox *blockbox = nullptr;  // per-workgroup deposit boxes of the push kernel
   long long blockbox_n = 0;

@@ -210,6 +210,26 @@ __device__ __forceinline__ void add_j_box(const Geo &g, Real *E1, Real *E2, Real
   }
 }
 
+// J cleared over the deposit box (x1 widened by pad)
+template <typename Real>
+__device__ __forceinline__ void clear_j_box(const Geo &g, Real *J1, Real *J2, Real *J3, const JBox &b, int pad,
+                                            long long t0, long long stride) {
+  int lo1, hi1;
+  if (!box_x1(g, b, pad, lo1, hi1)) return;
+  const long long w1 = hi1 - lo1 + 1, w2 = b.hi[1] - b.lo[1] + 1, w3 = b.hi[2] - b.lo[2] + 1;
+  const long long tot = w1 * w2 * w3;
+  for (long long t = t0; t < tot; t += stride) {
+    const int a = (int)(t % w1);
+    const long long r = t / w1;
+    const int i2 = b.lo[1] + (int)(r % w2);
+    const int i3 = b.lo[2] + (int)(r / w2);
+    const long long id = (long long)g.n1 * (i2 + (long long)g.n2 * i3) + col_of(g, lo1 + a);
+    J1[id] = Real(0);
+    J2[id] = Real(0);
+    J3[id] = Real(0);
+  }
+}
+
 // J1c = G * J1 along x1 inside the deposit box (x1 widened by ng)
 template <typename Real>
 __device__ __forceinline__ void jcorr_box(const Geo &g, const Real *J1, Real *J1c, const Real *taps, int ng,

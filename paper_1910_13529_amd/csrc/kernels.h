@@ -35,6 +35,21 @@ template <typename Real>
 void launch_new_slab(const Geo &g, const Fields<Real> &f, Real *const Bx[3], int col, const Axial<Real> &ax,
                      hipStream_t st);
 void launch_reset_box(JBox *b, hipStream_t st);
+// J cleared inside the J box (x1 widened by pad), `next` box reset
+template <typename Real>
+void launch_clear_j(const Geo &g, const Fields<Real> &f, const JBox *box, int pad, JBox *next, hipStream_t st);
+
+// Fused 3D update: Eout = Ein + dt curl- B - dt J (inside the box; J1s is J1
+// or the corrected J1c), then Bout = B - curl+ Eout with the time factor
+// folded into axB, h2, h3; axE, e2c, e3c carry dt.  Ein, Eout, B, Bout
+// distinct.  Only for grids where leap_supported holds.
+template <typename Real>
+bool leap_supported(const Geo &g, int M);
+template <typename Real>
+void launch_leap(const Geo &g, Real *const Ein[3], Real *const Eout[3], Real *const B[3], Real *const Bout[3],
+                 const Real *J1s, const Real *J2, const Real *J3, const JBox *box, int pad, Real dt,
+                 const Axial<Real> &axE, Real e2c, Real e3c, const Axial<Real> &axB, Real h2, Real h3,
+                 hipStream_t st);
 
 // K particles per thread; each workgroup handles a contiguous chunk of
 // 256 * K particles (sorted by cell for the LDS-tiled deposit to pay off)

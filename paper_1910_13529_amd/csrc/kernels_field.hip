@@ -273,6 +273,20 @@ __global__ __launch_bounds__(256) void k_add_j(Geo g, Fields<Real> f, const Real
             blockIdx.x * (long long)blockDim.x + threadIdx.x, (long long)gridDim.x * blockDim.x);
 }
 
+// J cleared over the box of deposited current (the fused update has added
+// it to E); one thread resets the box used by the next step's deposit.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_clear_j(Geo g, Fields<Real> f, const JBox *box, int pad, JBox *next) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int d = 0; d < 3; ++d) {
+      next->lo[d] = 0x7fffffff;
+      next->hi[d] = -0x7fffffff;
+    }
+  }
+  clear_j_box(g, f.J1, f.J2, f.J3, *box, pad, blockIdx.x * (long long)blockDim.x + threadIdx.x,
+              (long long)gridDim.x * blockDim.x);
+}
+
 // J1c = G * J1 along x1 inside the current box (x1 widened by ng): FIR with
 // taps g_0..g_ng (even in m), zero outside the window or wrapped on a
 // periodic line.
@@ -406,6 +420,11 @@ void launch_add_j(const Geo &g, const Fields<Real> &f, const Real *J1src, Real d
 }
 
 template <typename Real>
+void launch_clear_j(const Geo &g, const Fields<Real> &f, const JBox *box, int pad, JBox *next, hipStream_t st) {
+  k_clear_j<Real><<<1024, 256, 0, st>>>(g, f, box, pad, next);
+}
+
+template <typename Real>
 void launch_jcorr(const Geo &g, const Real *J1, Real *J1c, const Real *taps, int ng, const JBox *box,
                   hipStream_t st) {
   k_jcorr<Real><<<1024, 256, 0, st>>>(g, J1, J1c, taps, ng, box);
@@ -427,6 +446,7 @@ void launch_reset_box(JBox *b, hipStream_t st) { k_reset_box<<<1, 64, 0, st>>>(b
                                     hipStream_t);                                                                 \
   template void launch_add_j<Real>(const Geo &, const Fields<Real> &, const Real *, Real, const JBox *, int,     \
                                    JBox *, hipStream_t);                                                          \
+  template void launch_clear_j<Real>(const Geo &, const Fields<Real> &, const JBox *, int, JBox *, hipStream_t); \
   template void launch_jcorr<Real>(const Geo &, const Real *, Real *, const Real *, int, const JBox *,            \
                                    hipStream_t);                                                                  \
   template void launch_new_slab<Real>(const Geo &, const Fields<Real> &, Real *const[3], int, const Axial<Real> &, \

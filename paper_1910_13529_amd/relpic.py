@@ -25,13 +25,13 @@ EXPORTS = (
     "relpic_set_injection", "relpic_set_background_rho", "relpic_step", "relpic_sync", "relpic_read_field",
     "relpic_write_field", "relpic_field_device_ptr", "relpic_read_particles", "relpic_diagnostics",
     "relpic_get_step", "relpic_correction_halfwidth", "relpic_profile_enable", "relpic_profile_read",
-    "relpic_sort_particles", "relpic_set_sort_interval", "relpic_batch_create", "relpic_batch_destroy",
+    "relpic_sort_particles", "relpic_set_sort_interval", "relpic_set_fused_fields", "relpic_batch_create", "relpic_batch_destroy",
     "relpic_batch_run", "relpic_batch_step", "relpic_batch_sync", "relpic_batch_set_graph_steps",
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
     "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
     "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_self_force", "relpic_last_error",
 )
-KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes")
+KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes", "leap")
 
 
 class RelpicError(RuntimeError):
@@ -69,7 +69,7 @@ class Diag(ctypes.Structure):
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 7), ("total_ms", ctypes.c_double * 7)]
+    _fields_ = [("launches", ctypes.c_int64 * len(KERNEL_CLASSES)), ("total_ms", ctypes.c_double * len(KERNEL_CLASSES))]
 
 
 class BatchTune(ctypes.Structure):
@@ -137,6 +137,7 @@ def load():
                                         ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.relpic_sort_particles.argtypes = [P]
     L.relpic_set_sort_interval.argtypes = [P, I64]
+    L.relpic_set_fused_fields.argtypes = [P, ctypes.c_int, ip]
     L.relpic_diagnostics.argtypes = [P, ctypes.POINTER(Diag)]
     L.relpic_get_step.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.relpic_correction_halfwidth.argtypes = [P, ip]
@@ -358,6 +359,12 @@ class SimOps:
 
     def set_sort_interval(self, n):
         check(load().relpic_set_sort_interval(self.h, int(n)))
+
+    def set_fused_fields(self, enable):
+        """Fused E and B update (3D grids that qualify); returns whether it is active."""
+        a = ctypes.c_int(0)
+        check(load().relpic_set_fused_fields(self.h, 1 if enable else 0, ctypes.byref(a)))
+        return bool(a.value)
 
     def diagnostics(self):
         d = Diag()

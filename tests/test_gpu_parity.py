@@ -149,6 +149,65 @@ def test_rho_diagnostic_layouts_fp64(ndim, layout):
     g.sync()
 
 
+def _beam_sim(n, dx, dt, C, window, sp, precision):
+    from paper_1910_13529_amd.relpic import Sim
+    grid = dict(ndim=3, n=tuple(n), dx=tuple(dx), dt=dt, window=window, window_speed=1.0)
+    g = Sim(grid, C=list(C) if len(C) > 1 else None, precision=precision)
+    Q, qm, cell, off, u, cap = sp
+    sid = g.add_species(qm, Q, cap)
+    g.load_particles(sid, cell, off, u)
+    return g, sid
+
+
+@pytest.mark.parametrize("solver", ["yee", "custom"])
+@pytest.mark.parametrize("window", [False, True])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_fused_field_update_matches_separate(solver, window, precision, tol):
+    # the fused E and B update (one pass per step) against the separate
+    # updates on the same run: n3 = 40 is one full column of 32 planes and a
+    # partial one, the window shifts every 2.5 steps (shift steps take the
+    # separate updates), and calls of 7, 1, 1 and 12 steps end with the fused
+    # epilogue
+    n, dx, dt = (64, 12, 40), (0.5, 1.0, 1.0), 0.2
+    C = (1.0,) if solver == "yee" else TABLE1
+    sp = beam_species(5, 3000, n, dx, 50.0, Q=-0.02, sigma_cells=(4.0, 1.5, 1.5), center_frac=0.5,
+                      divergence=0.02, espread=0.02)
+    fields = {}
+    for fused in (True, False):
+        g, sid = _beam_sim(n, dx, dt, C, window, sp, precision)
+        assert g.set_fused_fields(fused) == fused
+        for k in (7, 1, 1, 12):
+            g.step(k)
+        fields[fused] = {nm: g.field(nm) for nm in ("E1", "E2", "E3", "B1", "B2", "B3")}
+        fields[fused]["x"] = g.particles(sid, 3000)
+        g.sync()
+    log("fused vs separate %s window=%s %s" % (solver, window, precision))
+    for grp in ("E", "B"):
+        scale = max(float(np.abs(fields[False][grp + c]).max()) for c in "123")
+        assert scale > 0
+        for c in "123":
+            d = float(np.abs(fields[True][grp + c] - fields[False][grp + c]).max())
+            assert d <= tol * scale, (grp + c, d, scale)
+    (ca, oa, ua, aa), (cb, ob, ub, ab) = fields[True]["x"], fields[False]["x"]
+    assert (aa == ab).all()
+    assert np.abs((ca + oa) - (cb + ob))[aa].max() < 10 * tol
+
+
+def test_fused_field_update_availability():
+    from paper_1910_13529_amd.relpic import RelpicError, Sim
+    g3 = Sim(dict(ndim=3, n=(64, 8, 8), dx=(1.0, 1.0, 1.0), dt=0.3), precision="fp32")
+    assert g3.set_fused_fields(True)
+    assert not g3.set_fused_fields(False)
+    g2 = Sim(dict(ndim=2, n=(64, 8, 1), dx=(1.0, 1.0, 1.0), dt=0.3), precision="fp32")
+    with pytest.raises(RelpicError):
+        g2.set_fused_fields(True)
+    assert not g2.set_fused_fields(False)
+    # odd x2 extent (the row block is two rows)
+    g3b = Sim(dict(ndim=3, n=(64, 7, 8), dx=(1.0, 1.0, 1.0), dt=0.3), precision="fp32")
+    with pytest.raises(RelpicError):
+        g3b.set_fused_fields(True)
+
+
 def test_plasma_injection_window_fp64():
     # cold plasma ahead of a beam in the moving window: the window injects a
     # slab of 2x2x2 particles per cell at each shift, momenta from the shared
