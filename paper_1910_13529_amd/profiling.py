@@ -49,6 +49,7 @@ def kernel_class(name):
 
 
 def short_name(name):
+    name = name.replace("(anonymous namespace)::", "")
     m = re.match(r"(?:void )?([\w:]+(?:<[^>]*>)?)", name)
     return m.group(1) if m else name[:60]
 
