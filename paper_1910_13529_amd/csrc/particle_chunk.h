@@ -118,23 +118,28 @@ struct StaggerL {
   bool h1lo, h2lo, h3lo;
 };
 
+// The stencil of each staggering starts at one of two consecutive window
+// cells per axis (x1[k + 1] = x1[k] + 1, likewise x2, x3 in rows and
+// planes), so one start per axis is selected and the three cells of an x1
+// row are read at constant offsets from one address.
 template <typename Real, int DIM, bool H1, bool H2, bool H3>
 __device__ __forceinline__ Real interp_lds(const StaggerL &s, const Real wN[3][3], const Real wH[3][3],
                                            const Real *ft) {
+  const int x0 = (H1 && s.h1lo) ? s.x1[0] : s.x1[1];
+  const int y0 = (H2 && s.h2lo) ? s.x2[0] : s.x2[1];
+  const int dy = s.x2[1] - s.x2[0];
+  const int z0 = DIM == 3 ? ((H3 && s.h3lo) ? s.x3[0] : s.x3[1]) : 0;
+  const int dz = DIM == 3 ? s.x3[1] - s.x3[0] : 0;
   Real acc = 0;
 #pragma unroll
   for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) {
-    const int z = DIM == 3 ? ((H3 && s.h3lo) ? s.x3[c] : s.x3[c + 1]) : 0;
     Real rc = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const int y = (H2 && s.h2lo) ? s.x2[b] : s.x2[b + 1];
+      const Real *row = ft + (x0 + y0 + b * dy + z0 + c * dz);
       Real r = 0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int x = (H1 && s.h1lo) ? s.x1[a] : s.x1[a + 1];
-        r += (H1 ? wH[0][a] : wN[0][a]) * lds_ld(ft + x + y + z);
-      }
+      for (int a = 0; a < 3; ++a) r += (H1 ? wH[0][a] : wN[0][a]) * lds_ld(row + a);
       rc += (H2 ? wH[1][b] : wN[1][b]) * r;
     }
     acc += DIM == 3 ? (H3 ? wH[2][c] : wN[2][c]) * rc : rc;
