@@ -13,6 +13,7 @@
 // workgroups are renumbered so that each XCD sweeps a contiguous band of
 // rows (neighbouring rows share its L2).
 #include "field_tiles.h"
+#include "xlane.h"
 
 namespace relpic {
 
@@ -311,32 +312,48 @@ __global__ __launch_bounds__(256) void k_jcorr(Geo g, const Real *J1, Real *J1c,
 //     terms are the axial ones reaching back into the window.
 // ax: C_l (dt/2) / dx1.  The other B buffer's column is cleared.
 template <typename Real>
-__global__ void k_new_slab(Geo g, Fields<Real> f, Real *Bx1, Real *Bx2, Real *Bx3, int col, Axial<Real> ax) {
-  const long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const long long rows = (long long)g.n2 * g.n3;
-  if (r >= rows) return;
+__global__ __launch_bounds__(256) void k_new_slab(Geo g, Fields<Real> f, Real *Bx1, Real *Bx2, Real *Bx3, int col,
+                                                  Axial<Real> ax) {
+  // one wavefront per (x2, x3) row, lanes over the cells the row touches
+  const long long r = blockIdx.x * (long long)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= (long long)g.n2 * g.n3) return;  // whole wavefront
   const long long row = r * g.n1;
   const long long id = row + col;
   const Real e2b = f.E2[id], e3b = f.E3[id];
   // old window cells j = 1..M-1 reach the leaving cell 0 through C_{j+1}
-  for (int j = 1; j < ax.M; ++j) {
-    const long long k = row + col_of(g, j);
-    f.B2[k] -= ax.c[j] * e3b;
-    f.B3[k] += ax.c[j] * e2b;
+  if (lane >= 1 && lane < ax.M) {
+    const long long k = row + col_of(g, lane);
+    f.B2[k] -= ax.c[lane] * e3b;
+    f.B3[k] += ax.c[lane] * e2b;
   }
-  f.E1[id] = f.E2[id] = f.E3[id] = Real(0);
   // new front cell = old window cell n1: d+ f = sum_l C_l (f(n1 + l) - f(n1 - l + 1)),
-  // with f zero at old cells >= n1
-  Real d1E2 = 0, d1E3 = 0;
-  for (int l = 2; l <= ax.M; ++l) {
-    const long long k = row + col_of(g, g.n1 - l + 1);
-    d1E2 -= ax.c[l - 1] * f.E2[k];
-    d1E3 -= ax.c[l - 1] * f.E3[k];
+  // with f zero at old cells >= n1; lane l holds the term of l
+  Real s2 = 0, s3 = 0;
+  if (lane >= 2 && lane <= ax.M) {
+    const long long k = row + col_of(g, g.n1 - lane + 1);
+    s2 = ax.c[lane - 1] * f.E2[k];
+    s3 = ax.c[lane - 1] * f.E3[k];
   }
-  f.B1[id] = Real(0);
-  f.B2[id] = -d1E3;
-  f.B3[id] = d1E2;
-  Bx1[id] = Bx2[id] = Bx3[id] = Real(0);
+  s2 += xor_lane<32>(s2);
+  s3 += xor_lane<32>(s3);
+  s2 += xor_lane<16>(s2);
+  s3 += xor_lane<16>(s3);
+  s2 += xor_lane<8>(s2);
+  s3 += xor_lane<8>(s3);
+  s2 += xor_lane<4>(s2);
+  s3 += xor_lane<4>(s3);
+  s2 += xor_lane<2>(s2);
+  s3 += xor_lane<2>(s3);
+  s2 += xor_lane<1>(s2);
+  s3 += xor_lane<1>(s3);
+  if (lane == 0) {
+    f.E1[id] = f.E2[id] = f.E3[id] = Real(0);
+    f.B1[id] = Real(0);
+    f.B2[id] = s3;   // -d1E3
+    f.B3[id] = -s2;  // d1E2
+    Bx1[id] = Bx2[id] = Bx3[id] = Real(0);
+  }
 }
 
 __global__ void k_reset_box(JBox *b) {
@@ -434,7 +451,7 @@ template <typename Real>
 void launch_new_slab(const Geo &g, const Fields<Real> &f, Real *const Bx[3], int col, const Axial<Real> &ax,
                      hipStream_t st) {
   const long long rows = (long long)g.n2 * g.n3;
-  k_new_slab<Real><<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(g, f, Bx[0], Bx[1], Bx[2], col, ax);
+  k_new_slab<Real><<<(unsigned)((rows + 3) / 4), 256, 0, st>>>(g, f, Bx[0], Bx[1], Bx[2], col, ax);
 }
 
 void launch_reset_box(JBox *b, hipStream_t st) { k_reset_box<<<1, 64, 0, st>>>(b); }
