@@ -221,9 +221,10 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
     f.B1 = Bb[0];
     f.B2 = Bb[1];
     f.B3 = Bb[2];
-    if (s->fuse && !shift) {
+    if (s->fuse) {
       // fused: also B^{n+3/2} (or B^{n+1} after the last step) into Ba,
-      // which held B^{n-1/2}; E^{n+1} into the second E buffer
+      // which held B^{n-1/2}; E^{n+1} into the second E buffer; a window
+      // shift after it is applied to the result (launch_shift_fused)
       const bool last = it + 1 == nsteps;
       const double fb = last ? 0.5 * dt : dt;
       Real *Ein[3] = {f.E1, f.E2, f.E3};
@@ -255,10 +256,17 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
     if (shift) {
       ProfScope ps(s, 4);
       Fields<Real> fz = fields<Real>(s);
-      fz.B1 = Ba[0];
-      fz.B2 = Ba[1];
-      fz.B3 = Ba[2];
-      launch_new_slab<Real>(g, fz, Bb, g.ws_mod, axial_scaled<Real>(s, 0.5 * dt), s->st);
+      if (s->fuse) {
+        // Ba: B^{n+1/2}, Bb: the B the fused update produced
+        Real *E[3] = {fz.E1, fz.E2, fz.E3};
+        launch_shift_fused<Real>(g, E, Ba, Bb, g.ws_mod, axial_scaled<Real>(s, 0.5 * dt), (Real)(b_final ? 0.0 : 1.0),
+                                 s->st);
+      } else {
+        fz.B1 = Ba[0];
+        fz.B2 = Ba[1];
+        fz.B3 = Ba[2];
+        launch_new_slab<Real>(g, fz, Bb, g.ws_mod, axial_scaled<Real>(s, 0.5 * dt), s->st);
+      }
       s->ws += 1;
       const Geo g2 = make_geo(s);
       for (auto &sp : s->sp) {

@@ -35,6 +35,12 @@ template <typename Real>
 void launch_new_slab(const Geo &g, const Fields<Real> &f, Real *const Bx[3], int col, const Axial<Real> &ax,
                      hipStream_t st);
 void launch_reset_box(JBox *b, hipStream_t st);
+// window shift after a fused step: E (E^{n+1}), X (B^{n+1/2}) and Y (the B
+// the fused update produced with factor f) from the old window to the
+// shifted one; ch: C_l (dt/2) / dx1, f2m1 = 2 f - 1
+template <typename Real>
+void launch_shift_fused(const Geo &g, Real *const E[3], Real *const X[3], Real *const Y[3], int col,
+                        const Axial<Real> &ch, Real f2m1, hipStream_t st);
 // J cleared inside the J box (x1 widened by pad), `next` box reset
 template <typename Real>
 void launch_clear_j(const Geo &g, const Fields<Real> &f, const JBox *box, int pad, JBox *next, hipStream_t st);

@@ -356,6 +356,66 @@ __global__ __launch_bounds__(256) void k_new_slab(Geo g, Fields<Real> f, Real *B
   }
 }
 
+// Window shift after a fused step n (g: geometry before the shift).  The
+// fused update took B from n + 1/2 to Bnext = B^{n+1/2} - f dt curl+ E^{n+1}
+// (f = 1: B^{n+3/2}; f = 1/2: B^{n+1}) on the old window, where the leaving
+// slab (window cell 0, storage column `col`) still holds E^{n+1}; on the
+// shifted window that slab is outside and its column is the new front slab.
+// The axial stencil is the only part of curl+ that sees the difference:
+//   - cells j = 1..M-1 behind the leaving slab: B^{n+1/2} takes the half-step
+//     correction of k_new_slab (-ch_j E3, +ch_j E2 on B2, B3, with ch_j =
+//     C_{j+1} (dt/2) / dx1), and the f dt curl+ of Bnext loses the leaving
+//     slab's term: Bnext gets +(2f - 1) ch_j E3, -(2f - 1) ch_j E2;
+//   - the new front column: E^{n+1} = 0, B^{n+1/2} = (0, S3, -S2) with
+//     S_c = sum_{l >= 2} ch_{l-1} E_c(old cell n1 - l + 1) as in k_new_slab,
+//     and Bnext = (0, (1 - 2f) S3, (2f - 1) S2), its curl+ having only the
+//     axial terms reaching back into the window.
+// X: B^{n+1/2}, Y: Bnext.  One wavefront per (x2, x3) row.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_shift_fused(Geo g, Real *E1, Real *E2, Real *E3, Real *X1, Real *X2, Real *X3,
+                                                     Real *Y1, Real *Y2, Real *Y3, int col, Axial<Real> ch, Real f2m1) {
+  const long long r = blockIdx.x * (long long)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= (long long)g.n2 * g.n3) return;  // whole wavefront
+  const long long row = r * g.n1;
+  const long long id = row + col;
+  const Real e2b = E2[id], e3b = E3[id];
+  if (lane >= 1 && lane < ch.M) {
+    const long long k = row + col_of(g, lane);
+    X2[k] -= ch.c[lane] * e3b;
+    X3[k] += ch.c[lane] * e2b;
+    Y2[k] += f2m1 * (ch.c[lane] * e3b);
+    Y3[k] -= f2m1 * (ch.c[lane] * e2b);
+  }
+  Real s2 = 0, s3 = 0;
+  if (lane >= 2 && lane <= ch.M) {
+    const long long k = row + col_of(g, g.n1 - lane + 1);
+    s2 = ch.c[lane - 1] * E2[k];
+    s3 = ch.c[lane - 1] * E3[k];
+  }
+  s2 += xor_lane<32>(s2);
+  s3 += xor_lane<32>(s3);
+  s2 += xor_lane<16>(s2);
+  s3 += xor_lane<16>(s3);
+  s2 += xor_lane<8>(s2);
+  s3 += xor_lane<8>(s3);
+  s2 += xor_lane<4>(s2);
+  s3 += xor_lane<4>(s3);
+  s2 += xor_lane<2>(s2);
+  s3 += xor_lane<2>(s3);
+  s2 += xor_lane<1>(s2);
+  s3 += xor_lane<1>(s3);
+  if (lane == 0) {
+    E1[id] = E2[id] = E3[id] = Real(0);
+    X1[id] = Real(0);
+    X2[id] = s3;
+    X3[id] = -s2;
+    Y1[id] = Real(0);
+    Y2[id] = -f2m1 * s3;
+    Y3[id] = f2m1 * s2;
+  }
+}
+
 __global__ void k_reset_box(JBox *b) {
   const int d = threadIdx.x;
   if (d < 3) {
@@ -454,6 +514,14 @@ void launch_new_slab(const Geo &g, const Fields<Real> &f, Real *const Bx[3], int
   k_new_slab<Real><<<(unsigned)((rows + 3) / 4), 256, 0, st>>>(g, f, Bx[0], Bx[1], Bx[2], col, ax);
 }
 
+template <typename Real>
+void launch_shift_fused(const Geo &g, Real *const E[3], Real *const X[3], Real *const Y[3], int col,
+                        const Axial<Real> &ch, Real f2m1, hipStream_t st) {
+  const long long rows = (long long)g.n2 * g.n3;
+  k_shift_fused<Real><<<(unsigned)((rows + 3) / 4), 256, 0, st>>>(g, E[0], E[1], E[2], X[0], X[1], X[2], Y[0], Y[1],
+                                                                    Y[2], col, ch, f2m1);
+}
+
 void launch_reset_box(JBox *b, hipStream_t st) { k_reset_box<<<1, 64, 0, st>>>(b); }
 
 #define RELPIC_INST_FIELD(Real)                                                                                   \
@@ -464,6 +532,8 @@ void launch_reset_box(JBox *b, hipStream_t st) { k_reset_box<<<1, 64, 0, st>>>(b
   template void launch_add_j<Real>(const Geo &, const Fields<Real> &, const Real *, Real, const JBox *, int,     \
                                    JBox *, hipStream_t);                                                          \
   template void launch_clear_j<Real>(const Geo &, const Fields<Real> &, const JBox *, int, JBox *, hipStream_t); \
+  template void launch_shift_fused<Real>(const Geo &, Real *const[3], Real *const[3], Real *const[3], int,         \
+                                         const Axial<Real> &, Real, hipStream_t);                                 \
   template void launch_jcorr<Real>(const Geo &, const Real *, Real *, const Real *, int, const JBox *,            \
                                    hipStream_t);                                                                  \
   template void launch_new_slab<Real>(const Geo &, const Fields<Real> &, Real *const[3], int, const Axial<Real> &, \
