@@ -479,6 +479,17 @@ def main():
                 "avg_launch_ms": prof[k][1] / prof[k][0],
                 "algorithmic_bytes_per_launch": algorithmic_bytes(k, ncells, npart, esz)}
             for k in ("curl_e", "curl_b", "leap") if prof.get(k, (0, 0))[0] > 0},
+        # the push against the vector-ALU peak (algorithmic flops), whichever kernel dominates
+        "roofline_push": ({
+            "bound": "alu", "kernel": "push_deposit",
+            "achieved": flops / (prof["push_deposit"][1] / prof["push_deposit"][0] * 1e-3) / 1e12,
+            "peak": peak_alu, "unit": "TFLOP/s",
+            "frac": flops / (prof["push_deposit"][1] / prof["push_deposit"][0] * 1e-3) / 1e12 / peak_alu,
+            "traffic": traffic_of.get("push_deposit"),
+            "avg_launch_ms": prof["push_deposit"][1] / prof["push_deposit"][0],
+            "algorithmic_flops_per_launch": flops,
+            "algorithmic_bytes_per_launch": algorithmic_bytes("push_deposit", ncells, npart, esz),
+        } if prof.get("push_deposit", (0, 0))[0] > 0 else None),
         "kernel_ms_per_step": {k: prof[k][1] / r["nprof"] for k in prof if prof[k][0]},
         "diag": {k: r["diag"][k] for k in ("step", "window_start", "n_alive", "w_field", "w_kin", "error_word")},
     }
