@@ -11,7 +11,7 @@
 // k_curl_e_col, in the same order.
 //
 // A workgroup owns R consecutive x2 rows of whole x1 lines (thread t holds
-// window cell t of every row) and marches through kLeapPlanes x3 planes.  B at
+// window cell t of every row) and marches through `planes` x3 planes.  B at
 // (row j, plane k) needs E^{n+1} at row j + 1 and at plane k + 1, so the B
 // update runs one plane behind the E update, and the workgroup also computes
 // E^{n+1} on the first row of the next row block (E1, E3) and on the first
@@ -24,7 +24,18 @@ namespace relpic {
 
 namespace {
 
-constexpr int kLeapPlanes = 32;
+// planes per workgroup: long enough columns that about two workgroups per CU
+// cover the grid in one round (the recomputed plane is 1/planes of the work),
+// at least 8
+constexpr int kLeapWorkgroups = 512;
+
+inline int leap_planes(const Geo &g, int R) {
+  const long long nrb = g.n2 / R;
+  long long p = (nrb * g.n3 + kLeapWorkgroups - 1) / kLeapWorkgroups;
+  if (p < 8) p = 8;
+  if (p > g.n3) p = g.n3;
+  return (int)p;
+}
 
 // x2 rows per workgroup: more rows share the recomputed neighbour row, fewer
 // keep the per-plane operands in registers at 4 waves per SIMD (FP32: 121
@@ -51,7 +62,7 @@ __global__ __launch_bounds__(512) void k_leap(Geo g, const Real *__restrict__ Ei
                                                Real *__restrict__ Bo2, Real *__restrict__ Bo3, const Real *J1s,
                                                const Real *J2, const Real *J3, const JBox *jbox, int pad, Real dt,
                                                Axial<Real> axE, Real e2c, Real e3c, Axial<Real> axB, Real h2,
-                                               Real h3) {
+                                               Real h3, int planes) {
   extern __shared__ __align__(16) unsigned char leap_lds[];
   constexpr int H = MM > 0 ? MM : kMaxM;  // staged halo per side
   const int M = MM > 0 ? MM : axE.M;
@@ -64,14 +75,14 @@ __global__ __launch_bounds__(512) void k_leap(Geo g, const Real *__restrict__ Ei
   // tile: rows r0 .. r0 + R - 1 of planes z0 .. z1 - 1; each XCD takes a
   // contiguous band of tiles, so row blocks that share a row run side by side
   const int nrb = g.n2 / R;
-  const int nz = (g.n3 + kLeapPlanes - 1) / kLeapPlanes;
+  const int nz = (g.n3 + planes - 1) / planes;
   const long long nb = (long long)nrb * nz;
   const long long per = (nb + kNumXcd - 1) / kNumXcd;
   const long long lin = (blockIdx.x % kNumXcd) * per + blockIdx.x / kNumXcd;
   if (lin >= nb) return;  // whole workgroup, before any barrier
   const int r0 = (int)(lin % nrb) * R;
-  const int z0 = (int)(lin / nrb) * kLeapPlanes;
-  const int z1 = min(z0 + kLeapPlanes, g.n3);
+  const int z0 = (int)(lin / nrb) * planes;
+  const int z1 = min(z0 + planes, g.n3);
 
   const int t = threadIdx.x;
   const bool own = t < g.n1;
@@ -281,11 +292,12 @@ void leap_dispatch(const Geo &g, Real *const Ein[3], Real *const Eout[3], Real *
   const int H = (axE.M == 1 || axE.M == 16) ? axE.M : kMaxM;
   const size_t lds = sizeof(Real) * (size_t)(4 * R + 1) * (size_t)(g.n1 + 2 * H);
   const unsigned threads = (unsigned)((g.n1 + 63) / 64 * 64);
-  const long long nb = (long long)(g.n2 / R) * ((g.n3 + kLeapPlanes - 1) / kLeapPlanes);
+  const int planes = leap_planes(g, R);
+  const long long nb = (long long)(g.n2 / R) * ((g.n3 + planes - 1) / planes);
   const unsigned blocks = (unsigned)((nb + kNumXcd - 1) / kNumXcd * kNumXcd);
 #define RELPIC_LEAP_ARGS                                                                                        \
   g, Ein[0], Ein[1], Ein[2], Eout[0], Eout[1], Eout[2], Bin[0], Bin[1], Bin[2], Bout[0], Bout[1], Bout[2], J1s, J2, \
-      J3, box, pad, dt, axE, e2c, e3c, axB, h2, h3
+      J3, box, pad, dt, axE, e2c, e3c, axB, h2, h3, planes
   if (axE.M == 1)
     k_leap<Real, 1, R><<<blocks, threads, lds, st>>>(RELPIC_LEAP_ARGS);
   else if (axE.M == 16)

@@ -164,11 +164,11 @@ def _beam_sim(n, dx, dt, C, window, sp, precision):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
 def test_fused_field_update_matches_separate(solver, window, precision, tol):
     # the fused E and B update (one pass per step) against the separate
-    # updates on the same run: n3 = 40 is one full column of 32 planes and a
-    # partial one, the window shifts every 2.5 steps (shift steps take the
-    # separate updates), and calls of 7, 1, 1 and 12 steps end with the fused
-    # epilogue
-    n, dx, dt = (64, 12, 40), (0.5, 1.0, 1.0), 0.2
+    # updates on the same run: n3 = 44 is five full columns of 8 planes and a
+    # partial one, the window shifts every 2.5 steps (the fused result is
+    # carried to the shifted window), and calls of 7, 1, 1 and 12 steps end
+    # with the fused epilogue
+    n, dx, dt = (64, 12, 44), (0.5, 1.0, 1.0), 0.2
     C = (1.0,) if solver == "yee" else TABLE1
     sp = beam_species(5, 3000, n, dx, 50.0, Q=-0.02, sigma_cells=(4.0, 1.5, 1.5), center_frac=0.5,
                       divergence=0.02, espread=0.02)
