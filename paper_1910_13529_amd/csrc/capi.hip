@@ -115,8 +115,8 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
   unsigned long long *cnt = (unsigned long long *)(s->dbuf + 6);
   unsigned long long *runs = (unsigned long long *)(s->dbuf + 7);
   HIP_OK(hipMemsetAsync(s->dbuf + 6, 0, 2 * sizeof(double), s->st));
-  launch_permute<Real>(src, dst, sp.id, sp.id2, sp.idx2, s->ndim, cnt, s->st);
-  launch_count_runs(sp.keys2, sp.n, runs, s->st);
+  launch_permute<Real>(src, dst, sp.id, sp.id2, sp.idx2, s->ndim, s->st);
+  launch_count_runs(sp.keys2, sp.n, runs, cnt, s->st);
   unsigned long long h[2] = {0, 0};
   HIP_OK(hipMemcpyAsync(h, s->dbuf + 6, sizeof(h), hipMemcpyDeviceToHost, s->st));
   HIP_OK(hipStreamSynchronize(s->st));

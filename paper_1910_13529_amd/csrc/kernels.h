@@ -73,8 +73,10 @@ template <typename Real>
 void launch_sort_keys(const Particles<Real> &p, unsigned *keys, unsigned *idx, hipStream_t st);
 template <typename Real>
 void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, const int *id_src, int *id_dst,
-                    const unsigned *perm, int ndim, unsigned long long *alive, hipStream_t st);
-void launch_count_runs(const unsigned *keys, long long n, unsigned long long *runs, hipStream_t st);
+                    const unsigned *perm, int ndim, hipStream_t st);
+// sorted keys: distinct alive cells added to *runs, alive count written to *alive
+void launch_count_runs(const unsigned *keys, long long n, unsigned long long *runs, unsigned long long *alive,
+                       hipStream_t st);
 // radix sort of (key, index) pairs; temp/temp_bytes from a first call with temp = null
 hipError_t sort_pairs(void *temp, size_t &temp_bytes, const unsigned *keys_in, unsigned *keys_out,
                       const unsigned *idx_in, unsigned *idx_out, long long n, hipStream_t st);

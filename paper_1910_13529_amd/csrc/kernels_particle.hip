@@ -90,7 +90,7 @@ __global__ void k_sort_keys(Particles<Real> p, unsigned *keys, unsigned *idx) {
 
 template <typename Real>
 __global__ void k_permute(Particles<Real> src, Particles<Real> dst, const int *id_src, int *id_dst,
-                          const unsigned *perm, int ndim, unsigned long long *alive) {
+                          const unsigned *perm, int ndim) {
   const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (j >= src.n) return;
   const long long i = perm[j];
@@ -103,23 +103,40 @@ __global__ void k_permute(Particles<Real> src, Particles<Real> dst, const int *i
   dst.u2[j] = src.u2[i];
   dst.u3[j] = src.u3[i];
   id_dst[j] = id_src[i];
-  // one atomic per wavefront (its first active lane) for the alive count
-  const unsigned long long live = __ballot(c >= 0);
-  const unsigned long long act = __ballot(1);
-  if ((threadIdx.x & 63) == __ffsll((long long)act) - 1) atomicAdd(alive, (unsigned long long)__popcll(live));
 }
 
-// number of distinct alive cells in a sorted key array (density estimate)
-__global__ void k_count_runs(const unsigned *keys, long long n, unsigned long long *runs) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const unsigned k = keys[i];
-  if (k != 0xFFFFFFFFu && (i == 0 || keys[i - 1] != k)) atomicAdd(runs, 1ULL);
+// In a sorted key array: the number of distinct alive cells (density
+// estimate) and the number of alive particles, written by the last alive
+// slot (dropped particles sort last; both counters zero beforehand).  A
+// counter that every wavefront hits serializes in L2 (65536 atomics on one
+// address took ~0.8 ms), so the runs are summed per workgroup over a bounded
+// grid and the alive count is not accumulated at all.
+constexpr int kRunsBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_count_runs(const unsigned *keys, long long n, unsigned long long *runs,
+                                                    unsigned long long *alive) {
+  __shared__ unsigned long long part[4];
+  unsigned long long cnt = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const unsigned k = keys[i];
+    if (k == 0xFFFFFFFFu) continue;
+    if (i == 0 || keys[i - 1] != k) ++cnt;
+    if (i + 1 == n || keys[i + 1] == 0xFFFFFFFFu) *alive = (unsigned long long)(i + 1);
+  }
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long tot = part[0] + part[1] + part[2] + part[3];
+    if (tot) atomicAdd(runs, tot);
+  }
 }
 
-void launch_count_runs(const unsigned *keys, long long n, unsigned long long *runs, hipStream_t st) {
+void launch_count_runs(const unsigned *keys, long long n, unsigned long long *runs, unsigned long long *alive,
+                       hipStream_t st) {
   if (n <= 0) return;
-  k_count_runs<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(keys, n, runs);
+  const long long need = (n + 255) / 256;
+  k_count_runs<<<(unsigned)(need < kRunsBlocks ? need : kRunsBlocks), 256, 0, st>>>(keys, n, runs, alive);
 }
 
 template <typename Real>
@@ -130,9 +147,9 @@ void launch_sort_keys(const Particles<Real> &p, unsigned *keys, unsigned *idx, h
 
 template <typename Real>
 void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, const int *id_src, int *id_dst,
-                    const unsigned *perm, int ndim, unsigned long long *alive, hipStream_t st) {
+                    const unsigned *perm, int ndim, hipStream_t st) {
   if (src.n <= 0) return;
-  k_permute<Real><<<(unsigned)((src.n + 255) / 256), 256, 0, st>>>(src, dst, id_src, id_dst, perm, ndim, alive);
+  k_permute<Real><<<(unsigned)((src.n + 255) / 256), 256, 0, st>>>(src, dst, id_src, id_dst, perm, ndim);
 }
 
 #define RELPIC_INST_PART(Real)                                                                                   \
@@ -141,7 +158,7 @@ void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, cons
                                           hipStream_t);                                                          \
   template void launch_sort_keys<Real>(const Particles<Real> &, unsigned *, unsigned *, hipStream_t);           \
   template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \
-                                     const unsigned *, int, unsigned long long *, hipStream_t);
+                                     const unsigned *, int, hipStream_t);
 
 RELPIC_INST_PART(float)
 RELPIC_INST_PART(double)
