@@ -93,3 +93,48 @@ def test_fullsize_beam_charge_conservation_fp32():
     assert abs(d["charge"] - d0["charge"]) < 1e-9 * abs(d0["charge"])
     assert abs(d["gauss_max"] - d0["rho_max"]) < 1e-5 * d0["rho_max"]
     g.close()
+
+
+@pytest.mark.parametrize("precision,utol,xtol", [("fp64", 1e-12, 1e-12), ("fp32", 2e-5, 1e-4)])
+def test_fullsize_gather_push_sampled(precision, utol, xtol):
+    # one push of the full beam on the full grid (periodic x1, the same kernels
+    # as the moving window) against the oracle's gather and Boris push of 4096
+    # sampled particles in the GPU's own fields E^n, B^n
+    from oracle.pic import OracleSim, boris
+    from paper_1910_13529_amd.relpic import Sim
+    w = inputs.config_beam3d(n=N)
+    g = Sim(dict(ndim=3, n=w.n, dx=w.dx, dt=w.dt, window=False), C=list(TABLE1), precision=precision)
+    assert g.set_fused_fields(True)
+    cell, off, u = inputs.beam_inputs(w, seed=2)
+    n = len(cell)
+    sid = g.add_species(-1.0, inputs.beam_charge(w), n)
+    g.load_particles(sid, cell, off, u)
+    g.step(10)
+    fields = {nm: g.field(nm) for nm in ("E1", "E2", "E3", "B1", "B2", "B3")}
+    c0, o0, u0, a0 = g.particles(sid, n)
+    g.step(1)
+    c1, o1, u1, a1 = g.particles(sid, n)
+    g.close()
+    o = OracleSim(N, w.dx, w.dt, C=TABLE1, window=False)
+    for nm in list(fields):
+        o.set_field(nm, fields.pop(nm))
+    sel = np.random.default_rng(7).choice(np.flatnonzero(a0 & a1), 4096, replace=False)
+    x0 = c0[sel] + o0[sel]
+    EB = o.gather_at(x0)
+    o.close()
+    un = np.array([boris(-1.0, w.dt, EB[i], u0[p]) for i, p in enumerate(sel)])
+    gam = np.sqrt(1.0 + (un * un).sum(axis=1))
+    xn = x0 + w.dt * un / gam[:, None] / np.asarray(w.dx)[None, :]
+    du = float((np.linalg.norm(u1[sel] - un, axis=1) / np.linalg.norm(un, axis=1)).max())
+    d = (c1[sel] + o1[sel]) - xn
+    nn = np.asarray(N, dtype=np.float64)[None, :]
+    d = (d + nn / 2) % nn - nn / 2  # periodic wrap
+    dx_max = float(np.abs(d).max())
+    # the momentum change itself (|u| ~ 1e4 hides it in FP32 storage)
+    kick = un - u0[sel]
+    dkick = float(np.abs((u1[sel] - u0[sel]) - kick).max() / np.abs(kick).max())
+    log("full-size sampled push %s: max |du|/|u| %.3g, max |dx| %.3g cells, kick error %.3g" %
+        (precision, du, dx_max, dkick))
+    assert du < utol and dx_max < xtol
+    if precision == "fp64":
+        assert dkick < 1e-11
