@@ -293,6 +293,90 @@ def adjoint_main(args):
     print(json.dumps(out), flush=True)
 
 
+def plasma_main(args):
+    """The 3D beam in a uniform plasma: the beam grid and bunch plus plasma
+    electrons at 8 particles per cell on a 2x2x2 quiet-start lattice (u ~
+    1e-4 N(0, 1) per component, weight dV/8, immobile ions), injected into the
+    front slab at every window shift; customized solver, fused field update.
+    The plasma is generated on the host in x1 slabs and appended."""
+    import numpy as np
+    import torch
+    from paper_1910_13529_amd import inputs
+    from paper_1910_13529_amd.relpic import Sim
+    w, cell, off, u, Q = make_workload(args)
+    n1, n2, n3 = w.n
+    dV = w.dx[0] * w.dx[1] * w.dx[2]
+    Qp = -dV / 8.0  # n0 = 1
+    ppc = (2, 2, 2)
+    shifts = (args.warmup + args.steps + 64) // 4 + 2
+    n_plasma0 = (n1 - 4) * n2 * n3 * 8
+    cap = n_plasma0 + shifts * n2 * n3 * 8
+    grid = dict(ndim=3, n=w.n, dx=w.dx, dt=w.dt, window=True, window_speed=1.0)
+    sim = Sim(grid, C=TABLE1_C, precision=args.precision)
+    try:
+        fused = sim.set_fused_fields(not args.separate_fields)
+    except RuntimeError:
+        fused = False
+    sb = sim.add_species(-1.0, Q, len(cell))
+    sim.load_particles(sb, cell, off, u)
+    sp = sim.add_species(-1.0, Qp, cap)
+    print("[bench] plasma: %d particles in %d slabs" % (n_plasma0, (n1 - 4 + 31) // 32), file=sys.stderr, flush=True)
+    for k, lo in enumerate(range(2, n1 - 2, 32)):
+        hi = min(lo + 32, n1 - 2)
+        c, o, uu = inputs.plasma_lattice(100 + k, (lo, 0, 0), (hi, n2, n3), ppc, 1e-4)
+        sim.load_particles(sp, c, o, uu)
+        del c, o, uu
+    sim.set_injection(sp, ppc, 1e-4, 12345)
+    npart = len(cell) + n_plasma0
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.profile_enable(True)
+    nprof = max(8, min(args.steps, 32))
+    sim.step(nprof)
+    prof = sim.profile_read()
+    sim.profile_enable(False)
+    diag = sim.diagnostics()
+    sim.close()
+    ncells = n1 * n2 * n3
+    esz = 4 if args.precision == "fp32" else 8
+    ms = 1e3 * wall / args.steps
+    pavg = prof["push_deposit"][1] / max(prof["push_deposit"][0], 1)
+    flops = push_flops_per_particle(3) * npart
+    peak_alu = FP32_VECTOR_PEAK_TFLOPS if args.precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
+    out = {
+        "metric": "particle-steps/s + field cell-updates/s per PIC step; % HBM peak; FP32 vs FP64",
+        "value": npart * args.steps / wall,
+        "unit": "particle-steps/s",
+        "cell_updates_per_s": ncells * args.steps / wall,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D beam in uniform plasma: beam grid and bunch plus plasma electrons at 8 ppc "
+                               "(2x2x2 lattice, u_th=1e-4, immobile ions), front-slab injection at each window "
+                               "shift, customized solver", "cells": ncells, "particles": npart,
+                   "fused_field_update": fused, "parallelism": "single GPU"},
+        "roofline_push": {"bound": "alu", "kernel": "push_deposit", "avg_launch_ms": pavg,
+                          "achieved": flops / (pavg * 1e-3) / 1e12, "peak": peak_alu, "unit": "TFLOP/s",
+                          "frac": flops / (pavg * 1e-3) / 1e12 / peak_alu,
+                          "hbm_achieved_gbs": algorithmic_bytes("push_deposit", ncells, npart, esz) / (pavg * 1e-3) / 1e9},
+        "kernel_ms_per_step": {k: prof[k][1] / nprof for k in prof if prof[k][0]},
+        "diag": {k: diag[k] for k in ("step", "window_start", "n_alive", "w_field", "w_kin", "error_word")},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(args, w, cell, off, u, Q, solver):
     """The FP64 oracle on the host: a bounded sample of the same workload.
 
@@ -349,9 +433,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--separate-fields", action="store_true",
                     help="3D beam: separate E and B updates instead of the fused one")
-    ap.add_argument("--workload", default="beam3d", choices=["beam3d", "batch", "adjoint"],
+    ap.add_argument("--workload", default="beam3d", choices=["beam3d", "batch", "adjoint", "plasma3d"],
                     help="beam3d: the 3D beam (default); batch: the 256-run batched workload; "
-                         "adjoint: time per gradient of the differentiable case")
+                         "adjoint: time per gradient of the differentiable case; plasma3d: the 3D beam in a "
+                         "uniform plasma (8 ppc, 2.7e8 particles)")
     ap.add_argument("--batch-solver", default="mixed", choices=["mixed", "yee", "custom"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")
@@ -376,6 +461,9 @@ def main():
         return
     if args.workload == "adjoint":
         adjoint_main(args)
+        return
+    if args.workload == "plasma3d":
+        plasma_main(args)
         return
     w, cell, off, u, Q = make_workload(args)
     ncells = int(math.prod(w.n))
