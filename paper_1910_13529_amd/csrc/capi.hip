@@ -87,15 +87,25 @@ long long window_target(const relpic_sim *s, long long steps_done) {
 }
 
 
+// Key order by density: a sparse species (a plasma filling the grid) sorts
+// by 3D tiles so that a push chunk covers a compact box; a dense bunch, whose
+// chunks sit in one or two cells either way, keeps plain row order (its
+// chunks then straddle no tile seams).  Mean particles per occupied cell
+// below kTileBelow switches to tiles, above kRowsAbove back to rows.
+constexpr double kTileBelow = 64.0, kRowsAbove = 128.0;
+
 // Sort a species by cell (dropped particles last), drop the dropped ones,
-// and pick the push chunk size from the particles per occupied cell.
+// and pick the push chunk size from the particles per occupied cell.  When
+// the measured density asks for the other key order, sort once more in it.
 template <typename Real>
 relpic_status do_sort(relpic_sim *s, Species &sp) {
   sp.dirty = false;
   sp.sorted_at = s->step;
   if (sp.n <= 1) return RELPIC_OK;
   Particles<Real> src = parts<Real>(sp);
-  launch_sort_keys<Real>(src, sp.keys, sp.idx, s->st);
+  const Geo g = make_geo(s);
+  const bool tiles = sp.tile_keys && sort_tiles_fit(g);
+  launch_sort_keys<Real>(g, src, tiles ? 1 : 0, sp.keys, sp.idx, s->st);
   size_t need = 0;
   HIP_OK(sort_pairs(nullptr, need, sp.keys, sp.keys2, sp.idx, sp.idx2, sp.n, s->st));
   if (need > sp.sort_tmp_bytes) {
@@ -128,7 +138,18 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
   std::swap(sp.id, sp.id2);
   sp.n = (long long)h[0];
   const double ppc = h[1] ? (double)h[0] / (double)h[1] : 0.0;
-  sp.K = ppc >= 512.0 ? 8 : (ppc >= 64.0 ? 4 : (ppc >= 16.0 ? 2 : 1));
+  const bool want = sort_tiles_fit(g) && sp.n > 1 && ppc < (sp.tile_keys ? kRowsAbove : kTileBelow);
+  if (want != tiles) {
+    sp.tile_keys = want;
+    return do_sort<Real>(s, sp);
+  }
+  if (tiles) {
+    // chunks of 256 K particles that fill about one tile
+    const double per_tile = ppc * (s->ndim == 3 ? 128.0 : 32.0);
+    sp.K = per_tile > 1024.0 ? 8 : (per_tile > 512.0 ? 4 : (per_tile > 256.0 ? 2 : 1));
+  } else {
+    sp.K = ppc >= 512.0 ? 8 : (ppc >= 64.0 ? 4 : (ppc >= 16.0 ? 2 : 1));
+  }
   return RELPIC_OK;
 }
 

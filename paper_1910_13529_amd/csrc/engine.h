@@ -31,6 +31,7 @@ struct Species {
   bool dirty = true;   // needs a sort before the next step
   long long sorted_at = 0;  // step of the last sort
   int K = 1;           // particles per thread in the push kernel
+  bool tile_keys = false;  // sort key order: 3D tiles (sparse) or rows (dense)
   bool inject = false;
   int ppc[3] = {1, 1, 1};
   double uth = 0.0;

@@ -70,7 +70,10 @@ long long push_blocks(long long n, int K);
 
 // ---- particle sort by cell ------------------------------------------------------
 template <typename Real>
-void launch_sort_keys(const Particles<Real> &p, unsigned *keys, unsigned *idx, hipStream_t st);
+void launch_sort_keys(const Geo &g, const Particles<Real> &p, int tiles, unsigned *keys, unsigned *idx,
+                      hipStream_t st);
+// whether the tiled sort keys fit in 32 bits on this grid
+bool sort_tiles_fit(const Geo &g);
 template <typename Real>
 void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, const int *id_src, int *id_dst,
                     const unsigned *perm, int ndim, hipStream_t st);

@@ -298,6 +298,36 @@ __global__ __launch_bounds__(256) void k_jcorr(Geo g, const Real *J1, Real *J1c,
             (long long)gridDim.x * blockDim.x);
 }
 
+// The same correction one x1 line of the box at a time: a workgroup stages
+// the line's J1 (box x1 range widened by 2 ng) in LDS and every output reads
+// its 2 ng + 1 taps from there (same arithmetic as jcorr_box).  For boxes
+// that cover much of the grid (a beam in a plasma) it replaces ~2 ng + 1
+// cached global loads per cell by one.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_jcorr_rows(Geo g, const Real *J1, Real *J1c, const Real *taps, int ng,
+                                                    const JBox *box) {
+  extern __shared__ __align__(16) unsigned char jc_lds[];
+  Real *line = reinterpret_cast<Real *>(jc_lds);
+  const JBox b = *box;
+  int lo1, hi1;
+  if (!box_x1(g, b, ng, lo1, hi1)) return;  // whole workgroup
+  const int W = hi1 - lo1 + 1;
+  const long long w2 = b.hi[1] - b.lo[1] + 1, rows = w2 * (b.hi[2] - b.lo[2] + 1);
+  for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int i2 = b.lo[1] + (int)(r % w2), i3 = b.lo[2] + (int)(r / w2);
+    const long long row = (long long)g.n1 * (i2 + (long long)g.n2 * i3);
+    for (int t = threadIdx.x; t < W + 2 * ng; t += blockDim.x) line[t] = ldc(J1, row, col_of(g, lo1 - ng + t));
+    __syncthreads();
+    for (int t = threadIdx.x; t < W; t += blockDim.x) {
+      const Real *c = line + ng + t;
+      Real acc = taps[0] * c[0];
+      for (int m = 1; m <= ng; ++m) acc += taps[m] * (c[-m] + c[m]);
+      J1c[row + col_of(g, lo1 + t)] = acc;
+    }
+    __syncthreads();
+  }
+}
+
 // Window shift after step n, with g the geometry before the shift.  The
 // step's second B half step, B^{n+1} = B^{n+1/2} - (dt/2) curl+ E^{n+1}, is
 // taken on the old window, and the window then moves: the back slab (window
@@ -504,7 +534,13 @@ void launch_clear_j(const Geo &g, const Fields<Real> &f, const JBox *box, int pa
 template <typename Real>
 void launch_jcorr(const Geo &g, const Real *J1, Real *J1c, const Real *taps, int ng, const JBox *box,
                   hipStream_t st) {
-  k_jcorr<Real><<<1024, 256, 0, st>>>(g, J1, J1c, taps, ng, box);
+  // a whole x1 line and its taps in LDS when they fit (the box's x1 range
+  // is at most n1 after widening)
+  const size_t lds = sizeof(Real) * (size_t)(g.n1 + 2 * ng);
+  if (lds <= 32768)
+    k_jcorr_rows<Real><<<4096, 256, lds, st>>>(g, J1, J1c, taps, ng, box);
+  else
+    k_jcorr<Real><<<1024, 256, 0, st>>>(g, J1, J1c, taps, ng, box);
 }
 
 template <typename Real>

@@ -31,10 +31,15 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
   push_chunk<Real, DIM>(g, f, Bh, p, q, K, blockIdx.x, blockbox + blockIdx.x, err, tile_raw, box);
 }
 
-// Box of a set of per-workgroup boxes merged into *out (one workgroup).
-__global__ __launch_bounds__(256) void k_merge_boxes(const JBox *boxes, int nbox, JBox *out) {
+// Box of a set of per-workgroup boxes merged into *out: each workgroup
+// reduces its share (at least 2048 boxes, at most 256 workgroups) and adds
+// one min/max per axis, so the single box sees few atomics.
+constexpr int kMergeMaxBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_merge_boxes(const JBox *boxes, long long nbox, JBox *out) {
+  __shared__ int wlo[3][4], whi[3][4];
   int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {-INT_MAX, -INT_MAX, -INT_MAX};
-  for (int b = threadIdx.x; b < nbox; b += blockDim.x)
+  for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < nbox; b += (long long)gridDim.x * blockDim.x)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       lo[d] = min(lo[d], boxes[b].lo[d]);
@@ -47,12 +52,30 @@ __global__ __launch_bounds__(256) void k_merge_boxes(const JBox *boxes, int nbox
       lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
       hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
     }
+  const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      atomicMin(&out->lo[d], lo[d]);
-      atomicMax(&out->hi[d], hi[d]);
+      wlo[d][wave] = lo[d];
+      whi[d][wave] = hi[d];
     }
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int l = min(min(wlo[d][0], wlo[d][1]), min(wlo[d][2], wlo[d][3]));
+      const int h = max(max(whi[d][0], whi[d][1]), max(whi[d][2], whi[d][3]));
+      if (l <= h) {
+        atomicMin(&out->lo[d], l);
+        atomicMax(&out->hi[d], h);
+      }
+    }
+}
+
+bool sort_tiles_fit(const Geo &g) {
+  const unsigned long long span = (unsigned long long)((g.n1 + 7) / 8 * 8) * (unsigned long long)((g.n2 + 3) / 4 * 4) *
+                                  (unsigned long long)(g.n3 > 1 ? (g.n3 + 3) / 4 * 4 : 1);
+  return span < 0xFFFFFFFFull;
 }
 
 long long push_blocks(long long n, int K) {
@@ -74,17 +97,35 @@ void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const Ha
 
 void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStream_t st) {
   if (nbox <= 0) return;
-  k_merge_boxes<<<1, 256, 0, st>>>(blockbox, (int)nbox, jbox);
+  const long long want = (nbox + 2047) / 2048;
+  k_merge_boxes<<<(unsigned)(want < kMergeMaxBlocks ? want : kMergeMaxBlocks), 256, 0, st>>>(blockbox, nbox, jbox);
 }
 
 // ---- particle sort (cell order) ---------------------------------------------------
 
+// Sort key of a packed cell: with tiles on, cells are grouped in 8 x 4 x 4
+// (2D: 8 x 4) tiles of storage cells, x1 fastest inside a tile, so that a
+// chunk of consecutive particles covers a compact 3D region (its LDS box
+// stays small when the particles fill the grid, as a plasma does); off, the
+// packed index itself.  Both are one-to-one on cells.
 template <typename Real>
-__global__ void k_sort_keys(Particles<Real> p, unsigned *keys, unsigned *idx) {
+__global__ void k_sort_keys(Geo g, Particles<Real> p, int tiles, unsigned *keys, unsigned *idx) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   const int c = p.cell[i];
-  keys[i] = c < 0 ? 0xFFFFFFFFu : (unsigned)c;
+  unsigned k = 0xFFFFFFFFu;
+  if (c >= 0) {
+    k = (unsigned)c;
+    if (tiles) {
+      int s1, c2, c3;
+      unpack_cell(g, c, s1, c2, c3);
+      const unsigned nt1 = (unsigned)(g.n1 + 7) >> 3, nt2 = (unsigned)(g.n2 + 3) >> 2;
+      const unsigned tile = ((unsigned)(c3 >> 2) * nt2 + (unsigned)(c2 >> 2)) * nt1 + (unsigned)(s1 >> 3);
+      const unsigned local = ((unsigned)(c3 & 3) * 4 + (unsigned)(c2 & 3)) * 8 + (unsigned)(s1 & 7);
+      k = tile * (g.n3 > 1 ? 128u : 32u) + local;
+    }
+  }
+  keys[i] = k;
   idx[i] = (unsigned)i;
 }
 
@@ -140,9 +181,10 @@ void launch_count_runs(const unsigned *keys, long long n, unsigned long long *ru
 }
 
 template <typename Real>
-void launch_sort_keys(const Particles<Real> &p, unsigned *keys, unsigned *idx, hipStream_t st) {
+void launch_sort_keys(const Geo &g, const Particles<Real> &p, int tiles, unsigned *keys, unsigned *idx,
+                      hipStream_t st) {
   if (p.n <= 0) return;
-  k_sort_keys<Real><<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(p, keys, idx);
+  k_sort_keys<Real><<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(g, p, tiles, keys, idx);
 }
 
 template <typename Real>
@@ -156,7 +198,8 @@ void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, cons
   template void launch_push_deposit<Real>(int, const Geo &, const Fields<Real> &, const HalfB<Real> &,          \
                                           const Particles<Real> &, const PushParams<Real> &, int, JBox *, int *,  \
                                           hipStream_t);                                                          \
-  template void launch_sort_keys<Real>(const Particles<Real> &, unsigned *, unsigned *, hipStream_t);           \
+  template void launch_sort_keys<Real>(const Geo &, const Particles<Real> &, int, unsigned *, unsigned *,        \
+                                       hipStream_t);                                                             \
   template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \
                                      const unsigned *, int, hipStream_t);
 
