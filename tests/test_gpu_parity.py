@@ -262,3 +262,67 @@ def test_dense_bunch(ndim, precision, tol):
     dxp, dup = particle_errors(g, o, ids[0], len(cell))
     assert dxp < (1e-12 if precision == "fp64" else 1e-4) and dup < tol * 2
     g.sync()
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_sort_key_order_by_density(ndim):
+    # the sort groups a sparse species (about two particles per cell over the
+    # whole grid) by 8 x 4 (x 4) tiles of cells, x1 fastest inside a tile, and
+    # a dense bunch (hundreds per occupied cell) by rows; either order keeps
+    # every particle once and each cell's particles together, and the step
+    # that follows matches the oracle.  The grid is ragged against the tiles
+    # in every axis.
+    n = (76, 22, 14)[:ndim]
+    dx = (0.5, 1.0, 1.0)[:ndim]
+    ncell = int(np.prod(n))
+    cs, os_, us = inputs.uniform_particles(21, 2 * ncell, n, 1e-2, ndim=ndim)
+    sparse = (-1e-4, -1.0, cs, os_, us, len(cs))
+    dense = beam_species(22, 20000, n, dx, 20.0, Q=-1e-4, sigma_cells=(1.5, 0.5, 0.5), center_frac=0.5)
+    g, o, ids = make_pair(ndim, n, dx, 0.2, (1.0,), False, [sparse, dense])
+    g.sort_particles()
+
+    def row_key(c):
+        k = c[:, ndim - 1].astype(np.int64)
+        for d in range(ndim - 2, -1, -1):
+            k = k * n[d] + c[:, d]
+        return k
+
+    def tile_key(c):
+        nt = [(n[0] + 7) // 8] + [(n[d] + 3) // 4 for d in range(1, ndim)]
+        tile = c[:, ndim - 1].astype(np.int64) // (8 if ndim == 1 else 4)
+        local = c[:, ndim - 1].astype(np.int64) % 4
+        for d in range(ndim - 2, -1, -1):
+            w = 8 if d == 0 else 4
+            tile = tile * nt[d] + c[:, d] // w
+            local = local * w + c[:, d] % w
+        return tile * (8 * 4 ** (ndim - 1)) + local
+
+    for sid, (_, _, cell0, _, _, cap), tiled in ((ids[0], sparse, True), (ids[1], dense, False)):
+        cell, off, u, alive = g.particles(sid, cap, order_by_id=False)
+        assert alive.all() and len(cell) == len(cell0)
+        assert sorted(g.last_ids.tolist()) == list(range(len(cell0)))
+        key = tile_key(cell) if tiled else row_key(cell)
+        assert (np.diff(key) >= 0).all()
+        if tiled:
+            assert (np.diff(row_key(cell)) < 0).any()  # not row order
+        log("sort order %dD %s: %d particles, %d cells" % (ndim, "tiles" if tiled else "rows", len(cell),
+                                                          len(np.unique(key))))
+    for _ in range(3):
+        g.step(1)
+        o.step(1)
+    errs = field_errors(g, o)
+    assert max(errs.values()) < 1e-12, errs
+    xo, uo, ao = o.particles()
+    assert ao.all()
+    nn = np.asarray(n, dtype=np.float64)[None, :]
+    start = 0
+    for sid, sp in zip(ids, (sparse, dense)):
+        cell, off, u, alive = g.particles(sid, sp[5])
+        sl = slice(start, start + sp[5])
+        start += sp[5]
+        d = (cell + off) - xo[sl]
+        d = (d + nn / 2) % nn - nn / 2  # periodic wrap
+        du = np.linalg.norm(u - uo[sl], axis=1) / np.maximum(np.linalg.norm(uo[sl], axis=1), 1e-300)
+        assert alive.all() and float(np.abs(d).max()) < 1e-12 and float(du.max()) < 1e-12
+    g.close()
+    o.close()
