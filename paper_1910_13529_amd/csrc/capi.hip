@@ -226,7 +226,8 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       }
       {
         ProfScope ps(s, 0);
-        launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, sp.K, s->blockbox, s->err, s->st);
+        launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, sp.K, sp.tile_keys, s->blockbox, s->err,
+                                  s->st);
       }
       ProfScope ps(s, 6);
       launch_merge_boxes(s->blockbox, nb, box, s->st);

@@ -58,12 +58,14 @@ void launch_leap(const Geo &g, Real *const Ein[3], Real *const Eout[3], Real *co
                  hipStream_t st);
 
 // K particles per thread; each workgroup handles a contiguous chunk of
-// 256 * K particles (sorted by cell for the LDS-tiled deposit to pay off)
+// 256 * K particles (sorted by cell for the LDS-tiled deposit to pay off);
+// wide (3D): deposit rounds over boxes four x1 cells wide instead of two, for
+// species spread over the grid at a few particles per cell
 // blockbox: push_blocks(n, K) scratch boxes, merged into *jbox after the launch
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
-                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *blockbox, int *err,
-                         hipStream_t st);
+                         const Particles<Real> &p, const PushParams<Real> &q, int K, bool wide, JBox *blockbox,
+                         int *err, hipStream_t st);
 // *jbox = union of the nbox per-workgroup boxes (atomic min/max into *jbox)
 void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStream_t st);
 long long push_blocks(long long n, int K);

@@ -22,13 +22,13 @@
 
 namespace relpic {
 
-template <typename Real, int DIM>
+template <typename Real, int DIM, int W>
 __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real> f, HalfB<Real> Bh,
                                                              Particles<Real> p, PushParams<Real> q, int K,
                                                              JBox *blockbox, int *err) {
   __shared__ __align__(16) unsigned char tile_raw[kTileBytes];
   __shared__ int box[kChunkBoxInts];
-  push_chunk<Real, DIM>(g, f, Bh, p, q, K, blockIdx.x, blockbox + blockIdx.x, err, tile_raw, box);
+  push_chunk<Real, DIM, W>(g, f, Bh, p, q, K, blockIdx.x, blockbox + blockIdx.x, err, tile_raw, box);
 }
 
 // Box of a set of per-workgroup boxes merged into *out: each workgroup
@@ -85,14 +85,16 @@ long long push_blocks(long long n, int K) {
 
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
-                         const Particles<Real> &p, const PushParams<Real> &q, int K, JBox *blockbox, int *err,
-                         hipStream_t st) {
+                         const Particles<Real> &p, const PushParams<Real> &q, int K, bool wide, JBox *blockbox,
+                         int *err, hipStream_t st) {
   if (p.n <= 0) return;
   const unsigned blocks = (unsigned)push_blocks(p.n, K);
-  if (ndim == 3)
-    k_push_deposit<Real, 3><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
+  if (ndim == 3 && wide)
+    k_push_deposit<Real, 3, 4><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
+  else if (ndim == 3)
+    k_push_deposit<Real, 3, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
   else
-    k_push_deposit<Real, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
+    k_push_deposit<Real, 2, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
 }
 
 void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStream_t st) {
@@ -196,8 +198,8 @@ void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, cons
 
 #define RELPIC_INST_PART(Real)                                                                                   \
   template void launch_push_deposit<Real>(int, const Geo &, const Fields<Real> &, const HalfB<Real> &,          \
-                                          const Particles<Real> &, const PushParams<Real> &, int, JBox *, int *,  \
-                                          hipStream_t);                                                          \
+                                          const Particles<Real> &, const PushParams<Real> &, int, bool, JBox *,  \
+                                          int *, hipStream_t);                                                   \
   template void launch_sort_keys<Real>(const Geo &, const Particles<Real> &, int, unsigned *, unsigned *,        \
                                        hipStream_t);                                                             \
   template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \

@@ -333,21 +333,29 @@ __device__ __forceinline__ void deposit_direct(const Moved<Real> &m, const PushP
   }
 }
 
-// Shift a 4-point stencil array into the 5-point box frame: out[b] = in[b - o].
-template <typename Real>
-__device__ __forceinline__ Real ext5(const Real *in, int o, int b) {
-  const Real a = (b <= 3) ? in[b] : Real(0);
-  const Real c = (b >= 1) ? in[b - 1] : Real(0);
-  return o ? c : a;
+// Shift an N-point stencil array into a box frame W - 1 points wider:
+// out[b] = in[b - o] (zero outside), o in [0, W).
+template <typename Real, int N, int W>
+__device__ __forceinline__ Real ext_shift(const Real *in, int o, int b) {
+  Real r = Real(0);
+#pragma unroll
+  for (int sft = 0; sft < W; ++sft) {
+    const int j = b - sft;
+    if (j >= 0 && j < N) r = (o == sft) ? in[j] : r;
+  }
+  return r;
 }
 
 // Wavefront-collective deposit (every lane of the wave must call it), in
 // rounds.  In a round the pending lanes in the (x2, x3) row of the first
-// pending lane join the reduction if their x1 stencil starts at most one node
-// after the leftmost one among them (that lane always joins, so every round
-// retires at least one lane).  Their exact supports are then J1: 4 x 3 x 3
+// pending lane join the reduction if their x1 stencil starts at most W - 1
+// nodes after the leftmost one among them (that lane always joins, so every
+// round retires at least one lane).  Their exact supports are then J1: 4 x 3 x 3
 // half/node points, J2: 5 x 2 x 3, J3: 5 x 3 x 2 (2D: 4 x 3, 5 x 2, 5 x 3),
-// all inside boxes that every such lane shares.  Lanes that cross a
+// all inside boxes that every such lane shares (3D with W = 4: stencils
+// starting up to three nodes after the leftmost one join, in boxes three
+// points wider, J1: 6 x 3 x 3, J2: 7 x 2 x 3, J3: 7 x 3 x 2; fewer rounds when
+// a wavefront's particles spread over several cells, as in a plasma).  Lanes that cross a
 // transverse cell boundary this step (a four-node transverse support) are not
 // pending and go to the direct path, which the whole wavefront executes as
 // soon as one lane needs it.  In 3D a round costs a fraction of it (144
@@ -358,9 +366,11 @@ __device__ __forceinline__ Real ext5(const Real *in, int o, int b) {
 constexpr int kDepositRounds = 64;
 constexpr int kDepositRounds2D = 3;
 
-template <typename Real, int DIM>
+template <typename Real, int DIM, int W = 2>
 __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, const PushParams<Real> &q,
                                              const Sink<Real> &sk) {
+  static_assert(W == 2 || (W == 4 && DIM == 3), "round width");
+  constexpr int NX = W + 3;  // x1 nodes of the J2, J3 boxes (J1: NX - 1 half points)
   const int lane = threadIdx.x & 63;
   // no transverse crossing: base -1 and no DS on the fourth node
   const bool flat2 = m.base[1] == -1 && m.DS[1][3] == Real(0);
@@ -376,7 +386,7 @@ __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, 
     // leftmost x1 stencil start among them; the lane that has it always fits
     const int smin = wave_min(inrow ? m.c[0] + m.base[0] : INT_MAX);
     const int o1 = m.c[0] + m.base[0] - smin;
-    const bool fits = inrow && (o1 == 0 || o1 == 1);
+    const bool fits = inrow && o1 >= 0 && o1 < W;
     {
       // Branch-free separable form of the exact supports: each box value is an
       // x1 factor (or x2/x3 running sum) times a transverse Esirkepov weight
@@ -384,20 +394,16 @@ __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, 
       // P = S0 + DS/2, Q = S0/2 + DS/3; lanes that do not fit contribute 0.
       const int oo = fits ? o1 : 0;
       const Real z = fits ? Real(1) : Real(0);
-      Real e1S0[5], e1DS[5];
+      Real e1S0[NX], e1DS[NX];
 #pragma unroll
-      for (int b = 0; b < 5; ++b) {
-        e1S0[b] = ext5(m.S0[0], oo, b);
-        e1DS[b] = ext5(m.DS[0], oo, b);
+      for (int b = 0; b < NX; ++b) {
+        e1S0[b] = ext_shift<Real, 4, W>(m.S0[0], oo, b);
+        e1DS[b] = ext_shift<Real, 4, W>(m.DS[0], oo, b);
       }
       // J1 at x1 half points: running sum of DS1 (three entries) shifted by oo
-      Real c1[4];
+      Real c1[NX - 1];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const Real lo = (b <= 2) ? m.cum[0][b] : Real(0);
-        const Real hi = (b >= 1 && b <= 3) ? m.cum[0][b - 1] : Real(0);
-        c1[b] = z * q.f1 * (oo ? hi : lo);
-      }
+      for (int b = 0; b < NX - 1; ++b) c1[b] = z * q.f1 * ext_shift<Real, 3, W>(m.cum[0], oo, b);
       Real P2[3], Q2[3], P3[3], Q3[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -409,40 +415,40 @@ __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, 
       const int x1 = smin, x2 = c2w - 1, x3 = DIM == 3 ? c3w - 1 : 0;
       if (DIM == 3) {
         {
-          Real v[36];
+          Real v[(NX - 1) * 9];
 #pragma unroll
           for (int a3 = 0; a3 < 3; ++a3)
 #pragma unroll
             for (int a2 = 0; a2 < 3; ++a2) {
               const Real w = m.S0[1][a2] * P3[a3] + m.DS[1][a2] * Q3[a3];
 #pragma unroll
-              for (int b = 0; b < 4; ++b) v[b + 4 * (a2 + 3 * a3)] = c1[b] * w;
+              for (int b = 0; b < NX - 1; ++b) v[b + (NX - 1) * (a2 + 3 * a3)] = c1[b] * w;
             }
-          box_reduce_add<Real, 4, 3, 3>(sk, 0, lane, x1, x2, x3, v);
+          box_reduce_add<Real, NX - 1, 3, 3>(sk, 0, lane, x1, x2, x3, v);
         }
         {
-          Real v[30];
+          Real v[NX * 6];
 #pragma unroll
           for (int a3 = 0; a3 < 3; ++a3)
 #pragma unroll
-            for (int b = 0; b < 5; ++b) {
+            for (int b = 0; b < NX; ++b) {
               const Real w = e1S0[b] * P3[a3] + e1DS[b] * Q3[a3];
 #pragma unroll
-              for (int a2 = 0; a2 < 2; ++a2) v[b + 5 * (a2 + 2 * a3)] = z * q.f2 * m.cum[1][a2] * w;
+              for (int a2 = 0; a2 < 2; ++a2) v[b + NX * (a2 + 2 * a3)] = z * q.f2 * m.cum[1][a2] * w;
             }
-          box_reduce_add<Real, 5, 2, 3>(sk, 1, lane, x1, x2, x3, v);
+          box_reduce_add<Real, NX, 2, 3>(sk, 1, lane, x1, x2, x3, v);
         }
         {
-          Real v[30];
+          Real v[NX * 6];
 #pragma unroll
           for (int a2 = 0; a2 < 3; ++a2)
 #pragma unroll
-            for (int b = 0; b < 5; ++b) {
+            for (int b = 0; b < NX; ++b) {
               const Real w = e1S0[b] * P2[a2] + e1DS[b] * Q2[a2];
 #pragma unroll
-              for (int a3 = 0; a3 < 2; ++a3) v[b + 5 * (a2 + 3 * a3)] = z * q.f3 * m.cum[2][a3] * w;
+              for (int a3 = 0; a3 < 2; ++a3) v[b + NX * (a2 + 3 * a3)] = z * q.f3 * m.cum[2][a3] * w;
             }
-          box_reduce_add<Real, 5, 3, 2>(sk, 2, lane, x1, x2, x3, v);
+          box_reduce_add<Real, NX, 3, 2>(sk, 2, lane, x1, x2, x3, v);
         }
       } else {
         {
@@ -480,7 +486,7 @@ __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, 
 // One workgroup's share of the particle phase: chunk `chunk` of K * 256
 // particles.  tile_raw: kTileBytes of LDS, box: kChunkBoxInts ints of LDS; *mybox
 // receives the chunk's deposit box.
-template <typename Real, int DIM>
+template <typename Real, int DIM, int W = 2>
 __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
                                            const Particles<Real> &p, const PushParams<Real> &q, int K,
                                            long long chunk, JBox *mybox, int *err, unsigned char *tile_raw,
@@ -792,7 +798,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
         p.u3[i] = un3;
       }
     }
-    if (deposit_wave<Real, DIM>(active, m, q, sk)) deposit_direct<Real, DIM>(m, q, sk);
+    if (deposit_wave<Real, DIM, W>(active, m, q, sk)) deposit_direct<Real, DIM>(m, q, sk);
   }
 
   // ---- flush the tile to HBM: one atomic per non-zero point
