@@ -88,11 +88,11 @@ TABLE1_C = [
 ]
 
 
-def run_gpu(args, w, cell, off, u, Q, solver):
+def run_gpu(args, w, cell, off, u, Q, solver, precision=None):
     import torch
     from paper_1910_13529_amd.relpic import Sim
     grid = dict(ndim=3, n=w.n, dx=w.dx, dt=w.dt, window=True, window_speed=1.0)
-    sim = Sim(grid, C=TABLE1_C if solver == "custom" else None, precision=args.precision)
+    sim = Sim(grid, C=TABLE1_C if solver == "custom" else None, precision=precision or args.precision)
     sid = sim.add_species(-1.0, Q, len(cell))
     sim.load_particles(sid, cell, off, u)
     try:
@@ -293,13 +293,8 @@ def adjoint_main(args):
     print(json.dumps(out), flush=True)
 
 
-def plasma_main(args):
-    """The 3D beam in a uniform plasma: the beam grid and bunch plus plasma
-    electrons at 8 particles per cell on a 2x2x2 quiet-start lattice (u ~
-    1e-4 N(0, 1) per component, weight dV/8, immobile ions), injected into the
-    front slab at every window shift; customized solver, fused field update.
-    The plasma is generated on the host in x1 slabs and appended."""
-    import numpy as np
+def run_plasma(args, precision, warmup, steps):
+    """One run of the beam-in-plasma workload; returns timings and diagnostics."""
     import torch
     from paper_1910_13529_amd import inputs
     from paper_1910_13529_amd.relpic import Sim
@@ -308,11 +303,12 @@ def plasma_main(args):
     dV = w.dx[0] * w.dx[1] * w.dx[2]
     Qp = -dV / 8.0  # n0 = 1
     ppc = (2, 2, 2)
-    shifts = (args.warmup + args.steps + 64) // 4 + 2
+    nprof = max(8, min(steps, 32))
+    shifts = (warmup + steps + nprof) // 4 + 2
     n_plasma0 = (n1 - 4) * n2 * n3 * 8
     cap = n_plasma0 + shifts * n2 * n3 * 8
     grid = dict(ndim=3, n=w.n, dx=w.dx, dt=w.dt, window=True, window_speed=1.0)
-    sim = Sim(grid, C=TABLE1_C, precision=args.precision)
+    sim = Sim(grid, C=TABLE1_C, precision=precision)
     try:
         fused = sim.set_fused_fields(not args.separate_fields)
     except RuntimeError:
@@ -320,33 +316,46 @@ def plasma_main(args):
     sb = sim.add_species(-1.0, Q, len(cell))
     sim.load_particles(sb, cell, off, u)
     sp = sim.add_species(-1.0, Qp, cap)
-    print("[bench] plasma: %d particles in %d slabs" % (n_plasma0, (n1 - 4 + 31) // 32), file=sys.stderr, flush=True)
+    print("[bench] plasma %s: %d particles in %d slabs" % (precision, n_plasma0, (n1 - 4 + 31) // 32),
+          file=sys.stderr, flush=True)
     for k, lo in enumerate(range(2, n1 - 2, 32)):
         hi = min(lo + 32, n1 - 2)
         c, o, uu = inputs.plasma_lattice(100 + k, (lo, 0, 0), (hi, n2, n3), ppc, 1e-4)
         sim.load_particles(sp, c, o, uu)
         del c, o, uu
     sim.set_injection(sp, ppc, 1e-4, 12345)
-    npart = len(cell) + n_plasma0
-    sim.step(args.warmup)
+    print("[bench] plasma %s: %d warmup + %d timed steps" % (precision, warmup, steps), file=sys.stderr, flush=True)
+    sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    sim.step(steps)
     sim.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sim.profile_enable(True)
-    nprof = max(8, min(args.steps, 32))
     sim.step(nprof)
     prof = sim.profile_read()
     sim.profile_enable(False)
     diag = sim.diagnostics()
     sim.close()
-    ncells = n1 * n2 * n3
+    return dict(w=w, npart=len(cell) + n_plasma0, wall_s=wall, prof=prof, nprof=nprof, diag=diag, fused=fused)
+
+
+def plasma_main(args):
+    """The 3D beam in a uniform plasma: the beam grid and bunch plus plasma
+    electrons at 8 particles per cell on a 2x2x2 quiet-start lattice (u ~
+    1e-4 N(0, 1) per component, weight dV/8, immobile ions), injected into the
+    front slab at every window shift; customized solver, fused field update.
+    The plasma is generated on the host in x1 slabs and appended.  With FP32
+    the same workload also runs in FP64 for --fp64-steps steps."""
+    r = run_plasma(args, args.precision, args.warmup, args.steps)
+    w, npart, wall, prof, nprof = r["w"], r["npart"], r["wall_s"], r["prof"], r["nprof"]
+    ncells = int(math.prod(w.n))
     esz = 4 if args.precision == "fp32" else 8
     ms = 1e3 * wall / args.steps
-    pavg = prof["push_deposit"][1] / max(prof["push_deposit"][0], 1)
+    # both species' push launches of a step against the flops of all particles
+    push_ms = prof["push_deposit"][1] / nprof
     flops = push_flops_per_particle(3) * npart
     peak_alu = FP32_VECTOR_PEAK_TFLOPS if args.precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
     out = {
@@ -366,14 +375,26 @@ def plasma_main(args):
         "config": {"workload": "3D beam in uniform plasma: beam grid and bunch plus plasma electrons at 8 ppc "
                                "(2x2x2 lattice, u_th=1e-4, immobile ions), front-slab injection at each window "
                                "shift, customized solver", "cells": ncells, "particles": npart,
-                   "fused_field_update": fused, "parallelism": "single GPU"},
-        "roofline_push": {"bound": "alu", "kernel": "push_deposit", "avg_launch_ms": pavg,
-                          "achieved": flops / (pavg * 1e-3) / 1e12, "peak": peak_alu, "unit": "TFLOP/s",
-                          "frac": flops / (pavg * 1e-3) / 1e12 / peak_alu,
-                          "hbm_achieved_gbs": algorithmic_bytes("push_deposit", ncells, npart, esz) / (pavg * 1e-3) / 1e9},
+                   "fused_field_update": r["fused"], "parallelism": "single GPU"},
+        "roofline_push": {"bound": "alu", "kernel": "push_deposit", "push_ms_per_step": push_ms,
+                          "achieved": flops / (push_ms * 1e-3) / 1e12, "peak": peak_alu, "unit": "TFLOP/s",
+                          "frac": flops / (push_ms * 1e-3) / 1e12 / peak_alu,
+                          "hbm_achieved_gbs": algorithmic_bytes("push_deposit", ncells, npart, esz) / (push_ms * 1e-3) / 1e9},
         "kernel_ms_per_step": {k: prof[k][1] / nprof for k in prof if prof[k][0]},
-        "diag": {k: diag[k] for k in ("step", "window_start", "n_alive", "w_field", "w_kin", "error_word")},
+        "diag": {k: r["diag"][k] for k in ("step", "window_start", "n_alive", "w_field", "w_kin", "error_word")},
     }
+    if args.precision == "fp32" and not args.no_fp64 and args.fp64_steps > 0:
+        wu = min(args.warmup, 5)
+        r64 = run_plasma(args, "fp64", wu, args.fp64_steps)
+        p64 = r64["prof"]
+        out["fp64"] = {
+            "steps": args.fp64_steps, "warmup": wu,
+            "ms_per_step": 1e3 * r64["wall_s"] / args.fp64_steps,
+            "particle_steps_per_s": npart * args.fp64_steps / r64["wall_s"],
+            "cell_updates_per_s": ncells * args.fp64_steps / r64["wall_s"],
+            "kernel_ms_per_step": {k: p64[k][1] / r64["nprof"] for k in p64 if p64[k][0]},
+            "diag": {k: r64["diag"][k] for k in ("step", "n_alive", "w_field", "w_kin", "error_word")},
+        }
     print(json.dumps(out), flush=True)
 
 
@@ -431,6 +452,8 @@ def main():
     ap.add_argument("--npart", type=int, default=1 << 22)
     ap.add_argument("--solvers", default="custom,yee")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run of the same workload")
+    ap.add_argument("--fp64-steps", type=int, default=20, help="timed steps of the plasma workload's FP64 run")
     ap.add_argument("--separate-fields", action="store_true",
                     help="3D beam: separate E and B updates instead of the fused one")
     ap.add_argument("--workload", default="beam3d", choices=["beam3d", "batch", "adjoint", "plasma3d"],
@@ -589,6 +612,29 @@ def main():
             "cell_updates_per_s": ncells * args.steps / rr["wall_s"],
             "particle_steps_per_s": npart * args.steps / rr["wall_s"],
             "kernel_ms_per_step": {k: rr["prof"][k][1] / rr["nprof"] for k in rr["prof"] if rr["prof"][k][0]},
+        }
+    if args.precision == "fp32" and not args.no_fp64:
+        # the same workload in FP64 (same steps): throughput and how far the
+        # FP32 run's FP64 diagnostics are from it at the same step
+        print("[bench] %s solver, FP64: %d warmup + %d timed steps" % (head, args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        r64 = run_gpu(args, w, cell, off, u, Q, head, precision="fp64")
+        p64 = r64["prof"]
+        d32, d64 = r["diag"], r64["diag"]
+        out["fp64"] = {
+            "ms_per_step": 1e3 * r64["wall_s"] / args.steps,
+            "cell_updates_per_s": ncells * args.steps / r64["wall_s"],
+            "particle_steps_per_s": npart * args.steps / r64["wall_s"],
+            "kernel_ms_per_step": {k: p64[k][1] / r64["nprof"] for k in p64 if p64[k][0]},
+            "fields_hbm_frac": {
+                k: algorithmic_bytes(k, ncells, npart, 8) / (p64[k][1] / p64[k][0] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                for k in ("curl_e", "curl_b", "leap") if p64.get(k, (0, 0))[0] > 0},
+            "fp32_vs_fp64_at_step_%d" % d64["step"]: {
+                "w_field_rel": abs(d32["w_field"] - d64["w_field"]) / abs(d64["w_field"]),
+                "w_kin_rel": abs(d32["w_kin"] - d64["w_kin"]) / abs(d64["w_kin"]),
+                "charge_rel": abs(d32["charge"] - d64["charge"]) / abs(d64["charge"]),
+                "gauss_max_fp32": d32["gauss_max"], "gauss_max_fp64": d64["gauss_max"], "rho_max": d64["rho_max"],
+            } if d32["step"] == d64["step"] else None,
         }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)

@@ -147,6 +147,9 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
     // chunks of 256 K particles that fill about one tile
     const double per_tile = ppc * (s->ndim == 3 ? 128.0 : 32.0);
     sp.K = per_tile > 1024.0 ? 8 : (per_tile > 512.0 ? 4 : (per_tile > 256.0 ? 2 : 1));
+    // FP64: a tile and its halo hold 9 words per cell in the same LDS, so
+    // chunks span at most half a tile
+    if (sizeof(Real) == 8 && sp.K > 2) sp.K = 2;
   } else {
     sp.K = ppc >= 512.0 ? 8 : (ppc >= 64.0 ? 4 : (ppc >= 16.0 ? 2 : 1));
   }

@@ -59,8 +59,8 @@ void launch_leap(const Geo &g, Real *const Ein[3], Real *const Eout[3], Real *co
 
 // K particles per thread; each workgroup handles a contiguous chunk of
 // 256 * K particles (sorted by cell for the LDS-tiled deposit to pay off);
-// wide (3D): deposit rounds over boxes four x1 cells wide instead of two, for
-// species spread over the grid at a few particles per cell
+// wide (3D, FP32): deposit rounds over boxes four x1 cells wide instead of
+// two, for species spread over the grid at a few particles per cell
 // blockbox: push_blocks(n, K) scratch boxes, merged into *jbox after the launch
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,

@@ -39,10 +39,14 @@ inline int leap_planes(const Geo &g, int R) {
 
 // x2 rows per workgroup: more rows share the recomputed neighbour row, fewer
 // keep the per-plane operands in registers at 4 waves per SIMD (FP32: 121
-// VGPRs at two rows, 204 at four)
+// VGPRs at two rows, 204 at four; FP64: 186 at two rows, so one)
 template <typename Real>
 struct LeapRows {
   static constexpr int R = 2;
+};
+template <>
+struct LeapRows<double> {
+  static constexpr int R = 1;
 };
 
 template <typename Real, int R>

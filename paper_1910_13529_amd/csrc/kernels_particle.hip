@@ -89,7 +89,8 @@ void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const Ha
                          int *err, hipStream_t st) {
   if (p.n <= 0) return;
   const unsigned blocks = (unsigned)push_blocks(p.n, K);
-  if (ndim == 3 && wide)
+  // FP64 keeps the narrow rounds: the wide ones take it from two waves per SIMD to one
+  if (ndim == 3 && wide && sizeof(Real) == 4)
     k_push_deposit<Real, 3, 4><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
   else if (ndim == 3)
     k_push_deposit<Real, 3, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
