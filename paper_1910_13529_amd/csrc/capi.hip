@@ -105,7 +105,9 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
   Particles<Real> src = parts<Real>(sp);
   const Geo g = make_geo(s);
   const bool tiles = sp.tile_keys && sort_tiles_fit(g);
-  launch_sort_keys<Real>(g, src, tiles ? 1 : 0, sp.keys, sp.idx, s->st);
+  // tile x1 width 2^tx: FP64 tiles are half as wide (LDS holds half the cells)
+  const int tx = sizeof(Real) == 8 ? 2 : 3;
+  launch_sort_keys<Real>(g, src, tiles ? tx : 0, sp.keys, sp.idx, s->st);
   size_t need = 0;
   HIP_OK(sort_pairs(nullptr, need, sp.keys, sp.keys2, sp.idx, sp.idx2, sp.n, s->st));
   if (need > sp.sort_tmp_bytes) {
@@ -144,12 +146,12 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
     return do_sort<Real>(s, sp);
   }
   if (tiles) {
-    // chunks of 256 K particles that fill about one tile
-    const double per_tile = ppc * (s->ndim == 3 ? 128.0 : 32.0);
-    sp.K = per_tile > 1024.0 ? 8 : (per_tile > 512.0 ? 4 : (per_tile > 256.0 ? 2 : 1));
-    // FP64: a tile and its halo hold 9 words per cell in the same LDS, so
-    // chunks span at most half a tile
-    if (sizeof(Real) == 8 && sp.K > 2) sp.K = 2;
+    // chunks of 256 K particles, at most one tile's worth: a chunk then spans
+    // parts of at most two x1-neighbouring tiles, whose cells with the
+    // deposit halo (3D FP32: 20 x 8 x 8, FP64: 12 x 8 x 8) fit the push's
+    // LDS tile
+    const double per_tile = ppc * (double)((s->ndim == 3 ? 16 : 4) << tx);
+    sp.K = per_tile >= 2048.0 ? 8 : (per_tile >= 1024.0 ? 4 : (per_tile >= 512.0 ? 2 : 1));
   } else {
     sp.K = ppc >= 512.0 ? 8 : (ppc >= 64.0 ? 4 : (ppc >= 16.0 ? 2 : 1));
   }

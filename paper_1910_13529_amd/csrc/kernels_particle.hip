@@ -26,9 +26,10 @@ template <typename Real, int DIM, int W>
 __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real> f, HalfB<Real> Bh,
                                                              Particles<Real> p, PushParams<Real> q, int K,
                                                              JBox *blockbox, int *err) {
-  __shared__ __align__(16) unsigned char tile_raw[kTileBytes];
+  constexpr int TILE = PushTile<Real>::bytes;
+  __shared__ __align__(16) unsigned char tile_raw[TILE];
   __shared__ int box[kChunkBoxInts];
-  push_chunk<Real, DIM, W>(g, f, Bh, p, q, K, blockIdx.x, blockbox + blockIdx.x, err, tile_raw, box);
+  push_chunk<Real, DIM, W, TILE>(g, f, Bh, p, q, K, blockIdx.x, blockbox + blockIdx.x, err, tile_raw, box);
 }
 
 // Box of a set of per-workgroup boxes merged into *out: each workgroup
@@ -106,11 +107,11 @@ void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStr
 
 // ---- particle sort (cell order) ---------------------------------------------------
 
-// Sort key of a packed cell: with tiles on, cells are grouped in 8 x 4 x 4
-// (2D: 8 x 4) tiles of storage cells, x1 fastest inside a tile, so that a
-// chunk of consecutive particles covers a compact 3D region (its LDS box
-// stays small when the particles fill the grid, as a plasma does); off, the
-// packed index itself.  Both are one-to-one on cells.
+// Sort key of a packed cell: with tiles = t > 0, cells are grouped in
+// 2^t x 4 x 4 (2D: 2^t x 4) tiles of storage cells, x1 fastest inside a tile,
+// so that a chunk of consecutive particles covers a compact 3D region (its
+// LDS box stays small when the particles fill the grid, as a plasma does);
+// tiles = 0: the packed index itself.  Both are one-to-one on cells.
 template <typename Real>
 __global__ void k_sort_keys(Geo g, Particles<Real> p, int tiles, unsigned *keys, unsigned *idx) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -119,13 +120,14 @@ __global__ void k_sort_keys(Geo g, Particles<Real> p, int tiles, unsigned *keys,
   unsigned k = 0xFFFFFFFFu;
   if (c >= 0) {
     k = (unsigned)c;
-    if (tiles) {
+    if (tiles > 0) {
       int s1, c2, c3;
       unpack_cell(g, c, s1, c2, c3);
-      const unsigned nt1 = (unsigned)(g.n1 + 7) >> 3, nt2 = (unsigned)(g.n2 + 3) >> 2;
-      const unsigned tile = ((unsigned)(c3 >> 2) * nt2 + (unsigned)(c2 >> 2)) * nt1 + (unsigned)(s1 >> 3);
-      const unsigned local = ((unsigned)(c3 & 3) * 4 + (unsigned)(c2 & 3)) * 8 + (unsigned)(s1 & 7);
-      k = tile * (g.n3 > 1 ? 128u : 32u) + local;
+      const unsigned w1 = 1u << tiles;
+      const unsigned nt1 = ((unsigned)g.n1 + w1 - 1) >> tiles, nt2 = (unsigned)(g.n2 + 3) >> 2;
+      const unsigned tile = ((unsigned)(c3 >> 2) * nt2 + (unsigned)(c2 >> 2)) * nt1 + ((unsigned)s1 >> tiles);
+      const unsigned local = (((unsigned)(c3 & 3) * 4 + (unsigned)(c2 & 3)) << tiles) + ((unsigned)s1 & (w1 - 1));
+      k = tile * ((g.n3 > 1 ? 16u : 4u) << tiles) + local;
     }
   }
   keys[i] = k;

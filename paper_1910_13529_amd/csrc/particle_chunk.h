@@ -11,6 +11,16 @@ namespace relpic {
 
 constexpr int kPushBlock = 256;
 constexpr int kTileBytes = 49152;  // LDS tile per workgroup: J (3 components) + E, B (6)
+// The single-run FP64 push runs two waves per SIMD (two workgroups per CU),
+// which leaves room for a larger tile: 768 cells of 9 FP64 words.
+template <typename Real>
+struct PushTile {
+  static constexpr int bytes = kTileBytes;
+};
+template <>
+struct PushTile<double> {
+  static constexpr int bytes = 61440;
+};
 constexpr int kChunkBoxInts = 10;  // LDS words of a chunk's box: min/max per axis, tile dividers
 
 typedef __attribute__((address_space(3))) float lds_f32;
@@ -484,9 +494,9 @@ __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, 
 }
 
 // One workgroup's share of the particle phase: chunk `chunk` of K * 256
-// particles.  tile_raw: kTileBytes of LDS, box: kChunkBoxInts ints of LDS; *mybox
+// particles.  tile_raw: TILE bytes of LDS, box: kChunkBoxInts ints of LDS; *mybox
 // receives the chunk's deposit box.
-template <typename Real, int DIM, int W = 2>
+template <typename Real, int DIM, int W = 2, int TILE = kTileBytes>
 __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
                                            const Particles<Real> &p, const PushParams<Real> &q, int K,
                                            long long chunk, JBox *mybox, int *err, unsigned char *tile_raw,
@@ -586,7 +596,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
   if (box[0] != INT_MAX) {
     const long long T1 = (long long)box[1] - box[0] + 5, T2 = (long long)box[3] - box[2] + 5;
     const long long T3 = DIM == 3 ? (long long)box[5] - box[4] + 5 : 1;
-    if (9 * T1 * T2 * T3 * (long long)sizeof(Real) <= kTileBytes) {
+    if (9 * T1 * T2 * T3 * (long long)sizeof(Real) <= TILE) {
       sk.T1 = (int)T1;
       sk.T2 = (int)T2;
       sk.T3 = (int)T3;
