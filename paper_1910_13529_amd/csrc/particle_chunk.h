@@ -513,20 +513,29 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
   __syncthreads();
   {
     int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
-    for (int k = 0; k < K; ++k) {
-      const long long i = chunk0 + (long long)k * kPushBlock + tid;
-      if (i >= p.n) break;
-      const int packed = p.cell[i];
-      if (packed < 0) continue;
-      int s1, c2, c3;
-      unpack_cell(g, packed, s1, c2, c3);
-      int c1 = s1 - g.ws_mod;
-      if (c1 < 0) c1 += g.n1;
-      const int cc[3] = {c1, c2, c3};
+    // the cells of up to 8 particles per thread are loaded together, so their
+    // latencies overlap
+    for (int k0 = 0; k0 < K; k0 += 8) {
+      int cells[8];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        mn[d] = min(mn[d], cc[d]);
-        mx[d] = max(mx[d], cc[d]);
+      for (int j = 0; j < 8; ++j) {
+        const long long i = chunk0 + (long long)(k0 + j) * kPushBlock + tid;
+        cells[j] = (k0 + j < K && i < p.n) ? p.cell[i] : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int packed = cells[j];
+        if (packed < 0) continue;
+        int s1, c2, c3;
+        unpack_cell(g, packed, s1, c2, c3);
+        int c1 = s1 - g.ws_mod;
+        if (c1 < 0) c1 += g.n1;
+        const int cc[3] = {c1, c2, c3};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          mn[d] = min(mn[d], cc[d]);
+          mx[d] = max(mx[d], cc[d]);
+        }
       }
     }
 #pragma unroll
