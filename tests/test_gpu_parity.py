@@ -208,10 +208,14 @@ def test_fused_field_update_availability():
         g3b.set_fused_fields(True)
 
 
-def test_plasma_injection_window_fp64():
+@pytest.mark.parametrize("precision,tol,xtol,utol,steps,sort_every", [
+    ("fp64", 1e-12, 1e-12, 1e-13, 13, 0), ("fp64", 1e-12, 1e-12, 1e-13, 30, 5), ("fp32", 2e-5, 2e-5, 2e-5, 30, 5)])
+def test_plasma_injection_window(precision, tol, xtol, utol, steps, sort_every):
     # cold plasma ahead of a beam in the moving window: the window injects a
     # slab of 2x2x2 particles per cell at each shift, momenta from the shared
-    # counter-based generator
+    # counter-based generator.  With re-sorts every few steps the plasma is
+    # sorted by tiles of storage cells after the window has moved (ring
+    # buffer offset), and in FP32 deposits with the wide rounds.
     n, dx, dt = (40, 8, 8), (0.02, 0.05, 0.05), 0.005
     cellp, offp, up = inputs.plasma_lattice(4, (2, 0, 0), (n[0] - 2, n[1], n[2]), (2, 2, 2), 1e-4)
     keep = cellp[:, 0] <= n[0] - 3
@@ -219,25 +223,36 @@ def test_plasma_injection_window_fp64():
     Qp = -(0.02 * 0.05 * 0.05) / 8.0
     nplasma = len(cellp)
     inj_per_shift = 8 * n[1] * n[2]
-    cap = nplasma + 4 * inj_per_shift
+    shifts = steps // 4
+    cap = nplasma + (shifts + 1) * inj_per_shift
     beam = beam_species(5, 300, n, dx, 1e4, Q=-1e-4, sigma_cells=(3.0, 1.0, 1.0), center_frac=0.5)
-    g, o, ids = make_pair(3, n, dx, dt, TABLE1, True, [beam, (Qp, -1.0, cellp, offp, up, cap)])
+    g, o, ids = make_pair(3, n, dx, dt, TABLE1, True, [beam, (Qp, -1.0, cellp, offp, up, cap)], precision=precision)
     g.set_injection(ids[1], (2, 2, 2), 1e-4, 1234)
     o.set_injection((2, 2, 2), Qp, -1.0, 1e-4, 1234)
-    g.step(13)
-    o.step(13)
+    if sort_every:
+        g.set_sort_interval(sort_every)
+    g.step(steps)
+    o.step(steps)
     errs = field_errors(g, o)
-    log("plasma injection: %s" % errs)
-    assert max(errs.values()) < 1e-12, errs
+    log("plasma injection %s, %d steps, sort every %d: %s" % (precision, steps, sort_every, errs))
+    assert max(errs.values()) < tol, errs
     # oracle stores both species in one list: beam first, then plasma
+    # (particle ids: load order, then injection order); a re-sort drops the
+    # particles that left the window, which the oracle keeps as dead slots
     xo, uo, ao = o.particles()
+    xo, uo, ao = xo[300:], uo[300:], ao[300:]
+    assert len(ao) == nplasma + shifts * inj_per_shift
     cell, off, u, alive = g.particles(ids[1], cap)
-    assert len(alive) == nplasma + 3 * inj_per_shift
-    xg = cell.astype(np.float64) + off
-    sl = slice(300, None)
-    assert (alive == ao[sl]).all()
-    assert np.abs(xg[alive] - xo[sl][ao[sl]]).max() < 1e-12
-    assert np.abs(u[alive] - uo[sl][ao[sl]]).max() < 1e-12 * 1e-4 * 10
+    gid = g.last_ids[alive]
+    assert np.array_equal(gid, np.flatnonzero(ao))
+    xg = cell[alive].astype(np.float64) + off[alive]
+    dxm = float(np.abs(xg - xo[gid]).max())
+    # momenta against the largest plasma momentum (the beam's field kicks the
+    # plasma electrons from u_th = 1e-4 to a few 1e-2)
+    umax = float(np.abs(uo[gid]).max())
+    dum = float(np.abs(u[alive] - uo[gid]).max()) / umax
+    log("  plasma particles: max |dx| %.3g cells, max |du|/max |u| %.3g (max |u| %.3g)" % (dxm, dum, umax))
+    assert dxm < xtol and dum < utol
 
 
 @pytest.mark.parametrize("ndim", [3, 2])
