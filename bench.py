@@ -25,6 +25,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+TRAFFIC_FILE_BATCH = os.path.join(ROOT, "profiles", "traffic_counters_batch.json")
+
+
+def measured_traffic(path, key):
+    """HBM bytes per launch of kernel class `key` ("solver/precision/class")
+    from a calibrated rocprofv3 counter summary, or None when the summary is
+    missing or was taken from other kernel sources."""
+    try:
+        tf = json.load(open(path))
+        from paper_1910_13529_amd.profiling import kernel_source_hash
+        if tf.get("source_hash") != kernel_source_hash():
+            return None
+        ent = tf.get("kernels", {}).get(key)
+        return ent["hbm_bytes_per_launch"] if ent else None
+    except Exception:
+        return None
 
 
 def algorithmic_bytes(kernel, ncells, npart, esz):
@@ -225,7 +241,8 @@ def batch_main(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(TRAFFIC_FILE_BATCH, "batch/%s/batch_curl_e" % args.precision)
+            if args.batch_solver == "mixed" else None,
             "avg_launch_ms": avg_ms,
             "algorithmic_bytes_per_launch": alg,
         },
