@@ -93,6 +93,7 @@ long long window_target(const relpic_sim *s, long long steps_done) {
 // chunks then straddle no tile seams).  Mean particles per occupied cell
 // below kTileBelow switches to tiles, above kRowsAbove back to rows.
 constexpr double kTileBelow = 64.0, kRowsAbove = 128.0;
+constexpr long long kMinPushChunks = 512;
 
 // Sort a species by cell (dropped particles last), drop the dropped ones,
 // and pick the push chunk size from the particles per occupied cell.  When
@@ -155,6 +156,9 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
   } else {
     sp.K = ppc >= 512.0 ? 8 : (ppc >= 64.0 ? 4 : (ppc >= 16.0 ? 2 : 1));
   }
+  // a small species still gets about two chunks per CU (a dense bunch of
+  // 65536 particles in 32 chunks left seven of eight CUs idle)
+  while (sp.K > 1 && push_blocks(sp.n, sp.K) < kMinPushChunks) sp.K /= 2;
   return RELPIC_OK;
 }
 
