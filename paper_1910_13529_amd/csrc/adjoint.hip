@@ -270,22 +270,29 @@ relpic_status do_backward(relpic_adj *a, double *dLdC) {
     if (relpic_status e = particles_copy(a, arrs, 1)) return e;
     launch_reset_box(s->jbox + (c0 & 1), s->st);
     // recompute the segment, storing e_n, b_n (n = c0 .. c1), b_{c1+1}, J1c_n and the boxes
+    // (one copy launch per step: e_n, b_n, and the box and J1c of step n - 1,
+    // which step n's particle phase overwrites)
     for (long long n = c0; n <= c1; ++n) {
       const long long k = n - c0;
-      for (int d = 0; d < 3; ++d) {
-        HIP_OK(hipMemcpyAsync(segE(k, d), c.E[d], c.fb, hipMemcpyDeviceToDevice, s->st));
-        HIP_OK(hipMemcpyAsync(segB(k, d), c.bc[d], c.fb, hipMemcpyDeviceToDevice, s->st));
+      CopyList cl;
+      cl.n = 0;
+      if (k > 0) {
+        cl.op[cl.n++] = CopyOp{a->segbox + (k - 1), s->jbox + ((n - 1) & 1), sizeof(JBox)};
+        if (M > 1) cl.op[cl.n++] = CopyOp{slot_ptr(a->segJ, c.fb, k - 1), s->F[9], c.fb};
       }
+      for (int d = 0; d < 3; ++d) {
+        cl.op[cl.n++] = CopyOp{segE(k, d), c.E[d], c.fb};
+        cl.op[cl.n++] = CopyOp{segB(k, d), c.bc[d], c.fb};
+      }
+      launch_copy_many(cl, s->st);
       c.curl_plus(c.E, c.bc, c.bn, c.dt);
       if (n == c1) {
-        for (int d = 0; d < 3; ++d)
-          HIP_OK(hipMemcpyAsync(segB(k + 1, d), c.bn[d], c.fb, hipMemcpyDeviceToDevice, s->st));
+        cl.n = 0;
+        for (int d = 0; d < 3; ++d) cl.op[cl.n++] = CopyOp{segB(k + 1, d), c.bn[d], c.fb};
+        launch_copy_many(cl, s->st);
         break;
       }
       if (relpic_status e = c.advance_e(n)) return e;
-      HIP_OK(hipMemcpyAsync(a->segbox + k, s->jbox + (n & 1), sizeof(JBox), hipMemcpyDeviceToDevice, s->st));
-      if (M > 1)
-        HIP_OK(hipMemcpyAsync(slot_ptr(a->segJ, c.fb, k), s->F[9], c.fb, hipMemcpyDeviceToDevice, s->st));
       c.swap_b();
     }
     // reverse sweep over n = c1 .. c0 + 1

@@ -32,4 +32,18 @@ template <typename Real>
 void launch_adj_grad_jcorr(const Geo &g, int M, const Real *aE1, const Real *J1c, const Real *taps, int ng,
                            const JBox *box, double scale, double *out, hipStream_t st);
 
+// Up to kCopyOps device-to-device copies in one launch (the per-step
+// segment stores of the reverse pass; separate copies cost a launch each).
+constexpr int kCopyOps = 8;
+struct CopyOp {
+  void *dst;
+  const void *src;
+  size_t bytes;
+};
+struct CopyList {
+  CopyOp op[kCopyOps];
+  int n;
+};
+void launch_copy_many(const CopyList &list, hipStream_t st);
+
 }  // namespace relpic

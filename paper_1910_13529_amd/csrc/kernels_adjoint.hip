@@ -189,6 +189,37 @@ void launch_adj_grad_jcorr(const Geo &g, int M, const Real *aE1, const Real *J1c
   k_adj_grad_jcorr<Real><<<dim3(64, M), 256, 0, st>>>(g, aE1, J1c, taps, ng, box, scale, out);
 }
 
+// Grid-stride copy of every op: 16-byte words where both pointers and the
+// size allow it, else 4-byte words, else bytes.
+__global__ __launch_bounds__(256) void k_copy_many(CopyList list) {
+  const size_t t0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < list.n; ++k) {
+    const CopyOp o = list.op[k];
+    const uintptr_t al = (uintptr_t)o.dst | (uintptr_t)o.src | (uintptr_t)o.bytes;
+    if ((al & 15) == 0) {
+      uint4 *d = (uint4 *)o.dst;
+      const uint4 *sr = (const uint4 *)o.src;
+      for (size_t i = t0; i < o.bytes / 16; i += stride) d[i] = sr[i];
+    } else if ((al & 3) == 0) {
+      unsigned *d = (unsigned *)o.dst;
+      const unsigned *sr = (const unsigned *)o.src;
+      for (size_t i = t0; i < o.bytes / 4; i += stride) d[i] = sr[i];
+    } else {
+      unsigned char *d = (unsigned char *)o.dst;
+      const unsigned char *sr = (const unsigned char *)o.src;
+      for (size_t i = t0; i < o.bytes; i += stride) d[i] = sr[i];
+    }
+  }
+}
+
+void launch_copy_many(const CopyList &list, hipStream_t st) {
+  if (list.n <= 0) return;
+  size_t words = 0;
+  for (int k = 0; k < list.n; ++k) words = list.op[k].bytes / 16 > words ? list.op[k].bytes / 16 : words;
+  const size_t want = (words + 255) / 256;
+  k_copy_many<<<(unsigned)(want < 1 ? 1 : (want > 2048 ? 2048 : want)), 256, 0, st>>>(list);
+}
+
 #define RELPIC_INST_ADJ(Real)                                                                                      \
   template void launch_adj_loss<Real>(const Geo &, const Real *, const Real *, const Real *, const Real *,         \
                                       const LossBox &, double, double *, hipStream_t);                            \
