@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_adj_loss_grad(Geo g, const Real *E1, co
 //                      part 1 (T2): sum -eA2 (B3(i+l-1) - B3(i-l)) + eA3 (B2(i+l-1) - B2(i-l))
 // times `scale`, added to out[l - 1].
 template <typename Real>
-__global__ __launch_bounds__(256) void k_adj_grad_curl(Geo g, int part, const Real *A2, const Real *A3,
+__global__ __launch_bounds__(256) void k_adj_grad_curl_flat(Geo g, int part, const Real *A2, const Real *A3,
                                                        const Real *F2, const Real *F3, double scale, double *out) {
   const int l = blockIdx.y + 1;
   double acc = 0.0;
@@ -160,14 +160,70 @@ __global__ __launch_bounds__(256) void k_adj_grad_jcorr(Geo g, const Real *aE1, 
   block_add(scale * acc, out + (l - 1));
 }
 
+// The same sums for every l <= M in one pass (M <= MM): a workgroup takes
+// whole x1 rows, stages F2, F3 of a row with MM cells of periodic halo on
+// each side in LDS (FP64), and each thread keeps one partial sum per l.
+template <typename Real, int MM>
+__global__ __launch_bounds__(256) void k_adj_grad_curl_rows(Geo g, int part, int M, const Real *A2, const Real *A3,
+                                                            const Real *F2, const Real *F3, double scale,
+                                                            double *out) {
+  extern __shared__ __align__(16) unsigned char gc_lds[];
+  __shared__ double wsum[4][MM];
+  const int pitch = g.n1 + 2 * MM;
+  double *f2 = reinterpret_cast<double *>(gc_lds);
+  double *f3 = f2 + pitch;
+  double acc[MM];
+#pragma unroll
+  for (int l = 0; l < MM; ++l) acc[l] = 0.0;
+  for (int r = blockIdx.x; r < g.n2; r += gridDim.x) {
+    const long long row = (long long)g.n1 * r;
+    __syncthreads();  // the previous row's readers are done
+    for (int t = threadIdx.x; t < pitch; t += blockDim.x) {
+      const int i = wrapi(t - MM, g.n1);
+      f2[t] = (double)F2[row + i];
+      f3[t] = (double)F3[row + i];
+    }
+    __syncthreads();
+    for (int i1 = threadIdx.x; i1 < g.n1; i1 += blockDim.x) {
+      const double a2 = (double)A2[row + i1], a3 = (double)A3[row + i1];
+      const double *c2 = f2 + MM + i1, *c3 = f3 + MM + i1;
+#pragma unroll
+      for (int l = 1; l <= MM; ++l) {
+        if (l > M) break;
+        if (part == 0)
+          acc[l - 1] += a2 * (c3[l] - c3[1 - l]) - a3 * (c2[l] - c2[1 - l]);
+        else
+          acc[l - 1] += -a2 * (c3[l - 1] - c3[-l]) + a3 * (c2[l - 1] - c2[-l]);
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int l = 0; l < MM; ++l) {
+    double v = acc[l];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) wsum[wave][l] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < M) {
+    const int l = threadIdx.x;
+    atomicAdd(out + l, scale * (wsum[0][l] + wsum[1][l] + wsum[2][l] + wsum[3][l]));
+  }
+}
+
 constexpr int kAdjGrid = 1024;
+// the loss sums into one FP64 word: one atomic per workgroup, and
+// same-address atomics serialize (1024 of them took ~12 us)
+constexpr int kAdjLossBlocks = 128;
+constexpr int kGradCurlRowsBlocks = 256;
 
 }  // namespace
 
 template <typename Real>
 void launch_adj_loss(const Geo &g, const Real *E1, const Real *E2, const Real *B3a, const Real *B3b,
                      const LossBox &lb, double w, double *out, hipStream_t st) {
-  k_adj_loss<Real><<<kAdjGrid, 256, 0, st>>>(g, E1, E2, B3a, B3b, lb, w, out);
+  k_adj_loss<Real><<<kAdjLossBlocks, 256, 0, st>>>(g, E1, E2, B3a, B3b, lb, w, out);
 }
 
 template <typename Real>
@@ -180,7 +236,21 @@ void launch_adj_loss_grad(const Geo &g, const Real *E1, const Real *E2, const Re
 template <typename Real>
 void launch_adj_grad_curl(const Geo &g, int part, int M, const Real *A2, const Real *A3, const Real *F2, const Real *F3,
                           double scale, double *out, hipStream_t st) {
-  k_adj_grad_curl<Real><<<dim3(kAdjGrid / 4, M), 256, 0, st>>>(g, part, A2, A3, F2, F3, scale, out);
+  const int MM = M <= 4 ? 4 : (M <= 8 ? 8 : (M <= 16 ? 16 : kMaxM));
+  const size_t lds = 2 * sizeof(double) * (size_t)(g.n1 + 2 * MM);
+  if (M > kMaxM || lds > 49152) {
+    k_adj_grad_curl_flat<Real><<<dim3(kAdjGrid / 4, M), 256, 0, st>>>(g, part, A2, A3, F2, F3, scale, out);
+    return;
+  }
+  const unsigned blocks = (unsigned)(g.n2 < kGradCurlRowsBlocks ? g.n2 : kGradCurlRowsBlocks);
+  if (MM == 4)
+    k_adj_grad_curl_rows<Real, 4><<<blocks, 256, lds, st>>>(g, part, M, A2, A3, F2, F3, scale, out);
+  else if (MM == 8)
+    k_adj_grad_curl_rows<Real, 8><<<blocks, 256, lds, st>>>(g, part, M, A2, A3, F2, F3, scale, out);
+  else if (MM == 16)
+    k_adj_grad_curl_rows<Real, 16><<<blocks, 256, lds, st>>>(g, part, M, A2, A3, F2, F3, scale, out);
+  else
+    k_adj_grad_curl_rows<Real, kMaxM><<<blocks, 256, lds, st>>>(g, part, M, A2, A3, F2, F3, scale, out);
 }
 
 template <typename Real>
