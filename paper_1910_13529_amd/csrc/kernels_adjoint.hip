@@ -161,6 +161,75 @@ __global__ __launch_bounds__(256) void k_adj_grad_jcorr(Geo g, const Real *aE1, 
 }
 
 // The same sums for every l <= M in one pass (M <= MM): a workgroup takes
+// rows of the support, stages the row's aE1 (reach ng + MM - 1 on each side)
+// in LDS, forms G aE1 there once, and adds the running sums
+// s_l = s_{l-1} + (G aE1)(i - l + 1) + (G aE1)(i + l - 1) per cell.
+template <typename Real, int MM>
+__global__ __launch_bounds__(256) void k_adj_grad_jcorr_rows(Geo g, int M, const Real *aE1, const Real *J1c,
+                                                             const Real *taps, int ng, const JBox *box, double scale,
+                                                             double *out) {
+  extern __shared__ __align__(16) unsigned char gj_lds[];
+  __shared__ double wsum[4][MM];
+  const JBox b = *box;
+  double acc[MM];
+#pragma unroll
+  for (int l = 0; l < MM; ++l) acc[l] = 0.0;
+  int w2 = 0;
+  if (b.hi[0] >= b.lo[0]) {
+    int lo1 = b.lo[0] - ng, hi1 = b.hi[0] + ng;
+    if (hi1 - lo1 + 1 >= g.n1) {
+      lo1 = 0;
+      hi1 = g.n1 - 1;
+    }
+    const int w1 = hi1 - lo1 + 1, h = MM - 1;
+    const int na = w1 + 2 * (h + ng), nge = w1 + 2 * h;
+    double *ae = reinterpret_cast<double *>(gj_lds);
+    double *ge = ae + na;
+    w2 = b.hi[1] - b.lo[1] + 1;
+    for (int r = blockIdx.x; r < w2; r += gridDim.x) {
+      const long long row = (long long)g.n1 * (b.lo[1] + r);
+      __syncthreads();  // the previous row's readers are done
+      for (int t = threadIdx.x; t < na; t += blockDim.x) ae[t] = (double)aE1[row + wrapi(lo1 - h - ng + t, g.n1)];
+      __syncthreads();
+      for (int t = threadIdx.x; t < nge; t += blockDim.x) {
+        const double *c = ae + ng + t;
+        double v = (double)taps[0] * c[0];
+        for (int m = 1; m <= ng; ++m) v += (double)taps[m] * (c[-m] + c[m]);
+        ge[t] = v;
+      }
+      __syncthreads();
+      for (int t = threadIdx.x; t < w1; t += blockDim.x) {
+        const double j = (double)J1c[row + wrapi(lo1 + t, g.n1)];
+        if (j == 0.0) continue;
+        const double *c = ge + h + t;
+        double sl = c[0];
+        acc[0] += j * sl;
+#pragma unroll
+        for (int l = 2; l <= MM; ++l) {
+          if (l > M) break;
+          sl += c[-(l - 1)] + c[l - 1];
+          acc[l - 1] += j * sl;
+        }
+      }
+    }
+  }
+  if ((int)blockIdx.x >= w2) return;  // no rows here (uniform over the workgroup)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int l = 0; l < MM; ++l) {
+    double v = acc[l];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) wsum[wave][l] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < M) {
+    const int l = threadIdx.x;
+    atomicAdd(out + l, scale * (wsum[0][l] + wsum[1][l] + wsum[2][l] + wsum[3][l]));
+  }
+}
+
+// The same sums for every l <= M in one pass (M <= MM): a workgroup takes
 // whole x1 rows, stages F2, F3 of a row with MM cells of periodic halo on
 // each side in LDS (FP64), and each thread keeps one partial sum per l.
 template <typename Real, int MM>
@@ -256,7 +325,20 @@ void launch_adj_grad_curl(const Geo &g, int part, int M, const Real *A2, const R
 template <typename Real>
 void launch_adj_grad_jcorr(const Geo &g, int M, const Real *aE1, const Real *J1c, const Real *taps, int ng,
                            const JBox *box, double scale, double *out, hipStream_t st) {
-  k_adj_grad_jcorr<Real><<<dim3(64, M), 256, 0, st>>>(g, aE1, J1c, taps, ng, box, scale, out);
+  const int MM = M <= 4 ? 4 : (M <= 8 ? 8 : (M <= 16 ? 16 : kMaxM));
+  const size_t lds = sizeof(double) * (size_t)(2 * g.n1 + 4 * (MM - 1) + 2 * ng);
+  if (M > kMaxM || lds > 49152) {
+    k_adj_grad_jcorr<Real><<<dim3(64, M), 256, 0, st>>>(g, aE1, J1c, taps, ng, box, scale, out);
+    return;
+  }
+  if (MM == 4)
+    k_adj_grad_jcorr_rows<Real, 4><<<64, 256, lds, st>>>(g, M, aE1, J1c, taps, ng, box, scale, out);
+  else if (MM == 8)
+    k_adj_grad_jcorr_rows<Real, 8><<<64, 256, lds, st>>>(g, M, aE1, J1c, taps, ng, box, scale, out);
+  else if (MM == 16)
+    k_adj_grad_jcorr_rows<Real, 16><<<64, 256, lds, st>>>(g, M, aE1, J1c, taps, ng, box, scale, out);
+  else
+    k_adj_grad_jcorr_rows<Real, kMaxM><<<64, 256, lds, st>>>(g, M, aE1, J1c, taps, ng, box, scale, out);
 }
 
 // Grid-stride copy of every op: 16-byte words where both pointers and the
