@@ -56,17 +56,18 @@ template <typename Real>
 __global__ __launch_bounds__(256) void k_adj_loss(Geo g, const Real *E1, const Real *E2, const Real *B3a,
                                                   const Real *B3b, LossBox lb, double w, double *out) {
   double acc = 0.0;
-  const long long N = (long long)g.n1 * g.n2;
-  for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < N; id += (long long)gridDim.x * blockDim.x) {
-    const int i1 = (int)(id % g.n1), i2 = (int)(id / g.n1);
-    const long long row = id - i1;
-    if (outside(lb, i1, 0.5, i2, 0.0)) {
-      const double e1 = (double)E1[id];
-      acc += e1 * e1;
-    }
-    if (outside(lb, i1, 0.0, i2, 0.5)) {
-      const double r = e2_minus_b3(g, E2, B3a, B3b, i1, row);
-      acc += r * r;
+  // rows per workgroup, cells per thread (no 64-bit index division)
+  for (int i2 = blockIdx.x; i2 < g.n2; i2 += gridDim.x) {
+    const long long row = (long long)g.n1 * i2;
+    for (int i1 = threadIdx.x; i1 < g.n1; i1 += blockDim.x) {
+      if (outside(lb, i1, 0.5, i2, 0.0)) {
+        const double e1 = (double)E1[row + i1];
+        acc += e1 * e1;
+      }
+      if (outside(lb, i1, 0.0, i2, 0.5)) {
+        const double r = e2_minus_b3(g, E2, B3a, B3b, i1, row);
+        acc += r * r;
+      }
     }
   }
   block_add(w * acc, out);
