@@ -71,10 +71,13 @@ void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStr
 long long push_blocks(long long n, int K);
 
 // ---- particle sort by cell ------------------------------------------------------
+// keys[i] = sort key of particle i's cell (dropped particles: 0xFFFFFFFF),
+// idx[i] = i; tiles = 0: the packed cell index, t > 0: 2^t x 4 x 4 tiles of
+// cells (2D: 2^t x 4), x1 fastest inside a tile
 template <typename Real>
 void launch_sort_keys(const Geo &g, const Particles<Real> &p, int tiles, unsigned *keys, unsigned *idx,
                       hipStream_t st);
-// whether the tiled sort keys fit in 32 bits on this grid
+// whether the tiled sort keys (any t <= 3) fit in 32 bits on this grid
 bool sort_tiles_fit(const Geo &g);
 template <typename Real>
 void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, const int *id_src, int *id_dst,
