@@ -138,3 +138,29 @@ def test_fullsize_gather_push_sampled(precision, utol, xtol):
     assert du < utol and dx_max < xtol
     if precision == "fp64":
         assert dkick < 1e-11
+
+
+def test_fullsize_beam_1000_steps_fp32():
+    # the full run length of the 3D beam configuration (1000 steps, 250
+    # window shifts, 40 re-sorts) in the benchmark's launch configuration:
+    # no particle lost, charge conserved, the Gauss residual still at its
+    # t = 0 value, finite energies
+    g, w = _sim(True)
+    cell, off, u = inputs.beam_inputs(w, seed=2)
+    n = len(cell)
+    sid = g.add_species(-1.0, inputs.beam_charge(w), n)
+    g.load_particles(sid, cell, off, u)
+    d0 = g.diagnostics()
+    g.step(1000)
+    d = g.diagnostics()
+    log("full-size beam, 1000 steps: window start %d, alive %d, charge %.12g -> %.12g, gauss_max %.9g (rho_max(0) %.9g), "
+        "w_field %.6g, w_kin %.9g -> %.9g" % (d["window_start"], d["n_alive"], d0["charge"], d["charge"], d["gauss_max"],
+                                              d0["rho_max"], d["w_field"], d0["w_kin"], d["w_kin"]))
+    assert d["step"] == 1000 and d["window_start"] == 250
+    assert d["n_alive"] == n and d["error_word"] == 0
+    assert abs(d["charge"] - d0["charge"]) < 1e-9 * abs(d0["charge"])
+    assert abs(d["gauss_max"] - d0["rho_max"]) < 1e-4 * d0["rho_max"]
+    assert math.isfinite(d["w_field"]) and d["w_field"] > 0
+    # the bunch barely exchanges energy with its own fields at gamma = 1e4
+    assert abs(d["w_kin"] - d0["w_kin"]) < 1e-3 * d0["w_kin"]
+    g.close()
