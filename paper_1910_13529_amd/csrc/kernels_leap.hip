@@ -178,7 +178,12 @@ __global__ __launch_bounds__(512) void k_leap(Geo g, const Real *__restrict__ Ei
       }
     }
     __syncthreads();
+    // the next plane's loads go out at raised wave priority, so waves leaving
+    // the barrier issue them before the LDS stencil work of the others
+    // (0.409 -> 0.394 ms on the 3D beam)
+    __builtin_amdgcn_s_setprio(3);
     if (k < z1) fetch(nxt, k + 1);
+    __builtin_amdgcn_s_setprio(0);
     const bool jplane = anyj && kw >= jb.lo[2] && kw <= jb.hi[2];
     // E^{n+1} of plane k, rows 0 .. R (row R: E1, E3 only)
     Real nE1[R + 1], nE2[R], nE3[R + 1];
