@@ -166,6 +166,9 @@ __global__ __launch_bounds__(512) void k_leap(Geo g, const Real *__restrict__ Ei
 
   for (int k = z0; k <= z1; ++k) {
     const int kw = wrap_near(k, g.n3);
+    // staging at raised priority too: the barrier is reached sooner
+    // (0.394 -> 0.381 ms); the stencil work below runs at priority 0
+    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int j = 0; j <= R; ++j) stage(sB2 + j * pitch, cur.b2[j]);
 #pragma unroll
