@@ -505,6 +505,9 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
   const long long chunk0 = chunk * kPushBlock * K;
   const int tid = threadIdx.x;
 
+  // wave priorities by phase: the box and staging passes (between
+  // barriers) 2, the particle loop 0, the flush 1
+  __builtin_amdgcn_s_setprio(2);
   // ---- chunk bounding box (window x1, x2, x3) of the particles' old cells
   if (tid == 0) {
     box[0] = box[2] = box[4] = INT_MAX;
@@ -639,6 +642,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
   __syncthreads();
   const bool lds_fields = sk.tile != nullptr;
 
+  __builtin_amdgcn_s_setprio(0);
   // ---- gather, push, move and deposit, K particles per thread; the next
   // particle's state is loaded while the current one is pushed
   int nx_cell = -1;
@@ -820,6 +824,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
     if (deposit_wave<Real, DIM, W>(active, m, q, sk)) deposit_direct<Real, DIM>(m, q, sk);
   }
 
+  __builtin_amdgcn_s_setprio(1);
   // ---- flush the tile to HBM: one atomic per non-zero point
   if (sk.tile) {
     __syncthreads();
