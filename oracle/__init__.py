@@ -13,6 +13,10 @@ Contents
   kspace.py              the paper's k-space integral for E1 around a
                          streaming particle (Eq. 13 with Plemelj k2 integrals,
                          App. D) and the self-force (Eqs. 19, 25)
+  steady.py              exact steady-state lattice fields of charges
+                         streaming along x1 on a periodic 2D grid (the
+                         Sec. 2.1 response in terms of the density, every
+                         wavenumber and aliased frequency on the lattice)
   dispersion.py          closed-form vacuum dispersion of the discrete
                          Maxwell operators (Eq. 4)
   field_loss.py          field loss around a moving bunch on the oracle's

@@ -187,6 +187,28 @@ class KSpace:
         return -tot / (2.0 * np.pi ** 2 * self.r)
 
 
+    def lattice_self_force(self, gather_order=2):
+        """F1 dx1 / q^2 as a PIC code measures it: the on-axis E1 line-out at
+        the E1 points (i1' + 1/2) around a particle on a node, interpolated to
+        the particle with the B-spline of order gather_order along x1 (the
+        gather's aliases included).  The transverse gather enters through
+        tpow (tpow = 2: quadratic deposit and quadratic gather in x2)."""
+        ip = np.arange(-3, 3)
+        w = bspline(ip + 0.5, gather_order)
+        keep = w != 0.0
+        return float(np.dot(w[keep], self.e1(ip[keep])))
+
+
+def bspline(d, order):
+    """Centred B-spline of order 1 (hat) or 2 (quadratic) at distances d (cells)."""
+    d = np.abs(np.asarray(d, dtype=np.float64))
+    if order == 1:
+        return np.where(d < 1.0, 1.0 - d, 0.0)
+    if order == 2:
+        return np.where(d <= 0.5, 0.75 - d * d, np.where(d < 1.5, 0.5 * (1.5 - d) ** 2, 0.0))
+    raise ValueError(order)
+
+
 # ---- regime thresholds (Sec. 2.2, 2.3, 3) ----------------------------------
 
 def r_crit():

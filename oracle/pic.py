@@ -19,10 +19,10 @@ _lib = None
 
 
 def build(force=False):
-    """Compile pic_oracle.c with gcc -O2 into liboracle_pic.so."""
+    """Compile pic_oracle.c with gcc -O2 (OpenMP on) into liboracle_pic.so."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -64,6 +64,9 @@ def lib():
         L.orc_deposit_one.argtypes = [P, D, dp, dp, D]
         L.orc_correct_j1.argtypes = [P]
         L.orc_set_injection.argtypes = [P, ip, D, D, D, ctypes.c_uint64]
+        L.orc_max_threads.restype = ctypes.c_int
+        L.orc_max_threads.argtypes = []
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -189,6 +192,16 @@ class OracleSim:
     @property
     def correction_halfwidth(self):
         return lib().orc_correction_halfwidth(self._h)
+
+
+def threads():
+    """Threads the oracle's parallel loops use."""
+    return int(lib().orc_max_threads())
+
+
+def set_threads(n):
+    """Use n threads in the parallel loops (results do not depend on n)."""
+    lib().orc_set_threads(int(n))
 
 
 def boris(qm, dt, EB, u):

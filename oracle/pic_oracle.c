@@ -37,11 +37,21 @@
  *   d+ f_i = (1/dx1) sum_{l=1..M} C_l (f_{i+l}   - f_{i-l+1})   acts on E -> B
  *   d- f_i = (1/dx1) sum_{l=1..M} C_l (f_{i+l-1} - f_{i-l})     acts on B -> E
  * M = 1, C_1 = 1 is the Yee operator.  x2 and x3 always use the Yee form.
+ *
+ * Threads (OpenMP, optional): only loops whose iterations write disjoint
+ * results run in parallel -- the field updates cell by cell, the J1
+ * correction line by line, and the gather + push particle by particle.  The
+ * current deposit (a sum over particles into shared nodes) and every
+ * reduction run serially in a fixed order, so the results do not depend on
+ * the number of threads.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_MAXM 64
 #define ORC_PI 3.14159265358979323846
@@ -439,11 +449,14 @@ static void deposit(orc_sim *s, double Q, const double *xo, const double *xn, do
 
 static void correct_j1(orc_sim *s) {
   long n1 = s->n[0];
-  double *line = (double *)malloc(sizeof(double) * n1);
-  double *out = (double *)malloc(sizeof(double) * n1);
-  for (long k = 0; k < s->n[2]; ++k)
-    for (long j = 0; j < s->n[1]; ++j) {
-      double *f = &s->F[J1][n1 * (j + s->n[1] * k)];
+  long nlines = s->n[1] * s->n[2];
+#pragma omp parallel
+  {
+    double *line = (double *)malloc(sizeof(double) * n1);
+    double *out = (double *)malloc(sizeof(double) * n1);
+#pragma omp for schedule(dynamic, 16)
+    for (long ln = 0; ln < nlines; ++ln) {
+      double *f = &s->F[J1][n1 * ln];
       int nz = 0;
       for (long i = 0; i < n1; ++i) {
         line[i] = f[i];
@@ -464,11 +477,13 @@ static void correct_j1(orc_sim *s) {
       }
       for (long i = 0; i < n1; ++i) f[i] = out[i];
     }
-  free(line);
-  free(out);
+    free(line);
+    free(out);
+  }
 }
 
 static void field_half_b(orc_sim *s, double h) {
+#pragma omp parallel for collapse(2) schedule(static)
   for (long k = 0; k < s->n[2]; ++k)
     for (long j = 0; j < s->n[1]; ++j)
       for (long i = 0; i < s->n[0]; ++i) {
@@ -481,6 +496,7 @@ static void field_half_b(orc_sim *s, double h) {
 
 static void field_e(orc_sim *s) {
   double dt = s->dt;
+#pragma omp parallel for collapse(2) schedule(static)
   for (long k = 0; k < s->n[2]; ++k)
     for (long j = 0; j < s->n[1]; ++j)
       for (long i = 0; i < s->n[0]; ++i) {
@@ -574,7 +590,12 @@ void orc_step(void *h, long nsteps) {
     memset(s->F[J1], 0, sizeof(double) * s->N);
     memset(s->F[J2], 0, sizeof(double) * s->N);
     memset(s->F[J3], 0, sizeof(double) * s->N);
-    for (long p = 0; p < s->np; ++p) {
+    long np = s->np;
+    double *xn = (double *)malloc(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
+    double *un = (double *)malloc(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
+    /* gather at x^n, Boris push, new position: independent per particle */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (long p = 0; p < np; ++p) {
       if (!s->alive[p]) continue;
       double xo[3] = {s->x[0][p], s->x[1][p], s->x[2][p]};
       double EB[6];
@@ -582,21 +603,32 @@ void orc_step(void *h, long nsteps) {
       double u[3] = {s->u[0][p], s->u[1][p], s->u[2][p]};
       boris(s->qm[p], s->dt, EB, u);
       double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-      double xn[3] = {xo[0], xo[1], xo[2]};
-      for (int d = 0; d < s->ndim; ++d) xn[d] = xo[d] + s->dt * u[d] / (g * s->dx[d]);
-      deposit(s, s->Q[p], xo, xn, u[2] / g);
+      for (int d = 0; d < 3; ++d) {
+        xn[3 * p + d] = (d < s->ndim) ? xo[d] + s->dt * u[d] / (g * s->dx[d]) : xo[d];
+        un[3 * p + d] = u[d];
+      }
+    }
+    /* current deposit in particle order (one shared J) */
+    for (long p = 0; p < np; ++p) {
+      if (!s->alive[p]) continue;
+      double xo[3] = {s->x[0][p], s->x[1][p], s->x[2][p]};
+      double *x1 = &xn[3 * p];
+      double g = sqrt(1.0 + un[3 * p] * un[3 * p] + un[3 * p + 1] * un[3 * p + 1] + un[3 * p + 2] * un[3 * p + 2]);
+      deposit(s, s->Q[p], xo, x1, un[3 * p + 2] / g);
       /* keep periodic coordinates in [-1/2, n - 1/2) */
       for (int d = 0; d < s->ndim; ++d) {
         if (d == 0 && s->window) continue;
         double nn = (double)s->n[d];
-        if (xn[d] >= nn - 0.5) xn[d] -= nn;
-        if (xn[d] < -0.5) xn[d] += nn;
+        if (x1[d] >= nn - 0.5) x1[d] -= nn;
+        if (x1[d] < -0.5) x1[d] += nn;
       }
       for (int d = 0; d < 3; ++d) {
-        s->x[d][p] = xn[d];
-        s->u[d][p] = u[d];
+        s->x[d][p] = x1[d];
+        s->u[d][p] = un[3 * p + d];
       }
     }
+    free(xn);
+    free(un);
     if (s->correct) correct_j1(s);
     field_half_b(s, 0.5 * s->dt);
     field_e(s);
@@ -604,6 +636,22 @@ void orc_step(void *h, long nsteps) {
     s->step++;
     window_update(s);
   }
+}
+
+/* number of threads the parallel loops use (1 without OpenMP) */
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 /* ---- accessors -------------------------------------------------------- */
