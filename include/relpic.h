@@ -47,7 +47,7 @@ typedef enum {
   RELPIC_EINVAL = 1,    /* malformed argument or descriptor */
   RELPIC_EUNSTABLE = 2, /* time step violates the operators' Courant limit */
   RELPIC_ERANGE = 3,    /* particle or index outside the grid / capacity */
-  RELPIC_ENOMEM = 4,    /* device allocation failed */
+  RELPIC_ENOMEM = 4,    /* device or host allocation failed */
   RELPIC_EDEVICE = 5,   /* HIP runtime error, or a kernel raised the error word */
   RELPIC_ESTATE = 6     /* call not valid in the object's current state */
 } relpic_status;
@@ -396,6 +396,33 @@ relpic_status relpic_kspace_e1(const relpic_kspace *q, const relpic_device *dev,
  * weighted by the gather's unaliased shape of order gather_order. */
 relpic_status relpic_kspace_self_force(const relpic_kspace *q, const relpic_device *dev, int gather_order,
                                        double *out);
+
+/* ---- Self-force and line-out against the k-space field (Sec. 2.2, Eq. 19) ---
+ *
+ * EB[6 k + c] (caller-owned, count x 6 doubles) = E1, E2, E3, B1, B2, B3 at
+ * particle slot first + k of a species (slots in relpic_read_particles
+ * order), interpolated at the particle's position with the push's quadratic
+ * B-spline, each component from its own staggered points, at the current
+ * step (E^n and B^n), in FP64.  The self-force on a particle of charge Q is
+ * Q (E + v x B); for a charge moving along x1 it is F1 = Q E1 (Eq. 19
+ * measures the same quantity in k space).  Dropped particles give zeros.
+ * Synchronizing.  RELPIC_ERANGE if the slots exceed the species. */
+relpic_status relpic_gather_particles(relpic_sim *sim, int species, int64_t first, int64_t count, double *EB);
+
+/* The simulated on-axis E1 around one particle next to the k-space
+ * prediction for the same points (Eq. 13, 2D runs only).  The particle (slot
+ * `slot` of `species`) must sit on an x1 node (|offset1| <= 1e-6, else
+ * RELPIC_ERANGE; a beta = 1 charge returns to a node every kappa steps when
+ * kappa is an integer).  For each k, sim_out[k] = E1 dx1 / Q at the E1
+ * point i1_rel[k] cells ahead of the particle's cell on its x2 row (E1 sits
+ * at i1 + 1/2), and theory_out[k] = relpic_kspace_e1 of q at the same
+ * point; the residual is their difference.  q must describe this run: its
+ * M, C, kappa (= dx1/dt) and r (= dx2/dx1) equal the simulation's (else
+ * RELPIC_EINVAL); beta, shape_order, tpow and nu_max are the caller's.
+ * Window runs: every point inside the window (else RELPIC_ERANGE).
+ * npts <= 4096.  Synchronizing. */
+relpic_status relpic_e1_residual(relpic_sim *sim, int species, int64_t slot, const relpic_kspace *q, int64_t npts,
+                                 const int32_t *i1_rel, double *sim_out, double *theory_out);
 
 const char *relpic_last_error(void);
 

@@ -327,104 +327,116 @@ extern "C" {
 relpic_status relpic_adj_create(const relpic_grid *grid, int M, const double *C0, relpic_precision prec,
                                 const relpic_device *dev, int64_t nsteps, int checkpoint_every,
                                 const relpic_loss_box *box, relpic_adj **out) {
-  if (!grid || !out || !box || !C0) return fail(RELPIC_EINVAL, "adj_create: null argument");
-  *out = nullptr;
-  if (grid->ndim != 2 || grid->bc1 != RELPIC_BC_PERIODIC)
-    return fail(RELPIC_EINVAL, "adj_create: the adjoint runs on a 2D periodic grid");
-  if (M < 1 || M > 8) return fail(RELPIC_EINVAL, "adj_create: M must be in 1..8");
-  if (nsteps < 1 || nsteps > (1 << 24) || checkpoint_every < 1 || checkpoint_every > 100000)
-    return fail(RELPIC_EINVAL, "adj_create: bad step count or checkpoint interval");
-  if (!(box->half1 > 0.0) || !(box->half2 > 0.0) || !std::isfinite(box->x1) || !std::isfinite(box->x2) ||
-      !std::isfinite(box->v1))
-    return fail(RELPIC_EINVAL, "adj_create: bad loss box");
-  relpic_solver sol{M, C0};
-  relpic_sim *s = nullptr;
-  if (relpic_status e = relpic_create(grid, &sol, prec, dev, &s)) return e;
-  relpic_adj *a = new (std::nothrow) relpic_adj();
-  if (!a) {
-    relpic_destroy(s);
-    return fail(RELPIC_ENOMEM, "adj_create: host allocation failed");
-  }
-  a->s = s;
-  a->nsteps = nsteps;
-  a->every = checkpoint_every;
-  a->box = *box;
-  a->M = M;
-  const size_t fb = s->esz * (size_t)s->N;
-  const long long nck = (nsteps + checkpoint_every - 1) / checkpoint_every;
-  const long long S = std::min<long long>(checkpoint_every, nsteps);
-  a->ckF = dev_alloc(s, fb * 6 * (size_t)nck);
-  a->segF = dev_alloc(s, fb * 6 * (size_t)(S + 2));
-  a->segJ = M > 1 ? dev_alloc(s, fb * (size_t)S) : nullptr;
-  a->segbox = (JBox *)dev_alloc(s, sizeof(JBox) * (size_t)S);
-  a->dacc = (double *)dev_alloc(s, sizeof(double) * (1 + kMaxM));
-  bool ok = a->ckF && a->segF && (M == 1 || a->segJ) && a->segbox && a->dacc;
-  for (int d = 0; d < 3 && ok; ++d) {
-    a->aE[d] = dev_alloc(s, fb);
-    a->aB[d] = dev_alloc(s, fb);
-    ok = a->aE[d] && a->aB[d];
-  }
-  if (!ok) {
-    relpic_destroy(s);
-    delete a;
-    return fail(RELPIC_ENOMEM, "adj_create: allocation failed");
-  }
-  *out = a;
-  return RELPIC_OK;
+  return guarded("adj_create", [&]() -> relpic_status {
+    if (!grid || !out || !box || !C0) return fail(RELPIC_EINVAL, "adj_create: null argument");
+    *out = nullptr;
+    if (grid->ndim != 2 || grid->bc1 != RELPIC_BC_PERIODIC)
+      return fail(RELPIC_EINVAL, "adj_create: the adjoint runs on a 2D periodic grid");
+    if (M < 1 || M > 8) return fail(RELPIC_EINVAL, "adj_create: M must be in 1..8");
+    if (nsteps < 1 || nsteps > (1 << 24) || checkpoint_every < 1 || checkpoint_every > 100000)
+      return fail(RELPIC_EINVAL, "adj_create: bad step count or checkpoint interval");
+    if (!(box->half1 > 0.0) || !(box->half2 > 0.0) || !std::isfinite(box->x1) || !std::isfinite(box->x2) ||
+        !std::isfinite(box->v1))
+      return fail(RELPIC_EINVAL, "adj_create: bad loss box");
+    relpic_solver sol{M, C0};
+    relpic_sim *s = nullptr;
+    if (relpic_status e = relpic_create(grid, &sol, prec, dev, &s)) return e;
+    relpic_adj *a = new (std::nothrow) relpic_adj();
+    if (!a) {
+      relpic_destroy(s);
+      return fail(RELPIC_ENOMEM, "adj_create: host allocation failed");
+    }
+    a->s = s;
+    a->nsteps = nsteps;
+    a->every = checkpoint_every;
+    a->box = *box;
+    a->M = M;
+    const size_t fb = s->esz * (size_t)s->N;
+    const long long nck = (nsteps + checkpoint_every - 1) / checkpoint_every;
+    const long long S = std::min<long long>(checkpoint_every, nsteps);
+    a->ckF = dev_alloc(s, fb * 6 * (size_t)nck);
+    a->segF = dev_alloc(s, fb * 6 * (size_t)(S + 2));
+    a->segJ = M > 1 ? dev_alloc(s, fb * (size_t)S) : nullptr;
+    a->segbox = (JBox *)dev_alloc(s, sizeof(JBox) * (size_t)S);
+    a->dacc = (double *)dev_alloc(s, sizeof(double) * (1 + kMaxM));
+    bool ok = a->ckF && a->segF && (M == 1 || a->segJ) && a->segbox && a->dacc;
+    for (int d = 0; d < 3 && ok; ++d) {
+      a->aE[d] = dev_alloc(s, fb);
+      a->aB[d] = dev_alloc(s, fb);
+      ok = a->aE[d] && a->aB[d];
+    }
+    if (!ok) {
+      relpic_destroy(s);
+      delete a;
+      return fail(RELPIC_ENOMEM, "adj_create: allocation failed");
+    }
+    *out = a;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_adj_destroy(relpic_adj *a) {
-  if (!a) return RELPIC_OK;
-  relpic_destroy(a->s);
-  delete a;
-  return RELPIC_OK;
+  return guarded("adj_destroy", [&]() -> relpic_status {
+    if (!a) return RELPIC_OK;
+    relpic_destroy(a->s);
+    delete a;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_adj_load_particles(relpic_adj *a, double Q, int64_t n, const int32_t *cell, const double *offset,
                                         const double *u) {
-  if (relpic_status e = check_adj(a)) return e;
-  if (a->nparts > 0 || !a->s->sp.empty()) return fail(RELPIC_ESTATE, "adj_load_particles: particles already loaded");
-  if (n < 1 || n >= (1LL << 31)) return fail(RELPIC_EINVAL, "adj_load_particles: bad count");
-  relpic_sim *s = a->s;
-  int sid = -1;
-  if (relpic_status e = relpic_add_species(s, 0.0, Q, n, &sid)) return e;
-  if (relpic_status e = relpic_load_particles(s, sid, n, cell, offset, u)) return e;
-  if (relpic_status e = relpic_sort_particles(s)) return e;
-  a->nparts = (int)s->sp[0].n;
-  const long long nck = (a->nsteps + a->every - 1) / a->every;
-  // initial state and per-checkpoint copies (each array sized for 8-byte elements)
-  const size_t pb = 8 * (size_t)a->nparts;
-  for (int k = 0; k < 6; ++k) {
-    a->p0[k] = dev_alloc(s, pb);
-    if (!a->p0[k]) return fail(RELPIC_ENOMEM, "adj_load_particles: allocation failed");
-  }
-  a->ckP = dev_alloc(s, pb * 6 * (size_t)nck);
-  if (!a->ckP) return fail(RELPIC_ENOMEM, "adj_load_particles: allocation failed");
-  if (relpic_status e = particles_copy(a, a->p0, 0)) return e;
-  HIP_OK(hipStreamSynchronize(s->st));
-  return RELPIC_OK;
+  return guarded("adj_load_particles", [&]() -> relpic_status {
+    if (relpic_status e = check_adj(a)) return e;
+    if (a->nparts > 0 || !a->s->sp.empty()) return fail(RELPIC_ESTATE, "adj_load_particles: particles already loaded");
+    if (n < 1 || n >= (1LL << 31)) return fail(RELPIC_EINVAL, "adj_load_particles: bad count");
+    relpic_sim *s = a->s;
+    int sid = -1;
+    if (relpic_status e = relpic_add_species(s, 0.0, Q, n, &sid)) return e;
+    if (relpic_status e = relpic_load_particles(s, sid, n, cell, offset, u)) return e;
+    if (relpic_status e = relpic_sort_particles(s)) return e;
+    a->nparts = (int)s->sp[0].n;
+    const long long nck = (a->nsteps + a->every - 1) / a->every;
+    // initial state and per-checkpoint copies (each array sized for 8-byte elements)
+    const size_t pb = 8 * (size_t)a->nparts;
+    for (int k = 0; k < 6; ++k) {
+      a->p0[k] = dev_alloc(s, pb);
+      if (!a->p0[k]) return fail(RELPIC_ENOMEM, "adj_load_particles: allocation failed");
+    }
+    a->ckP = dev_alloc(s, pb * 6 * (size_t)nck);
+    if (!a->ckP) return fail(RELPIC_ENOMEM, "adj_load_particles: allocation failed");
+    if (relpic_status e = particles_copy(a, a->p0, 0)) return e;
+    HIP_OK(hipStreamSynchronize(s->st));
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_adj_forward(relpic_adj *a, const double *C, double *loss) {
-  if (relpic_status e = check_adj(a)) return e;
-  if (!C || !loss) return fail(RELPIC_EINVAL, "adj_forward: null argument");
-  if (a->s->prec == RELPIC_FP32) return do_forward<float>(a, C, loss);
-  return do_forward<double>(a, C, loss);
+  return guarded("adj_forward", [&]() -> relpic_status {
+    if (relpic_status e = check_adj(a)) return e;
+    if (!C || !loss) return fail(RELPIC_EINVAL, "adj_forward: null argument");
+    if (a->s->prec == RELPIC_FP32) return do_forward<float>(a, C, loss);
+    return do_forward<double>(a, C, loss);
+  });
 }
 
 relpic_status relpic_adj_backward(relpic_adj *a, double *dLdC) {
-  if (relpic_status e = check_adj(a)) return e;
-  if (!dLdC) return fail(RELPIC_EINVAL, "adj_backward: null argument");
-  if (!a->forward_done) return fail(RELPIC_ESTATE, "adj_backward: no forward pass with these coefficients");
-  if (a->s->prec == RELPIC_FP32) return do_backward<float>(a, dLdC);
-  return do_backward<double>(a, dLdC);
+  return guarded("adj_backward", [&]() -> relpic_status {
+    if (relpic_status e = check_adj(a)) return e;
+    if (!dLdC) return fail(RELPIC_EINVAL, "adj_backward: null argument");
+    if (!a->forward_done) return fail(RELPIC_ESTATE, "adj_backward: no forward pass with these coefficients");
+    if (a->s->prec == RELPIC_FP32) return do_backward<float>(a, dLdC);
+    return do_backward<double>(a, dLdC);
+  });
 }
 
 relpic_status relpic_adj_sim(relpic_adj *a, relpic_sim **sim) {
-  if (relpic_status e = check_adj(a)) return e;
-  if (!sim) return fail(RELPIC_EINVAL, "adj_sim: null argument");
-  *sim = a->s;
-  return RELPIC_OK;
+  return guarded("adj_sim", [&]() -> relpic_status {
+    if (relpic_status e = check_adj(a)) return e;
+    if (!sim) return fail(RELPIC_EINVAL, "adj_sim: null argument");
+    *sim = a->s;
+    return RELPIC_OK;
+  });
 }
 
 }  // extern "C"

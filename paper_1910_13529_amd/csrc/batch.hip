@@ -580,105 +580,125 @@ extern "C" {
 
 relpic_status relpic_batch_create(int nruns, const relpic_grid *grids, const relpic_solver *solvers,
                                   relpic_precision prec, const relpic_device *dev, relpic_batch **out) {
-  if (!out || !grids || nruns < 1 || nruns > (1 << 20)) return fail(RELPIC_EINVAL, "batch_create: bad arguments");
-  *out = nullptr;
-  for (int r = 0; r < nruns; ++r)
-    if (grids[r].ndim != 2 || grids[r].bc1 != RELPIC_BC_PERIODIC)
-      return fail(RELPIC_EINVAL, "batch_create: every run must be 2D with a periodic x1 boundary");
-  relpic_batch *b = new (std::nothrow) relpic_batch();
-  if (!b) return fail(RELPIC_ENOMEM, "batch_create: host allocation failed");
-  b->prec = prec;
-  b->esz = prec == RELPIC_FP32 ? 4 : 8;
-  if (dev) b->dev = *dev;
-  b->st = (hipStream_t)b->dev.stream;
-  for (int r = 0; r < nruns; ++r) {
-    relpic_sim *s = nullptr;
-    const relpic_status e = relpic_create(&grids[r], solvers ? &solvers[r] : nullptr, prec, dev, &s);
-    if (e != RELPIC_OK) {
-      const std::string msg = std::string("batch_create: run ") + std::to_string(r) + ": " + relpic_last_error();
-      destroy_batch(b);
-      return fail(e, msg);
+  return guarded("batch_create", [&]() -> relpic_status {
+    if (!out || !grids || nruns < 1 || nruns > (1 << 20)) return fail(RELPIC_EINVAL, "batch_create: bad arguments");
+    *out = nullptr;
+    for (int r = 0; r < nruns; ++r)
+      if (grids[r].ndim != 2 || grids[r].bc1 != RELPIC_BC_PERIODIC)
+        return fail(RELPIC_EINVAL, "batch_create: every run must be 2D with a periodic x1 boundary");
+    relpic_batch *b = new (std::nothrow) relpic_batch();
+    if (!b) return fail(RELPIC_ENOMEM, "batch_create: host allocation failed");
+    b->prec = prec;
+    b->esz = prec == RELPIC_FP32 ? 4 : 8;
+    if (dev) b->dev = *dev;
+    b->st = (hipStream_t)b->dev.stream;
+    for (int r = 0; r < nruns; ++r) {
+      relpic_sim *s = nullptr;
+      const relpic_status e = relpic_create(&grids[r], solvers ? &solvers[r] : nullptr, prec, dev, &s);
+      if (e != RELPIC_OK) {
+        const std::string msg = std::string("batch_create: run ") + std::to_string(r) + ": " + relpic_last_error();
+        destroy_batch(b);
+        return fail(e, msg);
+      }
+      b->runs.push_back(s);
+      b->shape.push_back(kDefaultShape);
     }
-    b->runs.push_back(s);
-    b->shape.push_back(kDefaultShape);
-  }
-  *out = b;
-  return RELPIC_OK;
+    *out = b;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_batch_destroy(relpic_batch *b) {
-  if (b) destroy_batch(b);
-  return RELPIC_OK;
+  return guarded("batch_destroy", [&]() -> relpic_status {
+    if (b) destroy_batch(b);
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_batch_run(relpic_batch *b, int run, relpic_sim **sim) {
-  if (relpic_status e = check_batch(b)) return e;
-  if (!sim || run < 0 || run >= (int)b->runs.size()) return fail(RELPIC_EINVAL, "batch_run: bad run index");
-  *sim = b->runs[run];
-  return RELPIC_OK;
+  return guarded("batch_run", [&]() -> relpic_status {
+    if (relpic_status e = check_batch(b)) return e;
+    if (!sim || run < 0 || run >= (int)b->runs.size()) return fail(RELPIC_EINVAL, "batch_run: bad run index");
+    *sim = b->runs[run];
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_batch_step(relpic_batch *b, int64_t nsteps) {
-  if (relpic_status e = check_batch(b)) return e;
-  if (nsteps < 0) return fail(RELPIC_EINVAL, "batch_step: negative count");
-  if (b->prec == RELPIC_FP32) return do_batch_steps<float>(b, nsteps);
-  return do_batch_steps<double>(b, nsteps);
+  return guarded("batch_step", [&]() -> relpic_status {
+    if (relpic_status e = check_batch(b)) return e;
+    if (nsteps < 0) return fail(RELPIC_EINVAL, "batch_step: negative count");
+    if (b->prec == RELPIC_FP32) return do_batch_steps<float>(b, nsteps);
+    return do_batch_steps<double>(b, nsteps);
+  });
 }
 
 relpic_status relpic_batch_sync(relpic_batch *b) {
-  if (relpic_status e = check_batch(b)) return e;
-  HIP_OK(hipStreamSynchronize(b->st));
-  if (b->err) {
-    int err = 0;
-    HIP_OK(hipMemcpy(&err, b->err, sizeof(int), hipMemcpyDeviceToHost));
-    if (err) {
-      char buf[96];
-      std::snprintf(buf, sizeof buf, "batch kernel error word 0x%x (1: moved > 1 cell, 2: NaN momentum)", err);
-      return fail(RELPIC_EDEVICE, buf);
+  return guarded("batch_sync", [&]() -> relpic_status {
+    if (relpic_status e = check_batch(b)) return e;
+    HIP_OK(hipStreamSynchronize(b->st));
+    if (b->err) {
+      int err = 0;
+      HIP_OK(hipMemcpy(&err, b->err, sizeof(int), hipMemcpyDeviceToHost));
+      if (err) {
+        char buf[96];
+        std::snprintf(buf, sizeof buf, "batch kernel error word 0x%x (1: moved > 1 cell, 2: NaN momentum)", err);
+        return fail(RELPIC_EDEVICE, buf);
+      }
     }
-  }
-  return RELPIC_OK;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_batch_set_graph_steps(relpic_batch *b, int steps) {
-  if (relpic_status e = check_batch(b)) return e;
-  if (steps < 0 || (steps & 1) || steps > 100000)
-    return fail(RELPIC_EINVAL, "batch_set_graph_steps: steps must be even, 0 .. 100000");
-  b->graph_steps = steps;
-  drop_graphs(b);
-  return RELPIC_OK;
+  return guarded("batch_set_graph_steps", [&]() -> relpic_status {
+    if (relpic_status e = check_batch(b)) return e;
+    if (steps < 0 || (steps & 1) || steps > 100000)
+      return fail(RELPIC_EINVAL, "batch_set_graph_steps: steps must be even, 0 .. 100000");
+    b->graph_steps = steps;
+    drop_graphs(b);
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_batch_set_tiling(relpic_batch *b, const int *shape, int grid_workgroups) {
-  if (relpic_status e = check_batch(b)) return e;
-  if (grid_workgroups < 0 || (grid_workgroups % 8) != 0)
-    return fail(RELPIC_EINVAL, "batch_set_tiling: grid_workgroups must be a non-negative multiple of 8");
-  if (shape)
-    for (size_t r = 0; r < b->runs.size(); ++r)
-      if (shape[r] < 0 || shape[r] >= kNumShapes) return fail(RELPIC_EINVAL, "batch_set_tiling: bad shape");
-  if (shape) b->shape.assign(shape, shape + b->runs.size());
-  b->grid_wg = grid_workgroups;
-  if (!b->prepared) return RELPIC_OK;
-  return b->prec == RELPIC_FP32 ? build_tiles<float>(b) : build_tiles<double>(b);
+  return guarded("batch_set_tiling", [&]() -> relpic_status {
+    if (relpic_status e = check_batch(b)) return e;
+    if (grid_workgroups < 0 || (grid_workgroups % 8) != 0)
+      return fail(RELPIC_EINVAL, "batch_set_tiling: grid_workgroups must be a non-negative multiple of 8");
+    if (shape)
+      for (size_t r = 0; r < b->runs.size(); ++r)
+        if (shape[r] < 0 || shape[r] >= kNumShapes) return fail(RELPIC_EINVAL, "batch_set_tiling: bad shape");
+    if (shape) b->shape.assign(shape, shape + b->runs.size());
+    b->grid_wg = grid_workgroups;
+    if (!b->prepared) return RELPIC_OK;
+    return b->prec == RELPIC_FP32 ? build_tiles<float>(b) : build_tiles<double>(b);
+  });
 }
 
 relpic_status relpic_batch_get_tiling(relpic_batch *b, int *shape, int *grid_workgroups) {
-  if (relpic_status e = check_batch(b)) return e;
-  if (shape) std::copy(b->shape.begin(), b->shape.end(), shape);
-  if (grid_workgroups) *grid_workgroups = b->grid_wg;
-  return RELPIC_OK;
+  return guarded("batch_get_tiling", [&]() -> relpic_status {
+    if (relpic_status e = check_batch(b)) return e;
+    if (shape) std::copy(b->shape.begin(), b->shape.end(), shape);
+    if (grid_workgroups) *grid_workgroups = b->grid_wg;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_batch_autotune(relpic_batch *b, int reps, relpic_batch_tune *out) {
-  if (relpic_status e = check_batch(b)) return e;
-  if (reps < 1 || reps > 10000) return fail(RELPIC_EINVAL, "batch_autotune: reps must be in 1..10000");
-  return b->prec == RELPIC_FP32 ? do_autotune<float>(b, reps, out) : do_autotune<double>(b, reps, out);
+  return guarded("batch_autotune", [&]() -> relpic_status {
+    if (relpic_status e = check_batch(b)) return e;
+    if (reps < 1 || reps > 10000) return fail(RELPIC_EINVAL, "batch_autotune: reps must be in 1..10000");
+    return b->prec == RELPIC_FP32 ? do_autotune<float>(b, reps, out) : do_autotune<double>(b, reps, out);
+  });
 }
 
 relpic_status relpic_batch_read_field(relpic_batch *b, int run, relpic_field f, double *host, int64_t count) {
-  if (relpic_status e = check_batch(b)) return e;
-  if (run < 0 || run >= (int)b->runs.size()) return fail(RELPIC_EINVAL, "batch_read_field: bad run index");
-  return relpic_read_field(b->runs[run], f, host, count);
+  return guarded("batch_read_field", [&]() -> relpic_status {
+    if (relpic_status e = check_batch(b)) return e;
+    if (run < 0 || run >= (int)b->runs.size()) return fail(RELPIC_EINVAL, "batch_read_field: bad run index");
+    return relpic_read_field(b->runs[run], f, host, count);
+  });
 }
 
 }  // extern "C"

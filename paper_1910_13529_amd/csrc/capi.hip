@@ -21,15 +21,31 @@ using namespace relpic;
 namespace relpic_host {
 
 namespace {
-thread_local std::string g_last_error;
+// the last failure's message on this thread (fixed storage: setting it never allocates)
+thread_local char g_last_error[512] = "";
+
+void set_last_error(const char *a, const char *b) noexcept {
+  size_t k = 0;
+  for (const char *p = a; p && *p && k + 1 < sizeof g_last_error; ++p) g_last_error[k++] = *p;
+  if (b) {
+    for (const char *p = ": "; *p && k + 1 < sizeof g_last_error; ++p) g_last_error[k++] = *p;
+    for (const char *p = b; *p && k + 1 < sizeof g_last_error; ++p) g_last_error[k++] = *p;
+  }
+  g_last_error[k] = 0;
 }
+}  // namespace
 
 relpic_status fail(relpic_status s, const std::string &msg) {
-  g_last_error = msg;
+  set_last_error(msg.c_str(), nullptr);
   return s;
 }
 
-const char *last_error() { return g_last_error.c_str(); }
+relpic_status fail_noalloc(relpic_status s, const char *where, const char *what) noexcept {
+  set_last_error(where, what);
+  return s;
+}
+
+const char *last_error() { return g_last_error; }
 
 void *dev_alloc(relpic_sim *s, size_t bytes) {
   if (bytes == 0) bytes = 8;
@@ -372,6 +388,52 @@ relpic_status do_diag(relpic_sim *s, relpic_diag *out) {
   return RELPIC_OK;
 }
 
+// host staging buffers hold at most this many elements per array
+constexpr long long kStage = 1LL << 22;
+
+// Copy rows [r0, r0 + nr) of a field between its storage order (x1 columns
+// rotated by the ring buffer) and a dense FP64 window-relative host array,
+// through a bounded staging buffer.
+relpic_status copy_rows(relpic_sim *s, int f, double *host, bool to_host) {
+  const int n1 = s->n[0];
+  const long long rows = s->N / n1;
+  const long long per = std::max<long long>(1, kStage / n1);
+  const int wsm = make_geo(s).ws_mod;
+  std::vector<unsigned char> raw((size_t)std::min(rows, per) * n1 * s->esz);
+  for (long long r0 = 0; r0 < rows; r0 += per) {
+    const long long nr = std::min(per, rows - r0);
+    char *dev = (char *)s->F[f] + (size_t)r0 * n1 * s->esz;
+    if (to_host) {
+      HIP_OK(hipMemcpyAsync(raw.data(), dev, (size_t)nr * n1 * s->esz, hipMemcpyDeviceToHost, s->st));
+      HIP_OK(hipStreamSynchronize(s->st));
+    }
+    for (long long r = 0; r < nr; ++r)
+      for (int l = 0; l < n1; ++l) {
+        const long long sidx = r * n1 + (l + wsm) % n1;
+        double &h = host[(r0 + r) * n1 + l];
+        if (s->esz == 4) {
+          float x;
+          if (to_host) {
+            std::memcpy(&x, &raw[sidx * 4], 4);
+            h = x;
+          } else {
+            x = (float)h;
+            std::memcpy(&raw[sidx * 4], &x, 4);
+          }
+        } else if (to_host) {
+          std::memcpy(&h, &raw[sidx * 8], 8);
+        } else {
+          std::memcpy(&raw[sidx * 8], &h, 8);
+        }
+      }
+    if (!to_host) {
+      HIP_OK(hipMemcpyAsync(dev, raw.data(), (size_t)nr * n1 * s->esz, hipMemcpyHostToDevice, s->st));
+      HIP_OK(hipStreamSynchronize(s->st));
+    }
+  }
+  return RELPIC_OK;
+}
+
 relpic_status check_sim(relpic_sim *s) {
   if (!s) return fail(RELPIC_EINVAL, "null simulation handle");
   return RELPIC_OK;
@@ -385,509 +447,635 @@ const char *relpic_last_error(void) { return last_error(); }
 
 relpic_status relpic_fit_coefficients(double kappa, int M, int p, double wk1, double nsg, double *C_out,
                                       double *max_rel_err_out) {
-  if (!C_out || M < 1 || M > kMaxM) return fail(RELPIC_EINVAL, "fit: bad M or output pointer");
-  std::vector<double> C;
-  if (!fit_axial_coefficients(kappa, M, p, wk1, nsg, 2048, C)) return fail(RELPIC_EINVAL, "fit: singular or bad parameters");
-  std::copy(C.begin(), C.end(), C_out);
-  if (max_rel_err_out) {
-    double worst = 0.0;
-    for (int q = 1; q <= 2000; ++q) {
-      const double kh = 1.0 * q / 2000;
-      double v = 0.0;
-      for (int l = 1; l <= M; ++l) v += C[l - 1] * std::sin((2 * l - 1) * kh);
-      const double t = kappa * std::sin(kh / kappa);
-      worst = std::max(worst, std::fabs(v - t) / t);
+  return guarded("fit_coefficients", [&]() -> relpic_status {
+    if (!C_out || M < 1 || M > kMaxM) return fail(RELPIC_EINVAL, "fit: bad M or output pointer");
+    std::vector<double> C;
+    if (!fit_axial_coefficients(kappa, M, p, wk1, nsg, 2048, C)) return fail(RELPIC_EINVAL, "fit: singular or bad parameters");
+    std::copy(C.begin(), C.end(), C_out);
+    if (max_rel_err_out) {
+      double worst = 0.0;
+      for (int q = 1; q <= 2000; ++q) {
+        const double kh = 1.0 * q / 2000;
+        double v = 0.0;
+        for (int l = 1; l <= M; ++l) v += C[l - 1] * std::sin((2 * l - 1) * kh);
+        const double t = kappa * std::sin(kh / kappa);
+        worst = std::max(worst, std::fabs(v - t) / t);
+      }
+      *max_rel_err_out = worst;
     }
-    *max_rel_err_out = worst;
-  }
-  return RELPIC_OK;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver, relpic_precision prec,
                             const relpic_device *dev, relpic_sim **out) {
-  if (!grid || !out) return fail(RELPIC_EINVAL, "create: null descriptor");
-  *out = nullptr;
-  if (grid->ndim != 2 && grid->ndim != 3) return fail(RELPIC_EINVAL, "create: ndim must be 2 or 3");
-  if (prec != RELPIC_FP32 && prec != RELPIC_FP64) return fail(RELPIC_EINVAL, "create: bad precision");
-  if (grid->bc1 != RELPIC_BC_PERIODIC && grid->bc1 != RELPIC_BC_WINDOW) return fail(RELPIC_EINVAL, "create: bad bc1");
-  if (!(grid->dt > 0.0)) return fail(RELPIC_EINVAL, "create: dt must be positive");
-  long long N = 1;
-  for (int d = 0; d < grid->ndim; ++d) {
-    if (grid->n[d] < 1 || grid->n[d] > (1 << 24) || !(grid->dx[d] > 0.0))
-      return fail(RELPIC_EINVAL, "create: bad n or dx");
-    N *= grid->n[d];
-  }
-  // kernels address field arrays with 32-bit byte offsets
-  if (N * (prec == RELPIC_FP64 ? 8LL : 4LL) >= (1LL << 32))
-    return fail(RELPIC_EINVAL, "create: field arrays above 4 GiB each (2^30 cells FP32, 2^29 FP64)");
-  if (grid->n[0] < 8 || grid->n[1] < 2 || (grid->ndim == 3 && grid->n[2] < 2))
-    return fail(RELPIC_EINVAL, "create: grid too small (n1 >= 8, n2, n3 >= 2)");
-  if (grid->n[1] > 65535 || (grid->ndim == 3 && grid->n[2] > 65535))
-    return fail(RELPIC_EINVAL, "create: n2 and n3 are limited to 65535 (launch grid rows)");
-  int M = 1;
-  double C[kMaxM] = {1.0};
-  if (solver && solver->M > 1) {
-    if (solver->M > kMaxM || !solver->C) return fail(RELPIC_EINVAL, "create: bad solver coefficients");
-    M = solver->M;
-    for (int l = 0; l < M; ++l) C[l] = solver->C[l];
-    if (2 * M > grid->n[0]) return fail(RELPIC_EINVAL, "create: stencil wider than the grid");
-  } else if (solver && solver->M == 1 && solver->C) {
-    C[0] = solver->C[0];
-  }
-  if (grid->bc1 == RELPIC_BC_WINDOW) {
-    if (!(grid->window_speed > 0.0) || grid->window_speed * grid->dt >= grid->dx[0])
-      return fail(RELPIC_EINVAL, "create: window must advance less than one cell per step");
-  }
-  const double cn = courant_number(grid->ndim, grid->dx, grid->dt, C, M);
-  if (!(cn < 1.0)) {
-    char buf[128];
-    std::snprintf(buf, sizeof buf, "create: Courant number %.6f >= 1", cn);
-    return fail(RELPIC_EUNSTABLE, buf);
-  }
-  // every particle moves less than one cell per step only if dt < dx_d
-  for (int d = 0; d < grid->ndim; ++d)
-    if (!(grid->dt < grid->dx[d])) return fail(RELPIC_EUNSTABLE, "create: dt must be below every dx");
+  return guarded("create", [&]() -> relpic_status {
+    if (!grid || !out) return fail(RELPIC_EINVAL, "create: null descriptor");
+    *out = nullptr;
+    if (grid->ndim != 2 && grid->ndim != 3) return fail(RELPIC_EINVAL, "create: ndim must be 2 or 3");
+    if (prec != RELPIC_FP32 && prec != RELPIC_FP64) return fail(RELPIC_EINVAL, "create: bad precision");
+    if (grid->bc1 != RELPIC_BC_PERIODIC && grid->bc1 != RELPIC_BC_WINDOW) return fail(RELPIC_EINVAL, "create: bad bc1");
+    if (!(grid->dt > 0.0)) return fail(RELPIC_EINVAL, "create: dt must be positive");
+    long long N = 1;
+    for (int d = 0; d < grid->ndim; ++d) {
+      if (grid->n[d] < 1 || grid->n[d] > (1 << 24) || !(grid->dx[d] > 0.0))
+        return fail(RELPIC_EINVAL, "create: bad n or dx");
+      N *= grid->n[d];
+    }
+    // kernels address field arrays with 32-bit byte offsets
+    if (N * (prec == RELPIC_FP64 ? 8LL : 4LL) >= (1LL << 32))
+      return fail(RELPIC_EINVAL, "create: field arrays above 4 GiB each (2^30 cells FP32, 2^29 FP64)");
+    if (grid->n[0] < 8 || grid->n[1] < 2 || (grid->ndim == 3 && grid->n[2] < 2))
+      return fail(RELPIC_EINVAL, "create: grid too small (n1 >= 8, n2, n3 >= 2)");
+    if (grid->n[1] > 65535 || (grid->ndim == 3 && grid->n[2] > 65535))
+      return fail(RELPIC_EINVAL, "create: n2 and n3 are limited to 65535 (launch grid rows)");
+    int M = 1;
+    double C[kMaxM] = {1.0};
+    if (solver && solver->M > 1) {
+      if (solver->M > kMaxM || !solver->C) return fail(RELPIC_EINVAL, "create: bad solver coefficients");
+      M = solver->M;
+      for (int l = 0; l < M; ++l) C[l] = solver->C[l];
+      if (2 * M > grid->n[0]) return fail(RELPIC_EINVAL, "create: stencil wider than the grid");
+    } else if (solver && solver->M == 1 && solver->C) {
+      C[0] = solver->C[0];
+    }
+    if (grid->bc1 == RELPIC_BC_WINDOW) {
+      if (!(grid->window_speed > 0.0) || grid->window_speed * grid->dt >= grid->dx[0])
+        return fail(RELPIC_EINVAL, "create: window must advance less than one cell per step");
+    }
+    const double cn = courant_number(grid->ndim, grid->dx, grid->dt, C, M);
+    if (!(cn < 1.0)) {
+      char buf[128];
+      std::snprintf(buf, sizeof buf, "create: Courant number %.6f >= 1", cn);
+      return fail(RELPIC_EUNSTABLE, buf);
+    }
+    // every particle moves less than one cell per step only if dt < dx_d
+    for (int d = 0; d < grid->ndim; ++d)
+      if (!(grid->dt < grid->dx[d])) return fail(RELPIC_EUNSTABLE, "create: dt must be below every dx");
 
-  relpic_sim *s = new (std::nothrow) relpic_sim();
-  if (!s) return fail(RELPIC_ENOMEM, "create: host allocation failed");
-  s->grid = *grid;
-  s->ndim = grid->ndim;
-  for (int d = 0; d < 3; ++d) {
-    s->n[d] = d < grid->ndim ? (int)grid->n[d] : 1;
-    s->dx[d] = d < grid->ndim ? grid->dx[d] : 1.0;
-  }
-  s->N = N;
-  s->prec = prec;
-  s->esz = prec == RELPIC_FP32 ? 4 : 8;
-  s->M = M;
-  for (int l = 0; l < M; ++l) s->C[l] = C[l];
-  if (dev) s->dev = *dev;
-  s->st = (hipStream_t)s->dev.stream;
-  if (hipSetDevice(s->dev.device) != hipSuccess) {
-    delete s;
-    return fail(RELPIC_EDEVICE, "create: hipSetDevice failed");
-  }
-  std::vector<double> taps;
-  if (M > 1) {
-    const double tol = prec == RELPIC_FP64 ? 1e-16 : 1e-9;
-    if (!correction_taps(C, M, tol, kMaxTaps, taps)) {
-      delete s;
-      return fail(RELPIC_EINVAL, "create: J1 correction does not converge within the tap limit");
+    relpic_sim *s = new (std::nothrow) relpic_sim();
+    if (!s) return fail(RELPIC_ENOMEM, "create: host allocation failed");
+    s->grid = *grid;
+    s->ndim = grid->ndim;
+    for (int d = 0; d < 3; ++d) {
+      s->n[d] = d < grid->ndim ? (int)grid->n[d] : 1;
+      s->dx[d] = d < grid->ndim ? grid->dx[d] : 1.0;
     }
-    s->ng = (int)taps.size() - 1;
-  }
-  for (int k = 0; k < 10; ++k) {
-    if (k == 9 && M == 1) continue;
-    s->F[k] = dev_alloc(s, s->esz * N);
-    if (!s->F[k]) {
-      dev_free_all(s);
+    s->N = N;
+    s->prec = prec;
+    s->esz = prec == RELPIC_FP32 ? 4 : 8;
+    s->M = M;
+    for (int l = 0; l < M; ++l) s->C[l] = C[l];
+    if (dev) s->dev = *dev;
+    s->st = (hipStream_t)s->dev.stream;
+    if (hipSetDevice(s->dev.device) != hipSuccess) {
       delete s;
-      return fail(RELPIC_ENOMEM, "create: field allocation failed");
+      return fail(RELPIC_EDEVICE, "create: hipSetDevice failed");
     }
-  }
-  for (int d = 0; d < 3; ++d) {
-    s->Bx[d] = dev_alloc(s, s->esz * N);
-    if (!s->Bx[d]) {
-      dev_free_all(s);
-      delete s;
-      return fail(RELPIC_ENOMEM, "create: field allocation failed");
+    std::vector<double> taps;
+    if (M > 1) {
+      const double tol = prec == RELPIC_FP64 ? 1e-16 : 1e-9;
+      if (!correction_taps(C, M, tol, kMaxTaps, taps)) {
+        delete s;
+        return fail(RELPIC_EINVAL, "create: J1 correction does not converge within the tap limit");
+      }
+      s->ng = (int)taps.size() - 1;
     }
-  }
-  // second E buffer for the fused update, where the grid qualifies (the
-  // separate updates remain if it cannot be allocated)
-  if (grid->ndim == 3 && (prec == RELPIC_FP32 ? leap_supported<float>(make_geo(s), M)
-                                              : leap_supported<double>(make_geo(s), M))) {
-    bool ok = true;
-    for (int d = 0; d < 3 && ok; ++d) ok = (s->Ex[d] = dev_alloc(s, s->esz * N)) != nullptr;
-    s->fuse = ok;
-    if (!ok)
-      for (int d = 0; d < 3; ++d) s->Ex[d] = nullptr;
-  }
-  s->jbox = (JBox *)dev_alloc(s, 2 * sizeof(JBox));
-  s->err = (int *)dev_alloc(s, 64);
-  s->dbuf = (double *)dev_alloc(s, 8 * sizeof(double));
-  s->rho = (double *)dev_alloc(s, sizeof(double) * N);
-  s->taps = dev_alloc(s, s->esz * (kMaxTaps + 1));
-  if (!s->err || !s->dbuf || !s->rho || !s->taps || !s->jbox) {
-    dev_free_all(s);
-    delete s;
-    return fail(RELPIC_ENOMEM, "create: allocation failed");
-  }
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < 10 && e == hipSuccess; ++k)
-    if (s->F[k]) e = hipMemsetAsync(s->F[k], 0, s->esz * N, s->st);
-  for (int d = 0; d < 3 && e == hipSuccess; ++d) e = hipMemsetAsync(s->Bx[d], 0, s->esz * N, s->st);
-  for (int d = 0; d < 3 && e == hipSuccess; ++d)
-    if (s->Ex[d]) e = hipMemsetAsync(s->Ex[d], 0, s->esz * N, s->st);
-  if (e == hipSuccess) e = hipMemsetAsync(s->err, 0, 64, s->st);
-  if (e == hipSuccess) {
-    launch_reset_box(s->jbox, s->st);
-    launch_reset_box(s->jbox + 1, s->st);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess && M > 1) {
-    std::vector<unsigned char> host(s->esz * taps.size());
-    for (size_t i = 0; i < taps.size(); ++i) {
-      if (prec == RELPIC_FP32) {
-        float v = (float)taps[i];
-        std::memcpy(&host[i * 4], &v, 4);
-      } else {
-        std::memcpy(&host[i * 8], &taps[i], 8);
+    for (int k = 0; k < 10; ++k) {
+      if (k == 9 && M == 1) continue;
+      s->F[k] = dev_alloc(s, s->esz * N);
+      if (!s->F[k]) {
+        dev_free_all(s);
+        delete s;
+        return fail(RELPIC_ENOMEM, "create: field allocation failed");
       }
     }
-    e = hipMemcpyAsync(s->taps, host.data(), host.size(), hipMemcpyHostToDevice, s->st);
+    for (int d = 0; d < 3; ++d) {
+      s->Bx[d] = dev_alloc(s, s->esz * N);
+      if (!s->Bx[d]) {
+        dev_free_all(s);
+        delete s;
+        return fail(RELPIC_ENOMEM, "create: field allocation failed");
+      }
+    }
+    // second E buffer for the fused update, where the grid qualifies (the
+    // separate updates remain if it cannot be allocated)
+    if (grid->ndim == 3 && (prec == RELPIC_FP32 ? leap_supported<float>(make_geo(s), M)
+                                                : leap_supported<double>(make_geo(s), M))) {
+      bool ok = true;
+      for (int d = 0; d < 3 && ok; ++d) ok = (s->Ex[d] = dev_alloc(s, s->esz * N)) != nullptr;
+      s->fuse = ok;
+      if (!ok)
+        for (int d = 0; d < 3; ++d) s->Ex[d] = nullptr;
+    }
+    s->jbox = (JBox *)dev_alloc(s, 2 * sizeof(JBox));
+    s->err = (int *)dev_alloc(s, 64);
+    s->dbuf = (double *)dev_alloc(s, 8 * sizeof(double));
+    s->rho = (double *)dev_alloc(s, sizeof(double) * N);
+    s->taps = dev_alloc(s, s->esz * (kMaxTaps + 1));
+    if (!s->err || !s->dbuf || !s->rho || !s->taps || !s->jbox) {
+      dev_free_all(s);
+      delete s;
+      return fail(RELPIC_ENOMEM, "create: allocation failed");
+    }
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 10 && e == hipSuccess; ++k)
+      if (s->F[k]) e = hipMemsetAsync(s->F[k], 0, s->esz * N, s->st);
+    for (int d = 0; d < 3 && e == hipSuccess; ++d) e = hipMemsetAsync(s->Bx[d], 0, s->esz * N, s->st);
+    for (int d = 0; d < 3 && e == hipSuccess; ++d)
+      if (s->Ex[d]) e = hipMemsetAsync(s->Ex[d], 0, s->esz * N, s->st);
+    if (e == hipSuccess) e = hipMemsetAsync(s->err, 0, 64, s->st);
+    if (e == hipSuccess) {
+      launch_reset_box(s->jbox, s->st);
+      launch_reset_box(s->jbox + 1, s->st);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess && M > 1) {
+      std::vector<unsigned char> host(s->esz * taps.size());
+      for (size_t i = 0; i < taps.size(); ++i) {
+        if (prec == RELPIC_FP32) {
+          float v = (float)taps[i];
+          std::memcpy(&host[i * 4], &v, 4);
+        } else {
+          std::memcpy(&host[i * 8], &taps[i], 8);
+        }
+      }
+      e = hipMemcpyAsync(s->taps, host.data(), host.size(), hipMemcpyHostToDevice, s->st);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-  if (e != hipSuccess) {
-    dev_free_all(s);
-    delete s;
-    return fail(RELPIC_EDEVICE, std::string("create: ") + hipGetErrorString(e));
-  }
-  *out = s;
-  return RELPIC_OK;
+    if (e != hipSuccess) {
+      dev_free_all(s);
+      delete s;
+      return fail(RELPIC_EDEVICE, std::string("create: ") + hipGetErrorString(e));
+    }
+    *out = s;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_destroy(relpic_sim *sim) {
-  if (!sim) return RELPIC_OK;
-  (void)hipStreamSynchronize(sim->st);
-  for (hipEvent_t e : sim->ev_pool) (void)hipEventDestroy(e);
-  dev_free_all(sim);
-  delete sim;
-  return RELPIC_OK;
+  return guarded("destroy", [&]() -> relpic_status {
+    if (!sim) return RELPIC_OK;
+    (void)hipStreamSynchronize(sim->st);
+    for (hipEvent_t e : sim->ev_pool) (void)hipEventDestroy(e);
+    dev_free_all(sim);
+    delete sim;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_add_species(relpic_sim *s, double q_over_m, double Q, int64_t capacity, int *species_id) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (!std::isfinite(q_over_m) || !std::isfinite(Q) || capacity < 0 || capacity > (1LL << 31))
-    return fail(RELPIC_EINVAL, "add_species: bad q/m, charge or capacity");
-  Species sp;
-  sp.qm = q_over_m;
-  sp.Q = Q;
-  sp.cap = capacity;
-  const size_t cap = (size_t)std::max<int64_t>(capacity, 1);
-  sp.cell = (int *)dev_alloc(s, sizeof(int) * cap);
-  sp.cell2 = (int *)dev_alloc(s, sizeof(int) * cap);
-  sp.id = (int *)dev_alloc(s, sizeof(int) * cap);
-  sp.id2 = (int *)dev_alloc(s, sizeof(int) * cap);
-  sp.keys = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
-  sp.keys2 = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
-  sp.idx = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
-  sp.idx2 = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
-  bool ok = sp.cell && sp.cell2 && sp.id && sp.id2 && sp.keys && sp.keys2 && sp.idx && sp.idx2;
-  for (int d = 0; d < 3 && ok; ++d) {
-    sp.o[d] = (d < s->ndim) ? dev_alloc(s, s->esz * cap) : nullptr;
-    sp.o2[d] = (d < s->ndim) ? dev_alloc(s, s->esz * cap) : nullptr;
-    sp.u[d] = dev_alloc(s, s->esz * cap);
-    sp.u2[d] = dev_alloc(s, s->esz * cap);
-    ok = (d >= s->ndim || (sp.o[d] && sp.o2[d])) && sp.u[d] && sp.u2[d];
-  }
-  if (!ok) return fail(RELPIC_ENOMEM, "add_species: allocation failed");
-  s->sp.push_back(sp);
-  if (species_id) *species_id = (int)s->sp.size() - 1;
-  return RELPIC_OK;
+  return guarded("add_species", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (!std::isfinite(q_over_m) || !std::isfinite(Q) || capacity < 0 || capacity > (1LL << 31))
+      return fail(RELPIC_EINVAL, "add_species: bad q/m, charge or capacity");
+    Species sp;
+    sp.qm = q_over_m;
+    sp.Q = Q;
+    sp.cap = capacity;
+    const size_t cap = (size_t)std::max<int64_t>(capacity, 1);
+    sp.cell = (int *)dev_alloc(s, sizeof(int) * cap);
+    sp.cell2 = (int *)dev_alloc(s, sizeof(int) * cap);
+    sp.id = (int *)dev_alloc(s, sizeof(int) * cap);
+    sp.id2 = (int *)dev_alloc(s, sizeof(int) * cap);
+    sp.keys = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
+    sp.keys2 = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
+    sp.idx = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
+    sp.idx2 = (unsigned *)dev_alloc(s, sizeof(unsigned) * cap);
+    bool ok = sp.cell && sp.cell2 && sp.id && sp.id2 && sp.keys && sp.keys2 && sp.idx && sp.idx2;
+    for (int d = 0; d < 3 && ok; ++d) {
+      sp.o[d] = (d < s->ndim) ? dev_alloc(s, s->esz * cap) : nullptr;
+      sp.o2[d] = (d < s->ndim) ? dev_alloc(s, s->esz * cap) : nullptr;
+      sp.u[d] = dev_alloc(s, s->esz * cap);
+      sp.u2[d] = dev_alloc(s, s->esz * cap);
+      ok = (d >= s->ndim || (sp.o[d] && sp.o2[d])) && sp.u[d] && sp.u2[d];
+    }
+    if (!ok) return fail(RELPIC_ENOMEM, "add_species: allocation failed");
+    s->sp.push_back(sp);
+    if (species_id) *species_id = (int)s->sp.size() - 1;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_load_particles(relpic_sim *s, int species, int64_t n, const int32_t *cell, const double *offset,
                                     const double *u) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "load: bad species");
-  if (n < 0 || (n > 0 && (!cell || !offset || !u))) return fail(RELPIC_EINVAL, "load: bad arrays");
-  Species &sp = s->sp[species];
-  if (sp.n + n > sp.cap) return fail(RELPIC_ERANGE, "load: capacity exceeded");
-  if (n == 0) return RELPIC_OK;
-  const Geo g = make_geo(s);
-  const int nd = s->ndim;
-  std::vector<int> packed(n);
-  std::vector<double> o64[3], u64[3];
-  for (int d = 0; d < 3; ++d) {
-    o64[d].resize(d < nd ? n : 0);
-    u64[d].resize(n);
-  }
-  for (int64_t i = 0; i < n; ++i) {
-    long long l1 = cell[i * nd + 0];
-    if (g.window) {
-      l1 -= s->ws;
-      if (l1 < 2 || l1 > s->n[0] - 3) return fail(RELPIC_ERANGE, "load: particle outside the window interior");
-    } else if (l1 < 0 || l1 >= s->n[0]) {
-      return fail(RELPIC_ERANGE, "load: x1 cell outside the grid");
+  return guarded("load_particles", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "load: bad species");
+    if (n < 0 || (n > 0 && (!cell || !offset || !u))) return fail(RELPIC_EINVAL, "load: bad arrays");
+    Species &sp = s->sp[species];
+    if (sp.n + n > sp.cap) return fail(RELPIC_ERANGE, "load: capacity exceeded");
+    if (n == 0) return RELPIC_OK;
+    const Geo g = make_geo(s);
+    const int nd = s->ndim;
+    // validate everything before the first byte is copied: a rejected load leaves the species unchanged
+    for (int64_t i = 0; i < n; ++i) {
+      long long l1 = cell[i * nd + 0];
+      if (g.window) {
+        l1 -= s->ws;
+        if (l1 < 2 || l1 > s->n[0] - 3) return fail(RELPIC_ERANGE, "load: particle outside the window interior");
+      } else if (l1 < 0 || l1 >= s->n[0]) {
+        return fail(RELPIC_ERANGE, "load: x1 cell outside the grid");
+      }
+      const int c2 = cell[i * nd + 1];
+      const int c3 = nd == 3 ? cell[i * nd + 2] : 0;
+      if (c2 < 0 || c2 >= s->n[1] || c3 < 0 || c3 >= s->n[2]) return fail(RELPIC_ERANGE, "load: cell outside the grid");
+      for (int d = 0; d < nd; ++d) {
+        const double o = offset[i * nd + d];
+        if (!(o >= -0.5 && o < 0.5)) return fail(RELPIC_EINVAL, "load: offset outside [-1/2, 1/2)");
+      }
+      for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(u[i * 3 + d])) return fail(RELPIC_EINVAL, "load: non-finite momentum");
     }
-    const int c2 = cell[i * nd + 1];
-    const int c3 = nd == 3 ? cell[i * nd + 2] : 0;
-    if (c2 < 0 || c2 >= s->n[1] || c3 < 0 || c3 >= s->n[2]) return fail(RELPIC_ERANGE, "load: cell outside the grid");
-    for (int d = 0; d < nd; ++d) {
-      const double o = offset[i * nd + d];
-      if (!(o >= -0.5 && o < 0.5)) return fail(RELPIC_EINVAL, "load: offset outside [-1/2, 1/2)");
-      o64[d][i] = o;
-    }
-    for (int d = 0; d < 3; ++d) {
-      if (!std::isfinite(u[i * 3 + d])) return fail(RELPIC_EINVAL, "load: non-finite momentum");
-      u64[d][i] = u[i * 3 + d];
-    }
-    const int col = (int)((l1 + g.ws_mod) % s->n[0]);
-    packed[i] = col + s->n[0] * (c2 + s->n[1] * c3);
-  }
-  HIP_OK(hipMemcpyAsync(sp.cell + sp.n, packed.data(), sizeof(int) * n, hipMemcpyHostToDevice, s->st));
-  std::vector<int> ids(n);
-  for (int64_t i = 0; i < n; ++i) ids[i] = (int)(sp.next_id + i);
-  HIP_OK(hipMemcpyAsync(sp.id + sp.n, ids.data(), sizeof(int) * n, hipMemcpyHostToDevice, s->st));
-  HIP_OK(hipStreamSynchronize(s->st));
-  std::vector<float> tmp(s->prec == RELPIC_FP32 ? n : 0);
-  auto put = [&](void *dst, const std::vector<double> &src) -> relpic_status {
-    char *d = (char *)dst + s->esz * sp.n;
-    if (s->prec == RELPIC_FP32) {
-      for (int64_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
-      HIP_OK(hipMemcpyAsync(d, tmp.data(), 4 * n, hipMemcpyHostToDevice, s->st));
+    // staged through bounded host buffers (kStage particles at a time)
+    const int64_t chunk = std::min<int64_t>(n, kStage);
+    std::vector<int> packed(chunk), ids(chunk);
+    std::vector<unsigned char> col((size_t)chunk * s->esz);
+    auto put = [&](void *dst_base, int64_t first, int64_t m, const double *src, int stride, int k) -> relpic_status {
+      for (int64_t i = 0; i < m; ++i) {
+        const double v = src[(first + i) * stride + k];
+        if (s->prec == RELPIC_FP32) {
+          const float x = (float)v;
+          std::memcpy(&col[i * 4], &x, 4);
+        } else {
+          std::memcpy(&col[i * 8], &v, 8);
+        }
+      }
+      HIP_OK(hipMemcpyAsync((char *)dst_base + s->esz * (sp.n + first), col.data(), s->esz * m, hipMemcpyHostToDevice,
+                            s->st));
       HIP_OK(hipStreamSynchronize(s->st));
-    } else {
-      HIP_OK(hipMemcpyAsync(d, src.data(), 8 * n, hipMemcpyHostToDevice, s->st));
+      return RELPIC_OK;
+    };
+    for (int64_t first = 0; first < n; first += chunk) {
+      const int64_t m = std::min<int64_t>(chunk, n - first);
+      for (int64_t i = 0; i < m; ++i) {
+        const int64_t q = first + i;
+        long long l1 = cell[q * nd + 0];
+        if (g.window) l1 -= s->ws;
+        const int c2 = cell[q * nd + 1];
+        const int c3 = nd == 3 ? cell[q * nd + 2] : 0;
+        const int cc = (int)((l1 + g.ws_mod) % s->n[0]);
+        packed[i] = cc + s->n[0] * (c2 + s->n[1] * c3);
+        ids[i] = (int)(sp.next_id + q);
+      }
+      HIP_OK(hipMemcpyAsync(sp.cell + sp.n + first, packed.data(), sizeof(int) * m, hipMemcpyHostToDevice, s->st));
+      HIP_OK(hipMemcpyAsync(sp.id + sp.n + first, ids.data(), sizeof(int) * m, hipMemcpyHostToDevice, s->st));
       HIP_OK(hipStreamSynchronize(s->st));
+      for (int d = 0; d < nd; ++d)
+        if (relpic_status r = put(sp.o[d], first, m, offset, nd, d)) return r;
+      for (int d = 0; d < 3; ++d)
+        if (relpic_status r = put(sp.u[d], first, m, u, 3, d)) return r;
     }
+    sp.n += n;
+    sp.next_id += n;
+    sp.dirty = true;
     return RELPIC_OK;
-  };
-  for (int d = 0; d < nd; ++d)
-    if (relpic_status r = put(sp.o[d], o64[d])) return r;
-  for (int d = 0; d < 3; ++d)
-    if (relpic_status r = put(sp.u[d], u64[d])) return r;
-  sp.n += n;
-  sp.next_id += n;
-  sp.dirty = true;
-  return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_set_injection(relpic_sim *s, int species, const int *ppc, double uth, uint64_t seed) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (species < 0 || species >= (int)s->sp.size() || !ppc) return fail(RELPIC_EINVAL, "injection: bad species");
-  if (s->grid.bc1 != RELPIC_BC_WINDOW) return fail(RELPIC_ESTATE, "injection needs the moving window");
-  Species &sp = s->sp[species];
-  for (int d = 0; d < 3; ++d) {
-    sp.ppc[d] = d < s->ndim ? ppc[d] : 1;
-    if (sp.ppc[d] < 1 || sp.ppc[d] > 16) return fail(RELPIC_EINVAL, "injection: ppc must be in 1..16");
-  }
-  sp.inject = true;
-  sp.uth = uth;
-  sp.seed = seed;
-  sp.inj_count = 0;
-  return RELPIC_OK;
+  return guarded("set_injection", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (species < 0 || species >= (int)s->sp.size() || !ppc) return fail(RELPIC_EINVAL, "injection: bad species");
+    if (s->grid.bc1 != RELPIC_BC_WINDOW) return fail(RELPIC_ESTATE, "injection needs the moving window");
+    Species &sp = s->sp[species];
+    for (int d = 0; d < 3; ++d) {
+      sp.ppc[d] = d < s->ndim ? ppc[d] : 1;
+      if (sp.ppc[d] < 1 || sp.ppc[d] > 16) return fail(RELPIC_EINVAL, "injection: ppc must be in 1..16");
+    }
+    sp.inject = true;
+    sp.uth = uth;
+    sp.seed = seed;
+    sp.inj_count = 0;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_set_background_rho(relpic_sim *s, const double *rho, int64_t count) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (!rho || count != s->N) return fail(RELPIC_EINVAL, "background: count must equal the number of cells");
-  if (!s->rho_bg) {
-    s->rho_bg = (double *)dev_alloc(s, sizeof(double) * s->N);
-    if (!s->rho_bg) return fail(RELPIC_ENOMEM, "background: allocation failed");
-  }
-  // window-relative -> storage layout
-  std::vector<double> st((size_t)s->N);
-  const int n1 = s->n[0];
-  const int wsm = make_geo(s).ws_mod;
-  for (long long r = 0; r < s->N / n1; ++r)
-    for (int l = 0; l < n1; ++l) st[r * n1 + (l + wsm) % n1] = rho[r * n1 + l];
-  HIP_OK(hipMemcpyAsync(s->rho_bg, st.data(), sizeof(double) * s->N, hipMemcpyHostToDevice, s->st));
-  HIP_OK(hipStreamSynchronize(s->st));
-  return RELPIC_OK;
+  return guarded("set_background_rho", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (!rho || count != s->N) return fail(RELPIC_EINVAL, "background: count must equal the number of cells");
+    if (!s->rho_bg) {
+      s->rho_bg = (double *)dev_alloc(s, sizeof(double) * s->N);
+      if (!s->rho_bg) return fail(RELPIC_ENOMEM, "background: allocation failed");
+    }
+    // window-relative -> storage layout
+    std::vector<double> st((size_t)s->N);
+    const int n1 = s->n[0];
+    const int wsm = make_geo(s).ws_mod;
+    for (long long r = 0; r < s->N / n1; ++r)
+      for (int l = 0; l < n1; ++l) st[r * n1 + (l + wsm) % n1] = rho[r * n1 + l];
+    HIP_OK(hipMemcpyAsync(s->rho_bg, st.data(), sizeof(double) * s->N, hipMemcpyHostToDevice, s->st));
+    HIP_OK(hipStreamSynchronize(s->st));
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_step(relpic_sim *s, int64_t nsteps) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (nsteps < 0) return fail(RELPIC_EINVAL, "step: negative count");
-  if (s->prec == RELPIC_FP32) return do_steps<float>(s, nsteps);
-  return do_steps<double>(s, nsteps);
+  return guarded("step", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (nsteps < 0) return fail(RELPIC_EINVAL, "step: negative count");
+    if (s->prec == RELPIC_FP32) return do_steps<float>(s, nsteps);
+    return do_steps<double>(s, nsteps);
+  });
 }
 
 relpic_status relpic_sync(relpic_sim *s) {
-  if (relpic_status r = check_sim(s)) return r;
-  int err = 0;
-  HIP_OK(hipMemcpyAsync(&err, s->err, sizeof(int), hipMemcpyDeviceToHost, s->st));
-  HIP_OK(hipStreamSynchronize(s->st));
-  if (err) {
-    char buf[96];
-    std::snprintf(buf, sizeof buf, "kernel error word 0x%x (1: moved > 1 cell, 2: NaN momentum)", err);
-    return fail(RELPIC_EDEVICE, buf);
-  }
-  return RELPIC_OK;
+  return guarded("sync", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    int err = 0;
+    HIP_OK(hipMemcpyAsync(&err, s->err, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HIP_OK(hipStreamSynchronize(s->st));
+    if (err) {
+      char buf[96];
+      std::snprintf(buf, sizeof buf, "kernel error word 0x%x (1: moved > 1 cell, 2: NaN momentum)", err);
+      return fail(RELPIC_EDEVICE, buf);
+    }
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_read_field(relpic_sim *s, relpic_field f, double *host, int64_t count) {
-  if (relpic_status r = check_sim(s)) return r;
-  if ((int)f < 0 || (int)f > 8 || !host || count != s->N) return fail(RELPIC_EINVAL, "read_field: bad field or count");
-  std::vector<unsigned char> raw(s->esz * s->N);
-  HIP_OK(hipMemcpyAsync(raw.data(), s->F[(int)f], raw.size(), hipMemcpyDeviceToHost, s->st));
-  HIP_OK(hipStreamSynchronize(s->st));
-  const int n1 = s->n[0];
-  const int wsm = make_geo(s).ws_mod;
-  for (long long r = 0; r < s->N / n1; ++r)
-    for (int l = 0; l < n1; ++l) {
-      const long long src = r * n1 + (l + wsm) % n1;
-      double v;
-      if (s->esz == 4) {
-        float x;
-        std::memcpy(&x, &raw[src * 4], 4);
-        v = x;
-      } else {
-        std::memcpy(&v, &raw[src * 8], 8);
-      }
-      host[r * n1 + l] = v;
-    }
-  return RELPIC_OK;
+  return guarded("read_field", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if ((int)f < 0 || (int)f > 8 || !host || count != s->N) return fail(RELPIC_EINVAL, "read_field: bad field or count");
+    return copy_rows(s, (int)f, host, true);
+  });
 }
 
 relpic_status relpic_write_field(relpic_sim *s, relpic_field f, const double *host, int64_t count) {
-  if (relpic_status r = check_sim(s)) return r;
-  if ((int)f < 0 || (int)f > 8 || !host || count != s->N) return fail(RELPIC_EINVAL, "write_field: bad field or count");
-  std::vector<unsigned char> raw(s->esz * s->N);
-  const int n1 = s->n[0];
-  const int wsm = make_geo(s).ws_mod;
-  for (long long r = 0; r < s->N / n1; ++r)
-    for (int l = 0; l < n1; ++l) {
-      const long long dst = r * n1 + (l + wsm) % n1;
-      const double v = host[r * n1 + l];
-      if (s->esz == 4) {
-        const float x = (float)v;
-        std::memcpy(&raw[dst * 4], &x, 4);
-      } else {
-        std::memcpy(&raw[dst * 8], &v, 8);
-      }
-    }
-  HIP_OK(hipMemcpyAsync(s->F[(int)f], raw.data(), raw.size(), hipMemcpyHostToDevice, s->st));
-  HIP_OK(hipStreamSynchronize(s->st));
-  return RELPIC_OK;
+  return guarded("write_field", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if ((int)f < 0 || (int)f > 8 || !host || count != s->N) return fail(RELPIC_EINVAL, "write_field: bad field or count");
+    return copy_rows(s, (int)f, const_cast<double *>(host), false);
+  });
 }
 
 relpic_status relpic_field_device_ptr(relpic_sim *s, relpic_field f, void **ptr, int *elem_bytes) {
-  if (relpic_status r = check_sim(s)) return r;
-  if ((int)f < 0 || (int)f > 8 || !ptr) return fail(RELPIC_EINVAL, "field_device_ptr: bad field");
-  *ptr = s->F[(int)f];
-  if (elem_bytes) *elem_bytes = (int)s->esz;
-  return RELPIC_OK;
+  return guarded("field_device_ptr", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if ((int)f < 0 || (int)f > 8 || !ptr) return fail(RELPIC_EINVAL, "field_device_ptr: bad field");
+    *ptr = s->F[(int)f];
+    if (elem_bytes) *elem_bytes = (int)s->esz;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_read_particles(relpic_sim *s, int species, int64_t cap, int32_t *cell, double *offset, double *u,
                                     uint8_t *alive, int64_t *id, int64_t *n_out) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "read_particles: bad species");
-  Species &sp = s->sp[species];
-  if (n_out) *n_out = sp.n;
-  if (cap < sp.n || !cell || !offset || !u || !alive) return fail(RELPIC_ERANGE, "read_particles: buffers too small");
-  const long long n = sp.n;
-  const int nd = s->ndim;
-  std::vector<int> packed(n), ids(n);
-  HIP_OK(hipMemcpyAsync(packed.data(), sp.cell, sizeof(int) * n, hipMemcpyDeviceToHost, s->st));
-  HIP_OK(hipMemcpyAsync(ids.data(), sp.id, sizeof(int) * n, hipMemcpyDeviceToHost, s->st));
-  std::vector<unsigned char> raw(s->esz * std::max<long long>(n, 1));
-  auto get = [&](const void *src, int stride_idx, int stride, double *dst) -> relpic_status {
-    HIP_OK(hipMemcpyAsync(raw.data(), src, s->esz * n, hipMemcpyDeviceToHost, s->st));
-    HIP_OK(hipStreamSynchronize(s->st));
-    for (long long i = 0; i < n; ++i) {
-      double v;
-      if (s->esz == 4) {
-        float x;
-        std::memcpy(&x, &raw[i * 4], 4);
-        v = x;
-      } else {
-        std::memcpy(&v, &raw[i * 8], 8);
+  return guarded("read_particles", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "read_particles: bad species");
+    Species &sp = s->sp[species];
+    if (n_out) *n_out = sp.n;
+    if (cap < sp.n || !cell || !offset || !u || !alive) return fail(RELPIC_ERANGE, "read_particles: buffers too small");
+    const long long n = sp.n;
+    const int nd = s->ndim;
+    const int n1 = s->n[0];
+    const int wsm = make_geo(s).ws_mod;
+    // staged through bounded host buffers (kStage particles at a time)
+    const long long chunk = std::max<long long>(1, std::min<long long>(n, kStage));
+    std::vector<int> packed(chunk), ids(chunk);
+    std::vector<unsigned char> raw(s->esz * chunk);
+    for (long long first = 0; first < n; first += chunk) {
+      const long long m = std::min(chunk, n - first);
+      auto get = [&](const void *src, int stride_idx, int stride, double *dst) -> relpic_status {
+        HIP_OK(hipMemcpyAsync(raw.data(), (const char *)src + s->esz * first, s->esz * m, hipMemcpyDeviceToHost, s->st));
+        HIP_OK(hipStreamSynchronize(s->st));
+        for (long long i = 0; i < m; ++i) {
+          double v;
+          if (s->esz == 4) {
+            float x;
+            std::memcpy(&x, &raw[i * 4], 4);
+            v = x;
+          } else {
+            std::memcpy(&v, &raw[i * 8], 8);
+          }
+          dst[(first + i) * stride + stride_idx] = v;
+        }
+        return RELPIC_OK;
+      };
+      HIP_OK(hipMemcpyAsync(packed.data(), sp.cell + first, sizeof(int) * m, hipMemcpyDeviceToHost, s->st));
+      HIP_OK(hipMemcpyAsync(ids.data(), sp.id + first, sizeof(int) * m, hipMemcpyDeviceToHost, s->st));
+      for (int d = 0; d < nd; ++d)
+        if (relpic_status r = get(sp.o[d], d, nd, offset)) return r;
+      for (int d = 0; d < 3; ++d)
+        if (relpic_status r = get(sp.u[d], d, 3, u)) return r;
+      for (long long i = 0; i < m; ++i) {
+        const long long q = first + i;
+        const int pk = packed[i];
+        alive[q] = pk >= 0 ? 1 : 0;
+        if (id) id[q] = ids[i];
+        if (pk < 0) {
+          for (int d = 0; d < nd; ++d) cell[q * nd + d] = 0;
+          continue;
+        }
+        const int s1 = pk % n1;
+        const int rest = pk / n1;
+        const int l1 = ((s1 - wsm) % n1 + n1) % n1;
+        cell[q * nd + 0] = (int32_t)(l1 + (s->grid.bc1 == RELPIC_BC_WINDOW ? s->ws : 0));
+        cell[q * nd + 1] = rest % s->n[1];
+        if (nd == 3) cell[q * nd + 2] = rest / s->n[1];
       }
-      dst[i * stride + stride_idx] = v;
     }
     return RELPIC_OK;
-  };
-  for (int d = 0; d < nd; ++d)
-    if (relpic_status r = get(sp.o[d], d, nd, offset)) return r;
-  for (int d = 0; d < 3; ++d)
-    if (relpic_status r = get(sp.u[d], d, 3, u)) return r;
-  const int n1 = s->n[0];
-  const int wsm = make_geo(s).ws_mod;
-  for (long long i = 0; i < n; ++i) {
-    const int pk = packed[i];
-    alive[i] = pk >= 0 ? 1 : 0;
-    if (id) id[i] = ids[i];
-    if (pk < 0) {
-      for (int d = 0; d < nd; ++d) cell[i * nd + d] = 0;
-      continue;
+  });
+}
+
+relpic_status relpic_gather_particles(relpic_sim *s, int species, int64_t first, int64_t count, double *EB) {
+  return guarded("gather_particles", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "gather_particles: bad species");
+    Species &sp = s->sp[species];
+    if (first < 0 || count < 0 || first + count > sp.n) return fail(RELPIC_ERANGE, "gather_particles: slots out of range");
+    if (count > 0 && !EB) return fail(RELPIC_EINVAL, "gather_particles: null output");
+    if (count == 0) return RELPIC_OK;
+    const long long chunk = std::min<long long>(count, 1LL << 20);
+    if (chunk > s->gather_cap) {
+      s->gather_buf = (double *)dev_alloc(s, sizeof(double) * 6 * (size_t)chunk);
+      if (!s->gather_buf) return fail(RELPIC_ENOMEM, "gather_particles: allocation failed");
+      s->gather_cap = chunk;
     }
-    const int s1 = pk % n1;
-    const int rest = pk / n1;
-    const int l1 = ((s1 - wsm) % n1 + n1) % n1;
-    cell[i * nd + 0] = (int32_t)(l1 + (s->grid.bc1 == RELPIC_BC_WINDOW ? s->ws : 0));
-    cell[i * nd + 1] = rest % s->n[1];
-    if (nd == 3) cell[i * nd + 2] = rest / s->n[1];
-  }
-  return RELPIC_OK;
+    const Geo g = make_geo(s);
+    for (long long k0 = 0; k0 < count; k0 += chunk) {
+      const long long m = std::min<long long>(chunk, count - k0);
+      if (s->prec == RELPIC_FP32)
+        launch_gather_at_particles<float>(s->ndim, g, fields<float>(s), parts<float>(sp), first + k0, m, s->gather_buf,
+                                          s->st);
+      else
+        launch_gather_at_particles<double>(s->ndim, g, fields<double>(s), parts<double>(sp), first + k0, m,
+                                           s->gather_buf, s->st);
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipMemcpyAsync(EB + 6 * k0, s->gather_buf, sizeof(double) * 6 * m, hipMemcpyDeviceToHost, s->st));
+      HIP_OK(hipStreamSynchronize(s->st));
+    }
+    return RELPIC_OK;
+  });
+}
+
+relpic_status relpic_e1_residual(relpic_sim *s, int species, int64_t slot, const relpic_kspace *q, int64_t npts,
+                                 const int32_t *i1_rel, double *sim_out, double *theory_out) {
+  return guarded("e1_residual", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (s->ndim != 2) return fail(RELPIC_EINVAL, "e1_residual: the k-space field is the 2D one (Eq. 13)");
+    if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "e1_residual: bad species");
+    Species &sp = s->sp[species];
+    if (slot < 0 || slot >= sp.n) return fail(RELPIC_ERANGE, "e1_residual: particle slot out of range");
+    if (!q || npts < 1 || npts > 4096 || !i1_rel || !sim_out || !theory_out)
+      return fail(RELPIC_EINVAL, "e1_residual: bad arguments");
+    // the theory must describe this run: its axial operator, kappa = dx1/dt and r = dx2/dx1
+    const double kappa = s->dx[0] / s->grid.dt, r = s->dx[1] / s->dx[0];
+    if (std::fabs(q->kappa - kappa) > 1e-9 * kappa || std::fabs(q->r - r) > 1e-9 * r)
+      return fail(RELPIC_EINVAL, "e1_residual: kappa or r differ from the simulation's");
+    if (q->M != s->M) return fail(RELPIC_EINVAL, "e1_residual: axial operator differs from the simulation's");
+    for (int l = 0; l < s->M; ++l) {
+      const double c = (q->M == 1 && !q->C) ? 1.0 : q->C[l];
+      if (c != s->C[l]) return fail(RELPIC_EINVAL, "e1_residual: axial coefficients differ from the simulation's");
+    }
+    // the particle: on a node along x1 (the k-space field is for a charge on a node)
+    int packed = -1;
+    unsigned char o1raw[8] = {};
+    HIP_OK(hipMemcpyAsync(&packed, sp.cell + slot, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HIP_OK(hipMemcpyAsync(o1raw, (const char *)sp.o[0] + s->esz * slot, s->esz, hipMemcpyDeviceToHost, s->st));
+    HIP_OK(hipStreamSynchronize(s->st));
+    if (packed < 0) return fail(RELPIC_ESTATE, "e1_residual: the particle has been dropped");
+    double o1;
+    if (s->esz == 4) {
+      float x;
+      std::memcpy(&x, o1raw, 4);
+      o1 = x;
+    } else {
+      std::memcpy(&o1, o1raw, 8);
+    }
+    if (std::fabs(o1) > 1e-6) return fail(RELPIC_ERANGE, "e1_residual: the particle is not on an x1 node");
+    const int n1 = s->n[0];
+    const Geo g = make_geo(s);
+    const int s1 = packed % n1, row = packed / n1;
+    const int c1 = ((s1 - g.ws_mod) % n1 + n1) % n1;  // window cell
+    std::vector<double> line((size_t)n1);
+    {
+      std::vector<unsigned char> raw((size_t)n1 * s->esz);
+      HIP_OK(hipMemcpyAsync(raw.data(), (const char *)s->F[0] + (size_t)row * n1 * s->esz, raw.size(),
+                            hipMemcpyDeviceToHost, s->st));
+      HIP_OK(hipStreamSynchronize(s->st));
+      for (int l = 0; l < n1; ++l) {
+        const int sc = (l + g.ws_mod) % n1;
+        if (s->esz == 4) {
+          float x;
+          std::memcpy(&x, &raw[(size_t)sc * 4], 4);
+          line[l] = x;
+        } else {
+          std::memcpy(&line[l], &raw[(size_t)sc * 8], 8);
+        }
+      }
+    }
+    std::vector<double> rel((size_t)npts);
+    const double scale = s->dx[0] / sp.Q;
+    for (int64_t k = 0; k < npts; ++k) {
+      long long l = (long long)c1 + i1_rel[k];
+      if (s->grid.bc1 == RELPIC_BC_WINDOW) {
+        if (l < 0 || l >= n1) return fail(RELPIC_ERANGE, "e1_residual: point outside the window");
+      } else {
+        l = ((l % n1) + n1) % n1;
+      }
+      sim_out[k] = line[(size_t)l] * scale;
+      rel[(size_t)k] = (double)i1_rel[k];
+    }
+    relpic_kspace qq = *q;
+    relpic_device dv = s->dev;
+    return relpic_kspace_e1(&qq, &dv, npts, rel.data(), theory_out);
+  });
 }
 
 relpic_status relpic_diagnostics(relpic_sim *s, relpic_diag *out) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (!out) return fail(RELPIC_EINVAL, "diagnostics: null output");
-  if (s->prec == RELPIC_FP32) return do_diag<float>(s, out);
-  return do_diag<double>(s, out);
+  return guarded("diagnostics", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (!out) return fail(RELPIC_EINVAL, "diagnostics: null output");
+    if (s->prec == RELPIC_FP32) return do_diag<float>(s, out);
+    return do_diag<double>(s, out);
+  });
 }
 
 relpic_status relpic_get_step(relpic_sim *s, int64_t *step, int64_t *window_start) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (step) *step = s->step;
-  if (window_start) *window_start = s->ws;
-  return RELPIC_OK;
+  return guarded("get_step", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (step) *step = s->step;
+    if (window_start) *window_start = s->ws;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_sort_particles(relpic_sim *s) {
-  if (relpic_status r = check_sim(s)) return r;
-  for (auto &sp : s->sp) {
-    relpic_status r = s->prec == RELPIC_FP32 ? do_sort<float>(s, sp) : do_sort<double>(s, sp);
-    if (r) return r;
-  }
-  return RELPIC_OK;
+  return guarded("sort_particles", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    for (auto &sp : s->sp) {
+      relpic_status r = s->prec == RELPIC_FP32 ? do_sort<float>(s, sp) : do_sort<double>(s, sp);
+      if (r) return r;
+    }
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_set_sort_interval(relpic_sim *s, int64_t interval) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (interval < 0) return fail(RELPIC_EINVAL, "sort interval must be >= 0");
-  s->sort_interval = interval;
-  return RELPIC_OK;
+  return guarded("set_sort_interval", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (interval < 0) return fail(RELPIC_EINVAL, "sort interval must be >= 0");
+    s->sort_interval = interval;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_set_fused_fields(relpic_sim *s, int enable, int *active) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (enable && !s->Ex[0]) {
-    if (active) *active = 0;
-    return fail(RELPIC_EINVAL, "fused field update: not available on this grid (3D, n1 <= 512, n2 even, n1 at "
-                               "least twice the staged halo)");
-  }
-  s->fuse = enable != 0;
-  if (active) *active = s->fuse ? 1 : 0;
-  return RELPIC_OK;
+  return guarded("set_fused_fields", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (enable && !s->Ex[0]) {
+      if (active) *active = 0;
+      return fail(RELPIC_EINVAL, "fused field update: not available on this grid (3D, n1 <= 512, n2 even, n1 at "
+                                 "least twice the staged halo)");
+    }
+    s->fuse = enable != 0;
+    if (active) *active = s->fuse ? 1 : 0;
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_profile_enable(relpic_sim *s, int on) {
-  if (relpic_status r = check_sim(s)) return r;
-  HIP_OK(hipStreamSynchronize(s->st));
-  s->prof = on != 0;
-  s->ev_used = 0;
-  s->ev_marks.clear();
-  return RELPIC_OK;
+  return guarded("profile_enable", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    HIP_OK(hipStreamSynchronize(s->st));
+    s->prof = on != 0;
+    s->ev_used = 0;
+    s->ev_marks.clear();
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_profile_read(relpic_sim *s, relpic_profile *out) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (!out) return fail(RELPIC_EINVAL, "profile_read: null output");
-  HIP_OK(hipStreamSynchronize(s->st));
-  for (int k = 0; k < RELPIC_NUM_KERNEL_CLASSES; ++k) {
-    out->launches[k] = 0;
-    out->total_ms[k] = 0.0;
-  }
-  for (auto &m : s->ev_marks) {
-    float ms = 0.f;
-    HIP_OK(hipEventElapsedTime(&ms, s->ev_pool[m.second], s->ev_pool[m.second + 1]));
-    out->launches[m.first] += 1;
-    out->total_ms[m.first] += ms;
-  }
-  return RELPIC_OK;
+  return guarded("profile_read", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (!out) return fail(RELPIC_EINVAL, "profile_read: null output");
+    HIP_OK(hipStreamSynchronize(s->st));
+    for (int k = 0; k < RELPIC_NUM_KERNEL_CLASSES; ++k) {
+      out->launches[k] = 0;
+      out->total_ms[k] = 0.0;
+    }
+    for (auto &m : s->ev_marks) {
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, s->ev_pool[m.second], s->ev_pool[m.second + 1]));
+      out->launches[m.first] += 1;
+      out->total_ms[m.first] += ms;
+    }
+    return RELPIC_OK;
+  });
 }
 
 relpic_status relpic_correction_halfwidth(relpic_sim *s, int *hw) {
-  if (relpic_status r = check_sim(s)) return r;
-  if (hw) *hw = s->ng;
-  return RELPIC_OK;
+  return guarded("correction_halfwidth", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (hw) *hw = s->ng;
+    return RELPIC_OK;
+  });
 }
 
 }  // extern "C"

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -39,6 +41,26 @@ struct Species {
 };
 
 relpic_status fail(relpic_status s, const std::string &msg);
+// does not allocate: usable while handling std::bad_alloc
+relpic_status fail_noalloc(relpic_status s, const char *where, const char *what) noexcept;
+
+// Every extern "C" entry point runs its body through guarded(): a C++
+// exception (a host allocation that fails, a container length error) is
+// turned into a status and a message instead of crossing the C boundary.
+template <typename F>
+relpic_status guarded(const char *where, F &&body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return fail_noalloc(RELPIC_ENOMEM, where, "host allocation failed");
+  } catch (const std::length_error &) {
+    return fail_noalloc(RELPIC_ENOMEM, where, "host buffer size out of range");
+  } catch (const std::exception &e) {
+    return fail_noalloc(RELPIC_EINVAL, where, e.what());
+  } catch (...) {
+    return fail_noalloc(RELPIC_EINVAL, where, "unexpected C++ exception");
+  }
+}
 
 }  // namespace relpic_host
 
@@ -72,6 +94,8 @@ struct relpic_sim {
   double *dbuf = nullptr;      // diagnostics accumulators (8 doubles)
   double *rho = nullptr;       // FP64 scratch for the Gauss diagnostic
   double *rho_bg = nullptr;    // background charge, storage layout
+  double *gather_buf = nullptr;  // FP64 staging of fields gathered at particles (diagnostic)
+  long long gather_cap = 0;      // its capacity in particles
   std::vector<void *> owned;
   // per-kernel event timing
   bool prof = false;

@@ -107,6 +107,12 @@ void launch_diag_gauss(int ndim, const Geo &g, const Fields<Real> &f, const Axia
                        double idx3, const double *rho, const double *rho_bg, int margin1, double *out,
                        hipStream_t st);
 
+// E^n, B^n (f.B* = canonical B^n) at particles first .. first + count - 1,
+// quadratic spline per staggered component, FP64 out[6 k + c] (dropped: 0)
+template <typename Real>
+void launch_gather_at_particles(int ndim, const Geo &g, const Fields<Real> &f, const Particles<Real> &p,
+                                long long first, long long count, double *out, hipStream_t st);
+
 // ---- plasma injection ------------------------------------------------------------
 template <typename Real>
 void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, int *id, long long first, int win_cell, int ppc1,

@@ -326,4 +326,95 @@ void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, int *id, long
 RELPIC_INST_AUX(float)
 RELPIC_INST_AUX(double)
 
+
+// ---- fields at the particles (self-force diagnostic) ------------------------------
+// E^n and B^n interpolated at each particle with the push's quadratic
+// B-spline, each component from its own staggered points (E1 at (i1+1/2, i2,
+// i3), B3 at (i1+1/2, i2+1/2, i3), ...), in FP64.  B is the canonical B^n
+// held between relpic_step calls.  out[6 i + c] for particles first .. first
+// + count - 1; dropped particles give zeros.
+
+// weights at nodes c-1, c, c+1 (half = 0) or at half points j+1/2 with
+// j = the returned start - 1 .. start + 1 (half = 1) for offset o in [-1/2, 1/2)
+__device__ __forceinline__ int aux_weights(int c, double o, int half, double w[3]) {
+  double d = o;
+  int mid = c;
+  if (half) {
+    if (o >= 0.0) {
+      d = o - 0.5;
+    } else {
+      d = o + 0.5;
+      mid = c - 1;
+    }
+  }
+  const double a = 0.5 - d, b = 0.5 + d;
+  w[0] = 0.5 * a * a;
+  w[1] = 0.75 - d * d;
+  w[2] = 0.5 * b * b;
+  return mid;
+}
+
+template <typename Real, int DIM>
+__global__ __launch_bounds__(kRedBlock) void k_gather_at_particles(Geo g, Fields<Real> f, Particles<Real> p,
+                                                                    long long first, long long count, double *out) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const long long i = first + k;
+  const int packed = p.cell[i];
+  double res[6] = {0, 0, 0, 0, 0, 0};
+  if (packed >= 0) {
+    int s1, c2, c3;
+    unpack_cell(g, packed, s1, c2, c3);
+    int c1 = s1 - g.ws_mod;
+    if (c1 < 0) c1 += g.n1;
+    const int cc[3] = {c1, c2, c3};
+    const double o[3] = {(double)p.o1[i], (double)p.o2[i], DIM == 3 ? (double)p.o3[i] : 0.0};
+    const Real *F[6] = {f.E1, f.E2, f.E3, f.B1, f.B2, f.B3};
+    // half-integer staggering per component and axis
+    const int H[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+    for (int c = 0; c < 6; ++c) {
+      double w[3][3];
+      int mid[3] = {0, 0, 0};
+      for (int d = 0; d < 3; ++d) {
+        if (d < DIM) {
+          mid[d] = aux_weights(cc[d], o[d], H[c][d], w[d]);
+        } else {
+          w[d][0] = w[d][2] = 0.0;
+          w[d][1] = 1.0;
+        }
+      }
+      double acc = 0.0;
+      for (int kc = (DIM == 3 ? 0 : 1); kc < (DIM == 3 ? 3 : 2); ++kc) {
+        const int i3 = DIM == 3 ? wrap(mid[2] - 1 + kc, g.n3) : 0;
+        for (int kb = 0; kb < 3; ++kb) {
+          const int i2 = wrap(mid[1] - 1 + kb, g.n2);
+          for (int ka = 0; ka < 3; ++ka) {
+            const int col = col_of(g, mid[0] - 1 + ka);
+            if (col < 0) continue;  // outside the moving window: zero
+            const long long id = (long long)g.n1 * (i2 + (long long)g.n2 * i3) + col;
+            acc += w[0][ka] * w[1][kb] * w[2][kc] * (double)F[c][id];
+          }
+        }
+      }
+      res[c] = acc;
+    }
+  }
+  for (int c = 0; c < 6; ++c) out[6 * k + c] = res[c];
+}
+
+template <typename Real>
+void launch_gather_at_particles(int ndim, const Geo &g, const Fields<Real> &f, const Particles<Real> &p,
+                                long long first, long long count, double *out, hipStream_t st) {
+  if (count <= 0) return;
+  const unsigned nb = (unsigned)((count + kRedBlock - 1) / kRedBlock);
+  if (ndim == 3)
+    k_gather_at_particles<Real, 3><<<nb, kRedBlock, 0, st>>>(g, f, p, first, count, out);
+  else
+    k_gather_at_particles<Real, 2><<<nb, kRedBlock, 0, st>>>(g, f, p, first, count, out);
+}
+template void launch_gather_at_particles<float>(int, const Geo &, const Fields<float> &, const Particles<float> &,
+                                                long long, long long, double *, hipStream_t);
+template void launch_gather_at_particles<double>(int, const Geo &, const Fields<double> &, const Particles<double> &,
+                                                 long long, long long, double *, hipStream_t);
+
 }  // namespace relpic

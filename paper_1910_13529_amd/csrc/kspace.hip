@@ -267,25 +267,29 @@ extern "C" {
 
 relpic_status relpic_kspace_e1(const relpic_kspace *q, const relpic_device *dev, int64_t npts, const double *i1_rel,
                                double *out) {
-  KsParams p;
-  if (relpic_status e = check_params(q, p)) return e;
-  if (npts < 1 || npts > (1 << 20) || !i1_rel || !out) return fail(RELPIC_EINVAL, "kspace_e1: bad points");
-  std::vector<double> phase(npts);
-  for (int64_t i = 0; i < npts; ++i) {
-    if (!std::isfinite(i1_rel[i]) || std::fabs(i1_rel[i]) > 1e6) return fail(RELPIC_EINVAL, "kspace_e1: bad index");
-    phase[i] = 2.0 * i1_rel[i] + 1.0;
-  }
-  return run(p, q->nu_max, dev, phase, 0, out);
+  return guarded("kspace_e1", [&]() -> relpic_status {
+    KsParams p;
+    if (relpic_status e = check_params(q, p)) return e;
+    if (npts < 1 || npts > (1 << 20) || !i1_rel || !out) return fail(RELPIC_EINVAL, "kspace_e1: bad points");
+    std::vector<double> phase(npts);
+    for (int64_t i = 0; i < npts; ++i) {
+      if (!std::isfinite(i1_rel[i]) || std::fabs(i1_rel[i]) > 1e6) return fail(RELPIC_EINVAL, "kspace_e1: bad index");
+      phase[i] = 2.0 * i1_rel[i] + 1.0;
+    }
+    return run(p, q->nu_max, dev, phase, 0, out);
+  });
 }
 
 relpic_status relpic_kspace_self_force(const relpic_kspace *q, const relpic_device *dev, int gather_order,
                                        double *out) {
-  KsParams p;
-  if (relpic_status e = check_params(q, p)) return e;
-  if (!out || gather_order < 0 || gather_order > 4) return fail(RELPIC_EINVAL, "kspace_self_force: bad arguments");
-  p.gather_order = gather_order;
-  std::vector<double> phase(1, 0.0);
-  return run(p, q->nu_max, dev, phase, 1, out);
+  return guarded("kspace_self_force", [&]() -> relpic_status {
+    KsParams p;
+    if (relpic_status e = check_params(q, p)) return e;
+    if (!out || gather_order < 0 || gather_order > 4) return fail(RELPIC_EINVAL, "kspace_self_force: bad arguments");
+    p.gather_order = gather_order;
+    std::vector<double> phase(1, 0.0);
+    return run(p, q->nu_max, dev, phase, 1, out);
+  });
 }
 
 }  // extern "C"

@@ -29,7 +29,8 @@ EXPORTS = (
     "relpic_batch_run", "relpic_batch_step", "relpic_batch_sync", "relpic_batch_set_graph_steps",
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
     "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
-    "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_self_force", "relpic_last_error",
+    "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_self_force", "relpic_gather_particles", "relpic_e1_residual",
+    "relpic_last_error",
 )
 KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes", "leap")
 
@@ -163,6 +164,9 @@ def load():
     L.relpic_adj_sim.argtypes = [P, ctypes.POINTER(P)]
     L.relpic_kspace_e1.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), I64, dp, dp]
     L.relpic_kspace_self_force.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), ctypes.c_int, dp]
+    L.relpic_gather_particles.argtypes = [P, ctypes.c_int, I64, I64, dp]
+    L.relpic_e1_residual.argtypes = [P, ctypes.c_int, I64, ctypes.POINTER(KSpaceParams), I64,
+                                     ctypes.POINTER(ctypes.c_int32), dp, dp]
     L.relpic_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "relpic_last_error":
@@ -284,6 +288,7 @@ class SimOps:
     """The single-run calls on a handle (owned by a Sim or by a Batch)."""
 
     def _init_geometry(self, grid, precision):
+        self.grid = dict(grid)
         self.ndim = grid["ndim"]
         self.n = tuple(int(v) for v in grid["n"][: self.ndim])
         self.N = int(np.prod(self.n))
@@ -385,6 +390,36 @@ class SimOps:
         check(load().relpic_profile_read(self.h, ctypes.byref(p)))
         return {k: (int(p.launches[i]), float(p.total_ms[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
+    def gather_particles(self, species, first=0, count=None):
+        """E1..B3 (FP64, [count, 6]) at the particles of slots first .. first + count - 1."""
+        if count is None:
+            count = self.num_slots(species) - first
+        out = np.zeros((int(count), 6))
+        check(load().relpic_gather_particles(self.h, species, int(first), int(count), _dp(out)))
+        return out
+
+    def num_slots(self, species):
+        n = ctypes.c_int64()
+        st = load().relpic_read_particles(self.h, species, 0, None, None, None, None, None, ctypes.byref(n))
+        if st not in (RELPIC_OK, RELPIC_ERANGE):
+            check(st)
+        return n.value
+
+    def e1_residual(self, species, slot, i1_rel, C=None, kappa=None, r=None, beta=1.0, shape_order=2, tpow=1,
+                    nu_max=3):
+        """(simulated E1 dx1/Q, k-space E1 dx1/q) at E1 points i1_rel around the particle in `slot`."""
+        g = self.grid
+        C = getattr(self, "C", None) if C is None else C
+        kappa = g["dx"][0] / g["dt"] if kappa is None else kappa
+        r = g["dx"][1] / g["dx"][0] if r is None else r
+        q, keep = _kspace_struct(C, kappa, r, beta, shape_order, tpow, nu_max)
+        rel = np.ascontiguousarray(i1_rel, dtype=np.int32)
+        sim = np.zeros(rel.size)
+        th = np.zeros(rel.size)
+        check(load().relpic_e1_residual(self.h, species, int(slot), ctypes.byref(q), rel.size,
+                                        rel.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(sim), _dp(th)))
+        return sim, th
+
     @property
     def correction_halfwidth(self):
         v = ctypes.c_int()
@@ -397,6 +432,7 @@ class Sim(SimOps):
 
     def __init__(self, grid, C=None, precision="fp64", device=0, use_torch=True):
         self._init_geometry(grid, precision)
+        self.C = None if C is None or len(C) <= 1 else np.array(C, dtype=np.float64)
         self.allocator = None
         stream = None
         if use_torch:

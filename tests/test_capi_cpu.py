@@ -117,3 +117,56 @@ def test_batch_calls_reject_null_handle():
     assert L.relpic_batch_create(0, _grid_array([(2, 0)]), None, 0, None, ctypes.byref(ctypes.c_void_p())) == \
         relpic.RELPIC_EINVAL
     assert L.relpic_batch_destroy(None) == relpic.RELPIC_OK
+
+
+def test_every_entry_point_body_is_guarded():
+    """No C++ exception may cross the C boundary: every extern "C" entry point
+    returning a status runs its body inside guarded()."""
+    csrc = os.path.join(ROOT, "paper_1910_13529_amd", "csrc")
+    seen = 0
+    for fn in sorted(os.listdir(csrc)):
+        if not fn.endswith((".hip", ".cpp")):
+            continue
+        text = open(os.path.join(csrc, fn)).read()
+        for blk in re.findall(r'extern "C" \{(.*?)\}  // extern "C"', text, flags=re.S):
+            for m in re.finditer(r"^relpic_status (relpic_\w+)\([^;{]*\)\s*\{\s*(\S+)", blk, flags=re.M):
+                seen += 1
+                assert m.group(2).startswith("return"), m.group(1)
+                tail = blk[m.end(2) - len(m.group(2)):m.end(2) + 20]
+                assert tail.startswith("return guarded("), m.group(1)
+    assert seen == len(relpic.EXPORTS) - 1  # all but relpic_last_error
+
+
+def test_host_allocation_failure_returns_a_status():
+    """A host allocation that fails inside an entry point comes back as
+    RELPIC_ENOMEM with a message, not as std::terminate: the k-space entry
+    point stages its points in a host vector before any device call, and the
+    process's address space is capped just above what it already uses."""
+    import subprocess
+    import sys
+    script = r'''
+import ctypes, resource, sys
+sys.path.insert(0, %r)
+import numpy as np
+from paper_1910_13529_amd import relpic
+L = relpic.load()
+n = 1 << 20
+x = np.zeros(n)
+out = np.zeros(n)
+q, keep = relpic._kspace_struct(None, 4.0, 1.0, 1.0, 2, 0, 1)
+vm = 0
+for line in open("/proc/self/status"):
+    if line.startswith("VmSize:"):
+        vm = int(line.split()[1]) * 1024
+resource.setrlimit(resource.RLIMIT_AS, (vm + (2 << 20), resource.RLIM_INFINITY))
+st = L.relpic_kspace_e1(ctypes.byref(q), None, n, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+msg = L.relpic_last_error()
+resource.setrlimit(resource.RLIMIT_AS, (resource.RLIM_INFINITY, resource.RLIM_INFINITY))
+print("STATUS", st, msg.decode())
+''' % ROOT
+    r = subprocess.run([sys.executable, "-c", script], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    line = [ln for ln in r.stdout.splitlines() if ln.startswith("STATUS")][-1]
+    assert line.split()[1] == str(relpic.RELPIC_ENOMEM), line
+    assert "host allocation failed" in line
