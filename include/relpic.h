@@ -397,6 +397,21 @@ relpic_status relpic_kspace_e1(const relpic_kspace *q, const relpic_device *dev,
 relpic_status relpic_kspace_self_force(const relpic_kspace *q, const relpic_device *dev, int gather_order,
                                        double *out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid device allocation): relpic_kspace_e1
+ * without any device or host heap allocation.  Same arguments and results
+ * (the same panels and kernel); dev may be NULL (device 0, null stream) but
+ * must carry no allocator callbacks.  Its device scratch (quadrature panels,
+ * point phases, per-point results: 88 KiB) is a static array of the library,
+ * one copy per GPU, held until the process ends; limits: npts <= 4096
+ * (RELPIC_EINVAL beyond) and at most 1024 quadrature panels (RELPIC_ERANGE
+ * beyond; lower nu_max).  Every call on a GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (two host threads or two streams) race.
+ * Nothing in the scratch needs clearing (each call writes every value it
+ * reads).  Synchronizing. */
+relpic_status relpic_kspace_e1_noalloc(const relpic_kspace *q, const relpic_device *dev, int64_t npts,
+                                       const double *i1_rel, double *out);
+
 /* ---- Self-force and line-out against the k-space field (Sec. 2.2, Eq. 19) ---
  *
  * EB[6 k + c] (caller-owned, count x 6 doubles) = E1, E2, E3, B1, B2, B3 at

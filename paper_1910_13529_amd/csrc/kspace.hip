@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -149,15 +150,31 @@ __global__ __launch_bounds__(256) void k_kspace(KsParams p, const Panel *panels,
   if (threadIdx.x == 0) out[blockIdx.x] = -(part[0] + part[1] + part[2] + part[3]) / (2.0 * kPi * kPi * p.r);
 }
 
+// A fixed-capacity list (no heap allocation): panel breakpoints and panels
+// are built the same way for the allocating and the allocation-free entry
+// points, so both integrate over identical panels.
+template <typename T, int CAP>
+struct FixedList {
+  T v[CAP];
+  int n = 0;
+  bool overflow = false;
+  void push(const T &x) {
+    if (n < CAP)
+      v[n++] = x;
+    else
+      overflow = true;
+  }
+};
+
 // roots of f on [lo, hi] by a uniform scan and bisection
-template <typename F>
-void roots(F f, double lo, double hi, int n, std::vector<double> &out) {
+template <typename F, typename L>
+void roots(F f, double lo, double hi, int n, L &out) {
   double xa = lo, fa = f(lo);
   for (int i = 1; i <= n; ++i) {
     const double xb = lo + (hi - lo) * i / n;
     const double fb = f(xb);
     if (fa == 0.0) {
-      out.push_back(xa);
+      out.push(xa);
     } else if (fa * fb < 0.0) {
       double a = xa, b = xb, va = fa;
       for (int it = 0; it < 200 && b - a > 1e-16; ++it) {
@@ -173,27 +190,80 @@ void roots(F f, double lo, double hi, int n, std::vector<double> &out) {
           b = m;
         }
       }
-      out.push_back(0.5 * (a + b));
+      out.push(0.5 * (a + b));
     }
     xa = xb;
     fa = fb;
   }
 }
 
-std::vector<Panel> make_panels(const KsParams &p, int nu_max) {
-  std::vector<Panel> P;
+constexpr int kMaxBreaks = 256;  // breakpoints of one zone
+
+// Panels between consecutive breakpoints (A = 0, A = 1, sin(beta k1' dt) = 0,
+// the zone edges and 0) of every zone nu = -nu_max .. nu_max, written to out;
+// false if more than cap panels (or breakpoints) are needed.
+template <typename L>
+bool make_panels_into(const KsParams &p, int nu_max, L &out) {
   const double lo = -0.5 * kPi, hi = 0.5 * kPi;
   for (int nu = -nu_max; nu <= nu_max; ++nu) {
-    std::vector<double> bp = {lo, 0.0, hi};
+    FixedList<double, kMaxBreaks> bp;
+    bp.push(lo);
+    bp.push(0.0);
+    bp.push(hi);
     for (double lev : {0.0, 1.0}) roots([&](double k) { return a_of(p, k, nu) - lev; }, lo, hi, 4000, bp);
     roots([&](double k) { return std::sin(2.0 * p.beta * (k + nu * kPi) / p.kappa); }, lo, hi, 4000, bp);
-    std::sort(bp.begin(), bp.end());
-    for (size_t i = 0; i + 1 < bp.size(); ++i) {
-      const double a = std::max(lo, bp[i]), b = std::min(hi, bp[i + 1]);
-      if (b - a > 1e-14) P.push_back(Panel{a, b, nu, 0});
+    if (bp.overflow) return false;
+    std::sort(bp.v, bp.v + bp.n);
+    for (int i = 0; i + 1 < bp.n; ++i) {
+      const double a = std::max(lo, bp.v[i]), b = std::min(hi, bp.v[i + 1]);
+      if (b - a > 1e-14) out.push(Panel{a, b, nu, 0});
     }
   }
-  return P;
+  return !out.overflow;
+}
+
+struct PanelVec {
+  std::vector<Panel> v;
+  bool overflow = false;
+  void push(const Panel &x) { v.push_back(x); }
+};
+
+std::vector<Panel> make_panels(const KsParams &p, int nu_max) {
+  PanelVec out;
+  make_panels_into(p, nu_max, out);
+  return out.v;
+}
+
+
+// ---- allocation-free variant --------------------------------------------------------
+// Device scratch for relpic_kspace_e1_noalloc: panels, point phases and the
+// per-point results.  Each GPU the library runs on holds its own copy until
+// the process ends; its device address is looked up once per device.
+constexpr int kNaMaxPanels = 1024;
+constexpr int kNaMaxPoints = 4096;
+constexpr size_t kNaPanelBytes = sizeof(Panel) * kNaMaxPanels;       // 24 KiB
+constexpr size_t kNaPhaseOff = (kNaPanelBytes + 255) & ~size_t(255);
+constexpr size_t kNaOutOff = kNaPhaseOff + sizeof(double) * kNaMaxPoints;
+constexpr size_t kNaBytes = kNaOutOff + sizeof(double) * kNaMaxPoints;  // 88 KiB in all
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mutex;
+void *g_na_ptr[kNaMaxDevices] = {};
+
+// device address of `scratch` on the current device (hipGetSymbolAddress,
+// once per device); the array's host-side name is not a device address
+relpic_status scratch_ptr(int dev, unsigned char **out) {
+  if (dev < 0 || dev >= kNaMaxDevices) return fail_noalloc(RELPIC_EINVAL, "kspace_e1_noalloc", "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_na_mutex);
+  if (!g_na_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail_noalloc(RELPIC_EDEVICE, "kspace_e1_noalloc", "hipGetSymbolAddress failed");
+    g_na_ptr[dev] = ptr;
+  }
+  *out = (unsigned char *)g_na_ptr[dev];
+  return RELPIC_OK;
 }
 
 relpic_status check_params(const relpic_kspace *q, KsParams &p) {
@@ -289,6 +359,42 @@ relpic_status relpic_kspace_self_force(const relpic_kspace *q, const relpic_devi
     p.gather_order = gather_order;
     std::vector<double> phase(1, 0.0);
     return run(p, q->nu_max, dev, phase, 1, out);
+  });
+}
+
+relpic_status relpic_kspace_e1_noalloc(const relpic_kspace *q, const relpic_device *dev, int64_t npts,
+                                       const double *i1_rel, double *out) {
+  return guarded("kspace_e1_noalloc", [&]() -> relpic_status {
+    KsParams p;
+    if (relpic_status e = check_params(q, p)) return e;
+    if (npts < 1 || npts > kNaMaxPoints || !i1_rel || !out)
+      return fail_noalloc(RELPIC_EINVAL, "kspace_e1_noalloc", "need 1 <= npts <= 4096 and non-null arrays");
+    if (dev && (dev->alloc || dev->free))
+      return fail_noalloc(RELPIC_EINVAL, "kspace_e1_noalloc", "allocator callbacks are not used here: pass none");
+    double phase[kNaMaxPoints];
+    for (int64_t i = 0; i < npts; ++i) {
+      if (!std::isfinite(i1_rel[i]) || std::fabs(i1_rel[i]) > 1e6)
+        return fail_noalloc(RELPIC_EINVAL, "kspace_e1_noalloc", "bad index");
+      phase[i] = 2.0 * i1_rel[i] + 1.0;
+    }
+    FixedList<Panel, kNaMaxPanels> panels;  // on the stack (24 KiB): no heap allocation
+    if (!make_panels_into(p, q->nu_max, panels))
+      return fail_noalloc(RELPIC_ERANGE, "kspace_e1_noalloc", "more than 1024 quadrature panels: lower nu_max");
+    const int dv = dev ? dev->device : 0;
+    HIP_OK(hipSetDevice(dv));
+    hipStream_t st = dev ? (hipStream_t)dev->stream : nullptr;
+    unsigned char *base = nullptr;
+    if (relpic_status e = scratch_ptr(dv, &base)) return e;
+    Panel *dp = (Panel *)base;
+    double *dph = (double *)(base + kNaPhaseOff);
+    double *dout = (double *)(base + kNaOutOff);
+    HIP_OK(hipMemcpyAsync(dp, panels.v, sizeof(Panel) * panels.n, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(dph, phase, sizeof(double) * npts, hipMemcpyHostToDevice, st));
+    k_kspace<<<(unsigned)npts, 256, 0, st>>>(p, dp, panels.n, dph, 0, dout);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(out, dout, sizeof(double) * npts, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return RELPIC_OK;
   });
 }
 

@@ -30,7 +30,7 @@ EXPORTS = (
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
     "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
     "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_self_force", "relpic_gather_particles", "relpic_e1_residual",
-    "relpic_last_error",
+    "relpic_kspace_e1_noalloc", "relpic_last_error",
 )
 KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes", "leap")
 
@@ -164,6 +164,7 @@ def load():
     L.relpic_adj_sim.argtypes = [P, ctypes.POINTER(P)]
     L.relpic_kspace_e1.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), I64, dp, dp]
     L.relpic_kspace_self_force.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), ctypes.c_int, dp]
+    L.relpic_kspace_e1_noalloc.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), I64, dp, dp]
     L.relpic_gather_particles.argtypes = [P, ctypes.c_int, I64, I64, dp]
     L.relpic_e1_residual.argtypes = [P, ctypes.c_int, I64, ctypes.POINTER(KSpaceParams), I64,
                                      ctypes.POINTER(ctypes.c_int32), dp, dp]
@@ -634,6 +635,16 @@ def kspace_e1(i1_rel, C=None, kappa=4.0, r=1.0, beta=1.0, order=2, tpow=0, nu_ma
     out = np.zeros(x.size)
     dev = _device_struct(device, None, None)
     check(load().relpic_kspace_e1(ctypes.byref(q), ctypes.byref(dev), x.size, _dp(x), _dp(out)))
+    return out
+
+
+def kspace_e1_noalloc(i1_rel, C=None, kappa=4.0, r=1.0, beta=1.0, order=2, tpow=0, nu_max=1, device=0):
+    """relpic_kspace_e1 without device allocation (library-held scratch)."""
+    q, keep = _kspace_struct(C, kappa, r, beta, order, tpow, nu_max)
+    x = np.ascontiguousarray(np.atleast_1d(i1_rel), dtype=np.float64)
+    out = np.zeros(x.size)
+    dev = _device_struct(device, None, None)
+    check(load().relpic_kspace_e1_noalloc(ctypes.byref(q), ctypes.byref(dev), x.size, _dp(x), _dp(out)))
     return out
 
 
