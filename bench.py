@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of the relativistic-beam PIC step on one MI355X.
 
-Workload: 3D vacuum beam in a moving window, grid 512 x 256 x 256,
-dx = (0.02, 0.05, 0.05) c/omega_p, dt = dx1/4 (kappa = 4), 2^22 macro-electrons
-in a tri-Gaussian bunch (sigma_z = 0.1, sigma_r = 0.05, gamma = 1e4, 1% energy
-spread, 1 mrad divergence), FP32 fields and particles with cell + offset
-positions.  The headline line is the customized solver (Table 1, M = 16,
-with the J1 correction); the Yee solver is reported alongside.
+Default workload (the largest single-GPU configuration): a 3D beam in a
+uniform plasma, moving window, grid 512 x 256 x 256, dx = (0.02, 0.05, 0.05)
+c/omega_p, dt = dx1/4 (kappa = 4); 2^22 beam electrons in a tri-Gaussian
+bunch (sigma_z = 0.1, sigma_r = 0.05, gamma = 1e4, 1% energy spread, 1 mrad
+divergence) plus plasma electrons at 8 per cell (2 x 2 x 2 lattice, thermal
+u = 1e-4, immobile ions), 2.7e8 particles, injected into the front slab at
+every window shift; customized solver (Table 1, M = 16, J1 correction); FP32
+fields and particles with cell + offset positions, and the same workload in
+FP64.  The vacuum beam alone (the same grid and bunch) is reported beside it.
 
-One step = gather + Boris push + Esirkepov deposit + J1 correction + B half
-step + E step + B half step + window bookkeeping; particles are re-sorted by
-cell every 25 steps (the library's default), inside the timed region.  Inputs
+One step = gather + Boris push + Esirkepov deposit (both species) + J1
+correction + field update + window bookkeeping and injection.  The timed
+region starts with a particle re-sort (the library re-sorts every 25 steps),
+so a window of K <= 25 steps carries at least its share of sorting.  Inputs
 are resident on the GPU before the timed region.
 """
 import argparse
@@ -56,7 +60,10 @@ def algorithmic_bytes(kernel, ncells, npart, esz):
     return 0
 
 
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Vector ALU peaks: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6
+# TFLOP/s for FP32 issued one op per lane (the library is built without packed
+# FP32, whose 157.3 TFLOP/s it therefore cannot reach) and for FP64.
+FP32_VECTOR_PEAK_TFLOPS = 78.6
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
@@ -123,6 +130,7 @@ def run_gpu(args, w, cell, off, u, Q, solver, precision=None):
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
+    sim.sort_particles()  # the timed window opens with a re-sort (one per <= 25 steps)
     sim.step(args.steps)
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -310,6 +318,24 @@ def adjoint_main(args):
     print(json.dumps(out), flush=True)
 
 
+PUSH_PLASMA_KERNEL = "relpic::k_push_deposit<float, 3, 4>"  # the plasma's launch (tile-sorted, wide rounds)
+TRAFFIC_FILE_PLASMA = os.path.join(ROOT, "profiles", "traffic_plasma3d_fp32.json")
+
+
+def plasma_traffic(kernel):
+    """Calibrated HBM bytes per launch of `kernel` in the beam-in-plasma run,
+    or None when the counter summary is missing or from other sources."""
+    try:
+        tf = json.load(open(TRAFFIC_FILE_PLASMA))
+        from paper_1910_13529_amd.profiling import kernel_source_hash
+        if tf.get("source_hash") != kernel_source_hash():
+            return None
+        ent = tf.get("kernels", {}).get(kernel)
+        return ent["hbm_bytes_per_launch"] if ent else None
+    except Exception:
+        return None
+
+
 def run_plasma(args, precision, warmup, steps):
     """One run of the beam-in-plasma workload; returns timings and diagnostics."""
     import torch
@@ -320,7 +346,7 @@ def run_plasma(args, precision, warmup, steps):
     dV = w.dx[0] * w.dx[1] * w.dx[2]
     Qp = -dV / 8.0  # n0 = 1
     ppc = (2, 2, 2)
-    nprof = max(8, min(steps, 32))
+    nprof = max(4, min(steps, 12))
     shifts = (warmup + steps + nprof) // 4 + 2
     n_plasma0 = (n1 - 4) * n2 * n3 * 8
     cap = n_plasma0 + shifts * n2 * n3 * 8
@@ -346,35 +372,148 @@ def run_plasma(args, precision, warmup, steps):
     sim.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    sim.sort_particles()  # the timed window opens with a re-sort (one per <= 25 steps)
     sim.step(steps)
     sim.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # a re-sort alone, for its amortized cost
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.sort_particles()
+    torch.cuda.synchronize()
+    sort_ms = 1e3 * (time.perf_counter() - t1)
+    print("[bench] plasma %s: timing pass (%d steps)" % (precision, nprof), file=sys.stderr, flush=True)
     sim.profile_enable(True)
     sim.step(nprof)
     prof = sim.profile_read()
+    push_plasma = sim.profile_read_species(sp)
+    push_beam = sim.profile_read_species(sb)
     sim.profile_enable(False)
     diag = sim.diagnostics()
+    n_plasma_now = sim.num_slots(sp)
     sim.close()
-    return dict(w=w, npart=len(cell) + n_plasma0, wall_s=wall, prof=prof, nprof=nprof, diag=diag, fused=fused)
+    return dict(w=w, npart=len(cell) + n_plasma0, nbeam=len(cell), n_plasma_end=n_plasma_now, wall_s=wall,
+                sort_ms=sort_ms, prof=prof, nprof=nprof, push_plasma=push_plasma, push_beam=push_beam, diag=diag,
+                fused=fused)
+
+
+def beam_block(args):
+    """The vacuum beam alone (same grid and bunch, customized solver, FP32):
+    throughput and the fused field update's HBM roofline."""
+    w, cell, off, u, Q = make_workload(args)
+    ncells = int(math.prod(w.n))
+    print("[bench] vacuum beam: %d warmup + %d timed steps" % (args.warmup, args.steps), file=sys.stderr, flush=True)
+    r = run_gpu(args, w, cell, off, u, Q, "custom", precision="fp32")
+    prof = r["prof"]
+    out = {
+        "workload": "3D vacuum beam, moving window, grid 512x256x256, 4194304 macro-electrons, customized solver",
+        "ms_per_step": 1e3 * r["wall_s"] / args.steps,
+        "cell_updates_per_s": ncells * args.steps / r["wall_s"],
+        "particle_steps_per_s": len(cell) * args.steps / r["wall_s"],
+        "kernel_ms_per_step": {k: prof[k][1] / r["nprof"] for k in prof if prof[k][0]},
+    }
+    if prof.get("leap", (0, 0))[0]:
+        avg = prof["leap"][1] / prof["leap"][0]
+        alg = algorithmic_bytes("leap", ncells, len(cell), 4)
+        out["roofline_leap"] = {"bound": "hbm", "kernel": "k_leap (fused E and B update)",
+                                "achieved": alg / (avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "traffic": measured_traffic(TRAFFIC_FILE, "custom/fp32/leap"),
+                                "avg_launch_ms": avg, "algorithmic_bytes_per_launch": alg}
+    if prof.get("push_deposit", (0, 0))[0]:
+        avg = prof["push_deposit"][1] / prof["push_deposit"][0]
+        flops = push_flops_per_particle(3) * len(cell)
+        out["roofline_push"] = {"bound": "alu", "kernel": "k_push_deposit (beam)",
+                                "achieved": flops / (avg * 1e-3) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                                "unit": "TFLOP/s", "frac": flops / (avg * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                                "avg_launch_ms": avg}
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def plasma_cpu_baseline(args, w, cell, off, u, Q):
+    """The FP64 oracle on the host cores: a bounded sample of the
+    beam-in-plasma workload -- the full 256 x 256 transverse grid over a
+    16-cell window slab holding the plasma at 8 per cell and the beam
+    particles that fall in it; one field-only and one full step.  The
+    per-phase rates are combined at the full workload's cell and particle
+    counts."""
+    import numpy as np
+    from oracle import pic
+    from oracle.pic import OracleSim
+    from paper_1910_13529_amd import inputs
+    n1s = 16
+    n = (n1s, w.n[1], w.n[2])
+    dV = w.dx[0] * w.dx[1] * w.dx[2]
+    centre = int(np.round(np.median(cell[:, 0])))
+    shift = centre - n1s // 2
+    cs = cell.copy()
+    cs[:, 0] -= shift
+    keep = (cs[:, 0] >= 2) & (cs[:, 0] <= n1s - 3)
+    o = OracleSim(n, w.dx, w.dt, C=TABLE1_C, window=True)
+    t0 = time.perf_counter()
+    o.field_only(1)
+    t_fields = time.perf_counter() - t0
+    o2 = OracleSim(n, w.dx, w.dt, C=TABLE1_C, window=True)
+    c, of, uu = inputs.plasma_lattice(7, (2, 0, 0), (n1s - 2, n[1], n[2]), (2, 2, 2), 1e-4)
+    o2.add_particles(c.astype(np.float64) + of, uu, -dV / 8.0, -1.0)
+    o2.add_particles(cs[keep].astype(np.float64) + off[keep], u[keep], Q, -1.0)
+    npart_s = len(c) + int(keep.sum())
+    del c, of, uu
+    t0 = time.perf_counter()
+    o2.step(1)
+    t_step = time.perf_counter() - t0
+    ncell_s = int(np.prod(n))
+    rate_c = ncell_s / t_fields
+    rate_p = npart_s / max(t_step - t_fields, 1e-9)
+    ncells = int(np.prod(w.n))
+    npart = len(cell) + (w.n[0] - 4) * w.n[1] * w.n[2] * 8
+    t_est = ncells / rate_c + npart / rate_p
+    return {
+        "value": npart / t_est,
+        "unit": "particle-steps/s",
+        "cell_updates_per_s": ncells / t_est,
+        "cores": pic.threads(),
+        "nproc": os.cpu_count(),
+        "cpu_model": cpu_model(),
+        "kind": "oracle",
+        "sample": "FP64 C oracle (OpenMP over cells and particles' gather+push, deposit serial) on %d threads: "
+                  "full 256x256 transverse grid x 16-cell window slab with the plasma at 8 ppc and %d beam "
+                  "particles (%d particles), 1 field-only step (%.2f s) + 1 full step (%.2f s); per-phase rates "
+                  "(%.3g cell-updates/s, %.3g particle-steps/s) combined at the full workload's %d cells and %d "
+                  "particles" % (pic.threads(), int(keep.sum()), npart_s, t_fields, t_step, rate_c, rate_p, ncells,
+                                 npart),
+    }
 
 
 def plasma_main(args):
-    """The 3D beam in a uniform plasma: the beam grid and bunch plus plasma
-    electrons at 8 particles per cell on a 2x2x2 quiet-start lattice (u ~
-    1e-4 N(0, 1) per component, weight dV/8, immobile ions), injected into the
-    front slab at every window shift; customized solver, fused field update.
-    The plasma is generated on the host in x1 slabs and appended.  With FP32
-    the same workload also runs in FP64 for --fp64-steps steps."""
+    """The 3D beam in a uniform plasma (the largest single-GPU configuration):
+    headline throughput in FP32, the plasma push's ALU roofline, the same
+    workload in FP64, the vacuum beam alone, and the oracle on the host."""
     r = run_plasma(args, args.precision, args.warmup, args.steps)
     w, npart, wall, prof, nprof = r["w"], r["npart"], r["wall_s"], r["prof"], r["nprof"]
     ncells = int(math.prod(w.n))
     esz = 4 if args.precision == "fp32" else 8
     ms = 1e3 * wall / args.steps
-    # both species' push launches of a step against the flops of all particles
-    push_ms = prof["push_deposit"][1] / nprof
-    flops = push_flops_per_particle(3) * npart
-    peak_alu = FP32_VECTOR_PEAK_TFLOPS if args.precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
+    # dominant kernel: the plasma species' push+deposit launch (one per step)
+    pl_launches, pl_ms = r["push_plasma"]
+    avg_ms = pl_ms / max(pl_launches, 1)
+    n_pl = npart - r["nbeam"]  # plasma particles at the start of the timing pass (injection adds ~0.2% per shift)
+    flops = push_flops_per_particle(3) * n_pl
+    alg_bytes = algorithmic_bytes("push_deposit", ncells, n_pl, esz)
+    peak_alu = FP64_VECTOR_PEAK_TFLOPS  # non-packed FP32 = FP64 vector rate (packed FP32 is not used)
+    traffic = plasma_traffic(PUSH_PLASMA_KERNEL) if args.precision == "fp32" else None
+    step_bytes = ncells * (12 if r["fused"] else 18) * esz + npart * 2 * (4 + 6 * esz)
     out = {
         "metric": "particle-steps/s + field cell-updates/s per PIC step; % HBM peak; FP32 vs FP64",
         "value": npart * args.steps / wall,
@@ -389,14 +528,31 @@ def plasma_main(args):
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "3D beam in uniform plasma: beam grid and bunch plus plasma electrons at 8 ppc "
-                               "(2x2x2 lattice, u_th=1e-4, immobile ions), front-slab injection at each window "
-                               "shift, customized solver", "cells": ncells, "particles": npart,
-                   "fused_field_update": r["fused"], "parallelism": "single GPU"},
-        "roofline_push": {"bound": "alu", "kernel": "push_deposit", "push_ms_per_step": push_ms,
-                          "achieved": flops / (push_ms * 1e-3) / 1e12, "peak": peak_alu, "unit": "TFLOP/s",
-                          "frac": flops / (push_ms * 1e-3) / 1e12 / peak_alu,
-                          "hbm_achieved_gbs": algorithmic_bytes("push_deposit", ncells, npart, esz) / (push_ms * 1e-3) / 1e9},
+        "config": {"workload": "3D beam in uniform plasma, moving window, grid 512x256x256, dx=(0.02,0.05,0.05), "
+                               "dt=0.005 (kappa=4); 4194304 beam electrons (sigma_z=0.1, sigma_r=0.05, gamma=1e4, "
+                               "1% spread, 1 mrad) + plasma electrons at 8 ppc (2x2x2 lattice, u_th=1e-4, immobile "
+                               "ions) injected at each window shift; customized solver (Table 1, M=16, J1 "
+                               "correction)",
+                   "cells": ncells, "particles": npart, "fused_field_update": r["fused"],
+                   "particle_sort_interval": 25,
+                   "timed_region": "steps %d..%d after a re-sort at their start (sort included)" %
+                                   (args.warmup, args.warmup + args.steps - 1),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": PUSH_PLASMA_KERNEL + " (plasma species)",
+                     "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": peak_alu, "unit": "TFLOP/s",
+                     "frac": flops / (avg_ms * 1e-3) / 1e12 / peak_alu, "traffic": traffic,
+                     "avg_launch_ms": avg_ms, "flops_per_particle": push_flops_per_particle(3),
+                     "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": alg_bytes,
+                     "hbm_achieved_gbs": alg_bytes / (avg_ms * 1e-3) / 1e9,
+                     "hbm_frac": alg_bytes / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "peak_note": "78.6 TFLOP/s = 256 CU x 64 FP32 FMA lanes/clk x 2 x 2.4 GHz (packed FP32, "
+                                  "157.3, is not used: the build disables it)"},
+        "hbm_frac_step": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "hbm_bytes_step_definition": "%d B/cell (E, B read and written once%s) + %d B/particle (state read and "
+                                     "written once)" % ((12 if r["fused"] else 18) * esz,
+                                                        ", fused update" if r["fused"] else "", 2 * (4 + 6 * esz)),
+        "resort": {"ms_per_sort": r["sort_ms"], "amortized_ms_per_step": r["sort_ms"] / 25.0},
+        "push_ms_per_step": {"plasma": avg_ms, "beam": r["push_beam"][1] / max(r["push_beam"][0], 1)},
         "kernel_ms_per_step": {k: prof[k][1] / nprof for k in prof if prof[k][0]},
         "diag": {k: r["diag"][k] for k in ("step", "window_start", "n_alive", "w_field", "w_kin", "error_word")},
     }
@@ -412,6 +568,19 @@ def plasma_main(args):
             "kernel_ms_per_step": {k: p64[k][1] / r64["nprof"] for k in p64 if p64[k][0]},
             "diag": {k: r64["diag"][k] for k in ("step", "n_alive", "w_field", "w_kin", "error_word")},
         }
+        d32, d64 = r["diag"], r64["diag"]
+        if d32["step"] == d64["step"]:
+            out["fp64"]["fp32_vs_fp64_at_step_%d" % d64["step"]] = {
+                "w_field_rel": abs(d32["w_field"] - d64["w_field"]) / abs(d64["w_field"]),
+                "w_kin_rel": abs(d32["w_kin"] - d64["w_kin"]) / abs(d64["w_kin"]),
+                "charge_rel": abs(d32["charge"] - d64["charge"]) / abs(d64["charge"]),
+                "n_alive_fp32": d32["n_alive"], "n_alive_fp64": d64["n_alive"]}
+    if not args.no_beam_block:
+        out["beam3d"] = beam_block(args)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        w, cell, off, u, Q = make_workload(args)
+        out["cpu_baseline"] = plasma_cpu_baseline(args, w, cell, off, u, Q)
     print(json.dumps(out), flush=True)
 
 
@@ -462,8 +631,8 @@ def cpu_baseline(args, w, cell, off, u, Q, solver):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--grid", default="512,256,256")
     ap.add_argument("--npart", type=int, default=1 << 22)
@@ -473,10 +642,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=20, help="timed steps of the plasma workload's FP64 run")
     ap.add_argument("--separate-fields", action="store_true",
                     help="3D beam: separate E and B updates instead of the fused one")
-    ap.add_argument("--workload", default="beam3d", choices=["beam3d", "batch", "adjoint", "plasma3d"],
-                    help="beam3d: the 3D beam (default); batch: the 256-run batched workload; "
-                         "adjoint: time per gradient of the differentiable case; plasma3d: the 3D beam in a "
-                         "uniform plasma (8 ppc, 2.7e8 particles)")
+    ap.add_argument("--workload", default="plasma3d", choices=["beam3d", "batch", "adjoint", "plasma3d"],
+                    help="plasma3d: the 3D beam in a uniform plasma, 8 ppc, 2.7e8 particles (default); beam3d: "
+                         "the vacuum beam alone; batch: the 256-run batched workload; adjoint: time per "
+                         "gradient of the differentiable case")
+    ap.add_argument("--no-beam-block", action="store_true", help="plasma3d: skip the vacuum-beam block")
     ap.add_argument("--batch-solver", default="mixed", choices=["mixed", "yee", "custom"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (HBM counter calibration)")

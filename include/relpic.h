@@ -239,6 +239,10 @@ relpic_status relpic_profile_enable(relpic_sim *sim, int on);
 /* Synchronize and return the totals accumulated since enabling. */
 relpic_status relpic_profile_read(relpic_sim *sim, relpic_profile *out);
 
+/* The push+deposit launches (class 0) of one species alone, accumulated
+ * since enabling: number of launches and total time in ms (synchronizing). */
+relpic_status relpic_profile_read_species(relpic_sim *sim, int species, int64_t *launches, double *total_ms);
+
 /* ---- Batched many-run path ------------------------------------------------
  *
  * A batch advances many independent 2D runs with a periodic x1 boundary,

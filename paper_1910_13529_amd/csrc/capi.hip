@@ -240,7 +240,8 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
     f.B2 = Ba[1];
     f.B3 = Ba[2];
     const HalfB<Real> Bh{Bb[0], Bb[1], Bb[2]};
-    for (auto &sp : s->sp) {
+    for (size_t si = 0; si < s->sp.size(); ++si) {
+      Species &sp = s->sp[si];
       const PushParams<Real> q = push_params<Real>(s, sp, shift);
       const long long nb = push_blocks(sp.n, sp.K);
       if (nb > s->blockbox_n) {
@@ -252,7 +253,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
         s->blockbox_n = nb;
       }
       {
-        ProfScope ps(s, 0);
+        ProfScope ps(s, 0 + 64 * (int)(si + 1));
         launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, sp.K, sp.tile_keys, s->blockbox, s->err,
                                   s->st);
       }
@@ -1063,8 +1064,27 @@ relpic_status relpic_profile_read(relpic_sim *s, relpic_profile *out) {
     for (auto &m : s->ev_marks) {
       float ms = 0.f;
       HIP_OK(hipEventElapsedTime(&ms, s->ev_pool[m.second], s->ev_pool[m.second + 1]));
-      out->launches[m.first] += 1;
-      out->total_ms[m.first] += ms;
+      out->launches[m.first % 64] += 1;
+      out->total_ms[m.first % 64] += ms;
+    }
+    return RELPIC_OK;
+  });
+}
+
+relpic_status relpic_profile_read_species(relpic_sim *s, int species, int64_t *launches, double *total_ms) {
+  return guarded("profile_read_species", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (species < 0 || species >= (int)s->sp.size() || !launches || !total_ms)
+      return fail(RELPIC_EINVAL, "profile_read_species: bad species or output");
+    HIP_OK(hipStreamSynchronize(s->st));
+    *launches = 0;
+    *total_ms = 0.0;
+    for (auto &m : s->ev_marks) {
+      if (m.first != 64 * (species + 1)) continue;
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, s->ev_pool[m.second], s->ev_pool[m.second + 1]));
+      *launches += 1;
+      *total_ms += ms;
     }
     return RELPIC_OK;
   });

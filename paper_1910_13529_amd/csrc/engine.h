@@ -101,7 +101,8 @@ struct relpic_sim {
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<std::pair<int, size_t>> ev_marks;  // (class, index of the start event)
+  // (class + 64 * (species + 1) for a species' push, class otherwise; index of the start event)
+  std::vector<std::pair<int, size_t>> ev_marks;
 };
 
 #define HIP_OK(expr)                                                                              \

@@ -4,7 +4,7 @@ and into the per-launch HBM traffic that bench.py reports.
   python -m paper_1910_13529_amd.profiling trace STATS_CSV --command CMD --out FILE.md
   python -m paper_1910_13529_amd.profiling traffic --fetch CSV --write CSV \
       --fetch-copy CSV --write-copy CSV --copy-mib N --solver custom --precision fp32 \
-      --command-fetch CMD --command-write CMD --out profiles/traffic_counters.json
+      --command-fetch CMD --command-write CMD --out profiles/traffic_counters.json [--by-name]
 
 HBM traffic: FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch, each in
 its own rocprofv3 --pmc run, and scaled by what the same counter reads for a
@@ -98,7 +98,9 @@ def cmd_traffic(args):
         cls = kernel_class(name)
         if cls is None or name not in write:
             continue
-        key = "%s/%s/%s" % (args.solver, args.precision, cls)
+        # by name: one entry per kernel instantiation (e.g. the two species'
+        # push launches of the beam-in-plasma run); else one per class
+        key = short_name(name) if args.by_name else "%s/%s/%s" % (args.solver, args.precision, cls)
         if key in out["kernels"]:
             continue
         fb, wb = fetch[name] * sf, write[name] * sw
@@ -125,6 +127,7 @@ def main():
     c.add_argument("--copy-mib", type=int, required=True)
     c.add_argument("--solver", required=True)
     c.add_argument("--precision", required=True)
+    c.add_argument("--by-name", action="store_true", help="key the kernels by their instantiated names")
     args = ap.parse_args()
     cmd_trace(args) if args.cmd == "trace" else cmd_traffic(args)
 

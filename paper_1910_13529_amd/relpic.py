@@ -30,7 +30,7 @@ EXPORTS = (
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
     "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
     "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_self_force", "relpic_gather_particles", "relpic_e1_residual",
-    "relpic_kspace_e1_noalloc", "relpic_last_error",
+    "relpic_kspace_e1_noalloc", "relpic_profile_read_species", "relpic_last_error",
 )
 KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes", "leap")
 
@@ -164,6 +164,7 @@ def load():
     L.relpic_adj_sim.argtypes = [P, ctypes.POINTER(P)]
     L.relpic_kspace_e1.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), I64, dp, dp]
     L.relpic_kspace_self_force.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), ctypes.c_int, dp]
+    L.relpic_profile_read_species.argtypes = [P, ctypes.c_int, ctypes.POINTER(I64), dp]
     L.relpic_kspace_e1_noalloc.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), I64, dp, dp]
     L.relpic_gather_particles.argtypes = [P, ctypes.c_int, I64, I64, dp]
     L.relpic_e1_residual.argtypes = [P, ctypes.c_int, I64, ctypes.POINTER(KSpaceParams), I64,
@@ -420,6 +421,13 @@ class SimOps:
         check(load().relpic_e1_residual(self.h, species, int(slot), ctypes.byref(q), rel.size,
                                         rel.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(sim), _dp(th)))
         return sim, th
+
+    def profile_read_species(self, species):
+        """(launches, total ms) of one species' push+deposit since profiling was enabled."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        check(load().relpic_profile_read_species(self.h, species, ctypes.byref(n), ctypes.byref(ms)))
+        return int(n.value), float(ms.value)
 
     @property
     def correction_halfwidth(self):
