@@ -8,7 +8,7 @@ import pytest
 
 from oracle import dispersion, fit
 from paper_1910_13529_amd import inputs
-from tests.gpu_common import beam_species, field_errors, log, make_pair, particle_errors
+from tests.gpu_common import CANCEL_FRACTION, beam_species, field_errors, log, make_pair, particle_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -161,7 +161,7 @@ def _beam_sim(n, dx, dt, C, window, sp, precision):
 
 @pytest.mark.parametrize("solver", ["yee", "custom"])
 @pytest.mark.parametrize("window", [False, True])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_fused_field_update_matches_separate(solver, window, precision, tol):
     # the fused E and B update (one pass per step) against the separate
     # updates on the same run: n3 = 44 is five full columns of 8 planes and a
@@ -183,10 +183,13 @@ def test_fused_field_update_matches_separate(solver, window, precision, tol):
         g.sync()
     log("fused vs separate %s window=%s %s" % (solver, window, precision))
     for grp in ("E", "B"):
-        scale = max(float(np.abs(fields[False][grp + c]).max()) for c in "123")
-        assert scale > 0
+        gmax = max(float(np.abs(fields[False][grp + c]).max()) for c in "123")
         for c in "123":
+            own = float(np.abs(fields[False][grp + c]).max())
+            assert own > 0
+            scale = own if own >= CANCEL_FRACTION * gmax else gmax  # cancelling component: its terms' scale
             d = float(np.abs(fields[True][grp + c] - fields[False][grp + c]).max())
+            log("  %s%s: %.3g of %s maximum" % (grp, c, d / scale, "its" if scale == own else "the field's"))
             assert d <= tol * scale, (grp + c, d, scale)
     (ca, oa, ua, aa), (cb, ob, ub, ab) = fields[True]["x"], fields[False]["x"]
     assert (aa == ab).all()
@@ -209,7 +212,7 @@ def test_fused_field_update_availability():
 
 
 @pytest.mark.parametrize("precision,tol,xtol,utol,steps,sort_every", [
-    ("fp64", 1e-12, 1e-12, 1e-13, 13, 0), ("fp64", 1e-12, 1e-12, 1e-13, 30, 5), ("fp32", 2e-5, 2e-5, 2e-5, 30, 5)])
+    ("fp64", 1e-12, 1e-12, 1e-13, 13, 0), ("fp64", 1e-12, 1e-12, 1e-13, 30, 5), ("fp32", 1e-5, 2e-5, 2e-5, 30, 5)])
 def test_plasma_injection_window(precision, tol, xtol, utol, steps, sort_every):
     # cold plasma ahead of a beam in the moving window: the window injects a
     # slab of 2x2x2 particles per cell at each shift, momenta from the shared
@@ -280,7 +283,7 @@ def test_dense_bunch(ndim, precision, tol):
 
 
 @pytest.mark.parametrize("ndim", [2, 3])
-@pytest.mark.parametrize("precision,tol,ptol", [("fp64", 1e-12, 1e-12), ("fp32", 1e-4, 2e-5)])
+@pytest.mark.parametrize("precision,tol,ptol", [("fp64", 1e-12, 1e-12), ("fp32", 1e-5, 2e-5)])
 def test_sort_key_order_by_density(ndim, precision, tol, ptol):
     # the sort groups a sparse species (about two particles per cell over the
     # whole grid) by w x 4 (x 4) tiles of cells, x1 fastest inside a tile (w =
