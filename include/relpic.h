@@ -77,15 +77,31 @@ typedef struct {
   double window_speed;
 } relpic_grid;
 
-/* Axial operator: M coefficients C[0..M-1] (C_1..C_M of App. C).  M = 1 with
- * C = NULL or C[0] = 1 is the Yee solver.  For M > 1 the library also applies
- * the current correction J1 <- G * J1 (G the inverse of the telescoped
- * stencil) so that the discrete Gauss law holds with the customized
- * divergence (Sec. 3). */
+/* Axial operators (App. C).  M coefficients C[0..M-1] (C_1..C_M) of the
+ * operator on E (d+, Faraday's law: [k]_E1); M = 1 with C = NULL or C[0] = 1
+ * is Yee.  MB coefficients CB[0..MB-1] of the operator on B (d-, Ampere's
+ * law: [k]_B1; it is also the divergence of Gauss's law and of the
+ * continuity equation); MB = 0 (a zero-initialized struct) uses C for both,
+ * Sec. 3's choice [k]_E1 = [k]_B1.  Sec. 3 also allows [k]_E1 != [k]_B1 with
+ * [k]_E1 [k]_B1 = [k1]_t^2: e.g. MB = 1, CB = {1} (Yee on B) with C from
+ * relpic_fit_operator(..., RELPIC_FIT_E_WITH_YEE_B, ...).  Whenever the
+ * operator on B is wider than two points the library also applies the
+ * current correction J1 <- G * J1 (G the inverse of the telescoped d-
+ * stencil) so that the discrete Gauss law holds with that divergence; with
+ * Yee on B none is needed.  The shorter operator is zero-padded to the
+ * longer one's width. */
 typedef struct {
   int M;
   const double *C;
+  int MB;
+  const double *CB;
 } relpic_solver;
+
+/* Targets of the App. C fit. */
+enum {
+  RELPIC_FIT_TIME = 0,         /* [k]_1 = [k1]_t (the same operator on E and B) */
+  RELPIC_FIT_E_WITH_YEE_B = 1  /* [k]_E1 = [k1]_t^2 / [k]_Yee (operator on E when B uses Yee) */
+};
 
 typedef void *(*relpic_alloc_fn)(size_t bytes, void *user);
 typedef void (*relpic_free_fn)(void *device_ptr, void *user);
@@ -129,6 +145,11 @@ typedef struct {
  * (nullable): max relative symbol error for k1 dx1/2 <= 1. */
 relpic_status relpic_fit_coefficients(double kappa, int M, int p, double wk1, double nsg, double *C_out,
                                       double *max_rel_err_out);
+
+/* The same fit to another target (RELPIC_FIT_TIME or RELPIC_FIT_E_WITH_YEE_B);
+ * max_rel_err_out is then the error against that target. */
+relpic_status relpic_fit_operator(double kappa, int M, int p, double wk1, double nsg, int target, double *C_out,
+                                  double *max_rel_err_out);
 
 /* Create a simulation.  Returns RELPIC_EUNSTABLE if
  * (dt/2)^2 * max_k sum_d [k]_d^2 >= 1 for the chosen operators. */
@@ -372,13 +393,14 @@ relpic_status relpic_adj_sim(relpic_adj *adj, relpic_sim **sim);
  *
  * Sec. 2, Eq. 13 (general beta through Eqs. 8-9): the on-axis E1 of a point
  * charge q moving at beta along x1 through a 2D grid with the Yee transverse
- * operator and the axial operator C_1..C_M (Yee: M = 1, C = NULL or {1}),
+ * operator and the axial operators C_1..C_M on E and CB on B (Yee: M = 1,
+ * C = NULL or {1}; X = [beta k1']_t^2 - [k]_E1 [k]_B1, prefactor i/[k]_B1),
  * particle on a node, in the steady state of an infinite grid.  The k1
  * integral runs over the zones nu = -nu_max..nu_max of the aliased density
  * (App. A) with the k2 integral in closed form (App. D, causal pole
  * prescription).  Computed in FP64 by quadrature on the device. */
 typedef struct {
-  int M;
+  int M;           /* operator on E: [k]_E1 */
   const double *C;
   double kappa;    /* dx1 / dt (> 1) */
   double r;        /* dx2 / dx1 */
@@ -388,6 +410,8 @@ typedef struct {
                       0 for the paper's linear transverse shape, 1 for a quadratic
                       deposit, 2 for a quadratic deposit and gather */
   int nu_max;      /* alias zones (the paper uses 1) */
+  int MB;          /* operator on B, [k]_B1 (MB = 0: the same as on E) */
+  const double *CB;
 } relpic_kspace;
 
 /* out[i] = E1 dx1 / q at the E1 point i1_rel[i] cells ahead of the particle

@@ -28,6 +28,16 @@ TABLE1 = np.array([
 ])
 
 
+def target_e_with_yee_b(k, kappa):
+    """[k]_E1 / k_g1 such that [k]_E1 [k]_B1 = [k1]_t^2 with [k]_B1 the Yee
+    operator (Sec. 3: [k]_E1 != [k]_B1, product fixed), k normalized to k_g1:
+    kappa^2 sin^2(pi k / kappa) / (pi sin(pi k)); the k -> 0 limit is k."""
+    k = np.asarray(k, dtype=np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        v = kappa ** 2 * np.sin(np.pi * k / kappa) ** 2 / (np.pi * np.sin(np.pi * k))
+    return np.where(k == 0.0, 0.0, v)
+
+
 def weight(k, wk1=0.6, nsg=10.0):
     return np.exp(-math.log(2.0) * (2.0 * k / wk1) ** nsg)
 

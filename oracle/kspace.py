@@ -18,11 +18,12 @@ quadratic spline sampled at a node gives T = 1 - sin^2(k2 dx2/2)/2).
 In normalized variables khat = k1 dx1/2, theta = k2 dx2/2, r = dx2/dx1,
 kappa = dx1/dt this becomes
 
-  E1 dx1 / q = -(1/(2 pi^2 r)) int_{-pi/2}^{pi/2} dkhat (i/sigma1(khat))
+  E1 dx1 / q = -(1/(2 pi^2 r)) int_{-pi/2}^{pi/2} dkhat (i/sigmaB(khat))
                sum_nu Shat(khat + nu pi) Ihat_nu(khat) exp(i khat (2 i1' + 1))
 
-with sigma1 = [k]_1 dx1/2, Ihat = int dtheta T A/(A - sigma2(theta)^2),
-A = r^2 (tau^2 - sigma1^2), tau = kappa sin(beta (khat + nu pi)/kappa).
+with sigmaE = [k]_E1 dx1/2, sigmaB = [k]_B1 dx1/2 (equal unless the operators
+on E and on B differ, Sec. 3), Ihat = int dtheta T A/(A - sigma2(theta)^2),
+A = r^2 (tau^2 - sigmaE sigmaB), tau = kappa sin(beta (khat + nu pi)/kappa).
 
 The k2 integral is done in closed form (App. D, with the typo 1-A^2 read as
 1-A).  Poles (0 < A < 1 for the Yee transverse operator, 0 < A < pi^2/4 for
@@ -97,13 +98,17 @@ def k2_integral(A, s, kind="yee", tpow=0):
 class KSpace:
     """On-axis E1 and self-force of a streaming point charge (2D)."""
 
-    def __init__(self, solver="yee", kappa=4.0, r=1.0, order=2, beta=1.0, C=None, tpow=0, nus=(-1, 0, 1)):
+    def __init__(self, solver="yee", kappa=4.0, r=1.0, order=2, beta=1.0, C=None, tpow=0, nus=(-1, 0, 1), CB=None):
+        """solver names the operator on E (symbol [k]_E1); CB, when given,
+        the customized operator on B ([k]_B1, Sec. 3 allows them to differ),
+        else [k]_B1 = [k]_E1."""
         self.solver = solver
         self.kappa = float(kappa)
         self.r = float(r)
         self.order = order
         self.beta = float(beta)
         self.sigma1 = axial_symbol(solver, C, kappa)
+        self.sigmaB = self.sigma1 if CB is None else axial_symbol("custom", CB, kappa)
         self.kind = transverse_kind(solver)
         self.tpow = tpow
         self.nus = tuple(nus)
@@ -111,7 +116,7 @@ class KSpace:
     # X dx1^2/4 on zone nu
     def xhat(self, kh, nu):
         tau = self.kappa * np.sin(self.beta * (kh + nu * np.pi) / self.kappa)
-        return tau * tau - self.sigma1(kh) ** 2
+        return tau * tau - self.sigma1(kh) * self.sigmaB(kh)
 
     def A(self, kh, nu):
         return self.r ** 2 * self.xhat(kh, nu)
@@ -162,7 +167,7 @@ class KSpace:
             tot = 0.0
             for nu in self.nus:
                 def fn(kh, nu=nu):
-                    s1 = float(self.sigma1(kh))
+                    s1 = float(self.sigmaB(kh))  # i / [k]_B1 (continuity with the B operator)
                     if s1 == 0.0:
                         return 0.0
                     val = (1j / s1) * float(shape_hat(kh + nu * np.pi, self.order)) * self.ihat(kh, nu)
@@ -178,7 +183,7 @@ class KSpace:
         tot = 0.0
         for nu in self.nus:
             def fn(kh, nu=nu):
-                s1 = float(self.sigma1(kh))
+                s1 = float(self.sigmaB(kh))
                 if s1 == 0.0:
                     return 0.0
                 val = (1j / s1) * float(shape_hat(kh, go)) * float(shape_hat(kh + nu * np.pi, self.order)) * self.ihat(kh, nu)

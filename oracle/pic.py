@@ -39,7 +39,8 @@ def lib():
         lp = ctypes.POINTER(ctypes.c_long)
         ip = ctypes.POINTER(ctypes.c_int)
         L.orc_create.restype = P
-        L.orc_create.argtypes = [ctypes.c_int, lp, dp, D, ctypes.c_int, D, ctypes.c_int, dp, ctypes.c_int]
+        L.orc_create.argtypes = [ctypes.c_int, lp, dp, D, ctypes.c_int, D, ctypes.c_int, dp, ctypes.c_int, dp,
+                                 ctypes.c_int]
         L.orc_destroy.argtypes = [P]
         L.orc_add_particles.restype = Lg
         L.orc_add_particles.argtypes = [P, Lg, dp, dp, D, D]
@@ -80,21 +81,25 @@ class OracleSim:
 
     n, dx: per-dimension cells and spacing (len = ndim); dt: time step;
     window: False = periodic x1, True = moving window at speed vwin;
-    C: axial stencil coefficients (C = [1.0] is Yee); correct: apply the J1
-    correction (defaults to True whenever len(C) > 1).
+    C: axial stencil coefficients of d+ (E -> B) and, unless CB is given, of
+    d- (B -> E) as well (C = [1.0] is Yee); CB: coefficients of d- when the
+    two differ (Sec. 3, [k]_E1 != [k]_B1); correct: apply the J1 correction
+    (defaults to True whenever d- is not Yee).
     """
 
-    def __init__(self, n, dx, dt, C=(1.0,), window=False, vwin=1.0, correct=None):
+    def __init__(self, n, dx, dt, C=(1.0,), window=False, vwin=1.0, correct=None, CB=None):
         self.ndim = len(n)
         self.n = tuple(int(v) for v in n)
         self.shape = tuple(reversed(self.n))  # numpy view: [i3][i2][i1]
         C = np.ascontiguousarray(C, dtype=np.float64)
+        CBa = np.ascontiguousarray(C if CB is None else CB, dtype=np.float64)
         if correct is None:
-            correct = len(C) > 1
+            # a d- stencil wider than two points (trailing zeros aside) needs it
+            correct = int(np.flatnonzero(CBa).max(initial=0)) > 0
         nn = (ctypes.c_long * 3)(*(list(self.n) + [1] * (3 - self.ndim)))
         dd = np.ascontiguousarray(list(dx) + [1.0] * (3 - self.ndim), dtype=np.float64)
         self._h = lib().orc_create(self.ndim, nn, _dp(dd), float(dt), int(bool(window)), float(vwin),
-                                   len(C), _dp(C), int(bool(correct)))
+                                   len(C), _dp(C), 0 if CB is None else len(CBa), _dp(CBa), int(bool(correct)))
         if not self._h:
             raise ValueError("oracle: bad grid description")
         self.N = int(np.prod(self.n))

@@ -34,9 +34,13 @@
  * dropped and all d/dx3 vanish.
  *
  * Axial operators (App. C, the two one-sided forms):
- *   d+ f_i = (1/dx1) sum_{l=1..M} C_l (f_{i+l}   - f_{i-l+1})   acts on E -> B
- *   d- f_i = (1/dx1) sum_{l=1..M} C_l (f_{i+l-1} - f_{i-l})     acts on B -> E
+ *   d+ f_i = (1/dx1) sum_{l=1..M} C_l  (f_{i+l}   - f_{i-l+1})   acts on E -> B
+ *   d- f_i = (1/dx1) sum_{l=1..M} CB_l (f_{i+l-1} - f_{i-l})     acts on B -> E
  * M = 1, C_1 = 1 is the Yee operator.  x2 and x3 always use the Yee form.
+ * CB defaults to C ([k]_E1 = [k]_B1, Sec. 3's choice); Sec. 3 also allows
+ * [k]_E1 != [k]_B1 with [k]_E1 [k]_B1 = [k1]_t^2, e.g. [k]_B1 = Yee.  d- is
+ * the operator of Ampere's law and therefore of Gauss's law and of the
+ * continuity equation, so the J1 correction follows CB.
  *
  * Threads (OpenMP, optional): only loops whose iterations write disjoint
  * results run in parallel -- the field updates cell by cell, the J1
@@ -64,8 +68,9 @@ typedef struct {
   int window;   /* 0: periodic in x1;  1: moving window along +x1 */
   double vwin;  /* window speed in units of c */
   int M;
-  double C[ORC_MAXM];
-  int correct;  /* apply the J1 correction (customized solver) */
+  double C[ORC_MAXM];   /* d+ (E -> B) */
+  double CB[ORC_MAXM];  /* d- (B -> E), zero-padded to M */
+  int correct;  /* apply the J1 correction (customized d-) */
   long N;       /* number of cells */
   double *F[9]; /* E1 E2 E3 B1 B2 B3 J1 J2 J3 */
   /* particles: absolute positions in cell units (x1 is the global index) */
@@ -135,7 +140,7 @@ static double d1p(const orc_sim *s, const double *f, long i1, long i2, long i3) 
 static double d1m(const orc_sim *s, const double *f, long i1, long i2, long i3) {
   double acc = 0.0;
   for (int l = 1; l <= s->M; ++l)
-    acc += s->C[l - 1] * (fget(s, f, i1 + l - 1, i2, i3) - fget(s, f, i1 - l, i2, i3));
+    acc += s->CB[l - 1] * (fget(s, f, i1 + l - 1, i2, i3) - fget(s, f, i1 - l, i2, i3));
   return acc / s->dx[0];
 }
 /* transverse Yee differences (Eq. 14) */
@@ -165,15 +170,15 @@ static double spline2(double d) {
   return 0.0;
 }
 
-/* K^(theta) = [k]_custom / [k]_Yee, the symbol of the telescoped stencil */
+/* K^(theta) = [k]_B1 / [k]_Yee, the symbol of the telescoped d- stencil */
 static double khat_ratio(const orc_sim *s, double th) {
   double num = 0.0, den = sin(0.5 * th);
   if (fabs(den) < 1e-300) {
     double lim = 0.0;
-    for (int l = 1; l <= s->M; ++l) lim += s->C[l - 1] * (2.0 * l - 1.0);
+    for (int l = 1; l <= s->M; ++l) lim += s->CB[l - 1] * (2.0 * l - 1.0);
     return lim;
   }
-  for (int l = 1; l <= s->M; ++l) num += s->C[l - 1] * sin((2.0 * l - 1.0) * 0.5 * th);
+  for (int l = 1; l <= s->M; ++l) num += s->CB[l - 1] * sin((2.0 * l - 1.0) * 0.5 * th);
   return num / den;
 }
 
@@ -217,8 +222,8 @@ static void build_correction(orc_sim *s) {
 }
 
 void *orc_create(int ndim, const long *n, const double *dx, double dt, int window,
-                 double vwin, int M, const double *C, int correct) {
-  if (ndim < 2 || ndim > 3 || M < 1 || M > ORC_MAXM) return NULL;
+                 double vwin, int M, const double *C, int MB, const double *CB, int correct) {
+  if (ndim < 2 || ndim > 3 || M < 1 || M > ORC_MAXM || MB < 0 || MB > ORC_MAXM) return NULL;
   orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
   s->ndim = ndim;
   for (int d = 0; d < 3; ++d) {
@@ -228,8 +233,13 @@ void *orc_create(int ndim, const long *n, const double *dx, double dt, int windo
   s->dt = dt;
   s->window = window;
   s->vwin = vwin;
-  s->M = M;
-  for (int l = 0; l < M; ++l) s->C[l] = C[l];
+  /* both operators on max(M, MB) coefficients, the shorter one zero-padded */
+  int Mx = (MB > M) ? MB : M;
+  s->M = Mx;
+  for (int l = 0; l < Mx; ++l) {
+    s->C[l] = (l < M) ? C[l] : 0.0;
+    s->CB[l] = (MB == 0) ? s->C[l] : ((l < MB) ? CB[l] : 0.0);
+  }
   s->correct = correct;
   s->N = s->n[0] * s->n[1] * s->n[2];
   for (int k = 0; k < 9; ++k) s->F[k] = (double *)calloc((size_t)s->N, sizeof(double));

@@ -138,7 +138,7 @@ struct Ctx {
   // Ee += c curl- Bb
   void curl_minus(Real *const Ee[3], Real *const Bb[3], double c) const {
     const Fields<Real> f = fields_with(Ee, Bb);
-    launch_curl_b<Real>(2, g, f, axial_scaled<Real>(s, c), (Real)(c / s->dx[1]), Real(0), s->st);
+    launch_curl_b<Real>(2, g, f, axial_scaled_b<Real>(s, c), (Real)(c / s->dx[1]), Real(0), s->st);
   }
   // particle phase and E update of step n: e_{n+1} = e_n + dt curl- b_{n+1} - dt G J.
   // jbox receives the deposit box; J1c (M > 1) is left in F[9].
@@ -180,7 +180,8 @@ relpic_status set_coefficients(relpic_adj *a, const double *C) {
     if (!std::isfinite(C[l])) return fail(RELPIC_EINVAL, "adjoint: non-finite coefficient");
   const double cn = courant_number(2, s->dx, s->grid.dt, C, a->M);
   if (!(cn < 1.0)) return fail(RELPIC_EUNSTABLE, "adjoint: coefficients violate the Courant limit");
-  for (int l = 0; l < a->M; ++l) s->C[l] = C[l];
+  for (int l = 0; l < a->M; ++l) s->C[l] = s->CB[l] = C[l];  // one operator on E and on B
+  s->correct = a->M > 1;
   if (a->M > 1) {
     std::vector<double> taps;
     const double tol = s->prec == RELPIC_FP64 ? 1e-16 : 1e-9;

@@ -586,6 +586,9 @@ relpic_status relpic_batch_create(int nruns, const relpic_grid *grids, const rel
     for (int r = 0; r < nruns; ++r)
       if (grids[r].ndim != 2 || grids[r].bc1 != RELPIC_BC_PERIODIC)
         return fail(RELPIC_EINVAL, "batch_create: every run must be 2D with a periodic x1 boundary");
+    for (int r = 0; solvers && r < nruns; ++r)
+      if (solvers[r].MB != 0)
+        return fail(RELPIC_EINVAL, "batch_create: batched runs use one axial operator on E and B (MB = 0)");
     relpic_batch *b = new (std::nothrow) relpic_batch();
     if (!b) return fail(RELPIC_ENOMEM, "batch_create: host allocation failed");
     b->prec = prec;

@@ -193,7 +193,7 @@ template <typename Real>
 relpic_status do_steps(relpic_sim *s, long long nsteps) {
   if (nsteps == 0) return RELPIC_OK;
   const double dt = s->grid.dt;
-  const Axial<Real> axE = axial_scaled<Real>(s, dt);
+  const Axial<Real> axE = axial_scaled_b<Real>(s, dt);  // E update: the operator on B
   const Real e2 = (Real)(dt / s->dx[1]), e3 = (Real)(s->ndim == 3 ? dt / s->dx[2] : 0.0);
   const bool window = s->grid.bc1 == RELPIC_BC_WINDOW;
   Real *Ba[3] = {(Real *)s->F[3], (Real *)s->F[4], (Real *)s->F[5]};
@@ -262,7 +262,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
     }
     if (status) break;
     const Real *J1src = f.J1;
-    if (s->M > 1) {
+    if (s->correct) {
       ProfScope ps(s, 1);
       launch_jcorr<Real>(g, f.J1, f.J1c, (const Real *)s->taps, s->ng, box, s->st);
       J1src = f.J1c;
@@ -281,12 +281,12 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       Real *Eout[3] = {(Real *)s->Ex[0], (Real *)s->Ex[1], (Real *)s->Ex[2]};
       {
         ProfScope ps(s, 7);
-        launch_leap<Real>(g, Ein, Eout, Bb, Ba, J1src, f.J2, f.J3, box, s->M > 1 ? s->ng : 0, (Real)dt, axE, e2, e3,
+        launch_leap<Real>(g, Ein, Eout, Bb, Ba, J1src, f.J2, f.J3, box, s->correct ? s->ng : 0, (Real)dt, axE, e2, e3,
                           axial_scaled<Real>(s, fb), (Real)(fb / s->dx[1]), (Real)(fb / s->dx[2]), s->st);
       }
       {
         ProfScope ps(s, 5);
-        launch_clear_j<Real>(g, f, box, s->M > 1 ? s->ng : 0, next, s->st);
+        launch_clear_j<Real>(g, f, box, s->correct ? s->ng : 0, next, s->st);
       }
       for (int d = 0; d < 3; ++d) std::swap(s->F[d], s->Ex[d]);
       b_ahead = !last;
@@ -298,7 +298,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       }
       {
         ProfScope ps(s, 5);
-        launch_add_j<Real>(g, f, J1src, (Real)dt, box, s->M > 1 ? s->ng : 0, next, s->st);
+        launch_add_j<Real>(g, f, J1src, (Real)dt, box, s->correct ? s->ng : 0, next, s->st);
       }
     }
     swapB();
@@ -366,7 +366,7 @@ relpic_status do_diag(relpic_sim *s, relpic_diag *out) {
   }
   Axial<double> c1{};
   c1.M = s->M;
-  for (int l = 0; l < s->M; ++l) c1.c[l] = s->C[l] / s->dx[0];
+  for (int l = 0; l < s->M; ++l) c1.c[l] = s->CB[l] / s->dx[0];  // Gauss: the operator on B
   launch_diag_gauss<Real>(s->ndim, g, f, c1, 1.0 / s->dx[1], s->ndim == 3 ? 1.0 / s->dx[2] : 0.0, s->rho, s->rho_bg,
                           2 * s->M + 2, s->dbuf + 2, s->st);
   double h[8];
@@ -446,12 +446,14 @@ extern "C" {
 
 const char *relpic_last_error(void) { return last_error(); }
 
-relpic_status relpic_fit_coefficients(double kappa, int M, int p, double wk1, double nsg, double *C_out,
-                                      double *max_rel_err_out) {
-  return guarded("fit_coefficients", [&]() -> relpic_status {
-    if (!C_out || M < 1 || M > kMaxM) return fail(RELPIC_EINVAL, "fit: bad M or output pointer");
+relpic_status relpic_fit_operator(double kappa, int M, int p, double wk1, double nsg, int target, double *C_out,
+                                  double *max_rel_err_out) {
+  return guarded("fit_operator", [&]() -> relpic_status {
+    if (!C_out || M < 1 || M > kMaxM || (target != RELPIC_FIT_TIME && target != RELPIC_FIT_E_WITH_YEE_B))
+      return fail(RELPIC_EINVAL, "fit: bad M, target or output pointer");
     std::vector<double> C;
-    if (!fit_axial_coefficients(kappa, M, p, wk1, nsg, 2048, C)) return fail(RELPIC_EINVAL, "fit: singular or bad parameters");
+    if (!fit_axial_coefficients(kappa, M, p, wk1, nsg, 2048, C, target))
+      return fail(RELPIC_EINVAL, "fit: singular or bad parameters");
     std::copy(C.begin(), C.end(), C_out);
     if (max_rel_err_out) {
       double worst = 0.0;
@@ -459,12 +461,20 @@ relpic_status relpic_fit_coefficients(double kappa, int M, int p, double wk1, do
         const double kh = 1.0 * q / 2000;
         double v = 0.0;
         for (int l = 1; l <= M; ++l) v += C[l - 1] * std::sin((2 * l - 1) * kh);
-        const double t = kappa * std::sin(kh / kappa);
+        double t = kappa * std::sin(kh / kappa);
+        if (target == RELPIC_FIT_E_WITH_YEE_B) t = t * t / std::sin(kh);
         worst = std::max(worst, std::fabs(v - t) / t);
       }
       *max_rel_err_out = worst;
     }
     return RELPIC_OK;
+  });
+}
+
+relpic_status relpic_fit_coefficients(double kappa, int M, int p, double wk1, double nsg, double *C_out,
+                                      double *max_rel_err_out) {
+  return guarded("fit_coefficients", [&]() -> relpic_status {
+    return relpic_fit_operator(kappa, M, p, wk1, nsg, RELPIC_FIT_TIME, C_out, max_rel_err_out);
   });
 }
 
@@ -490,21 +500,40 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
       return fail(RELPIC_EINVAL, "create: grid too small (n1 >= 8, n2, n3 >= 2)");
     if (grid->n[1] > 65535 || (grid->ndim == 3 && grid->n[2] > 65535))
       return fail(RELPIC_EINVAL, "create: n2 and n3 are limited to 65535 (launch grid rows)");
-    int M = 1;
-    double C[kMaxM] = {1.0};
+    // operator on E (d+): M, C; operator on B (d-): MB, CB (MB = 0: the same as on E)
+    int ME = 1, MB = 0;
+    double CE[kMaxM] = {1.0}, CBv[kMaxM] = {1.0};
     if (solver && solver->M > 1) {
       if (solver->M > kMaxM || !solver->C) return fail(RELPIC_EINVAL, "create: bad solver coefficients");
-      M = solver->M;
-      for (int l = 0; l < M; ++l) C[l] = solver->C[l];
-      if (2 * M > grid->n[0]) return fail(RELPIC_EINVAL, "create: stencil wider than the grid");
+      ME = solver->M;
+      for (int l = 0; l < ME; ++l) CE[l] = solver->C[l];
     } else if (solver && solver->M == 1 && solver->C) {
-      C[0] = solver->C[0];
+      CE[0] = solver->C[0];
     }
+    if (solver && solver->MB > 0) {
+      if (solver->MB > kMaxM || (solver->MB > 1 && !solver->CB))
+        return fail(RELPIC_EINVAL, "create: bad coefficients of the operator on B");
+      MB = solver->MB;
+      for (int l = 0; l < MB; ++l) CBv[l] = solver->CB ? solver->CB[l] : 1.0;
+    } else if (solver && solver->MB < 0) {
+      return fail(RELPIC_EINVAL, "create: MB must be >= 0");
+    }
+    // both on M = max(ME, MB) coefficients, the shorter zero-padded
+    const int M = std::max(ME, MB);
+    double C[kMaxM] = {0.0}, CB[kMaxM] = {0.0};
+    for (int l = 0; l < M; ++l) {
+      C[l] = l < ME ? CE[l] : 0.0;
+      CB[l] = MB == 0 ? C[l] : (l < MB ? CBv[l] : 0.0);
+    }
+    int MBeff = 1;  // d- stencil width without trailing zeros: wider than two points needs the J1 correction
+    for (int l = 0; l < M; ++l)
+      if (CB[l] != 0.0) MBeff = l + 1;
+    if (2 * M > grid->n[0]) return fail(RELPIC_EINVAL, "create: stencil wider than the grid");
     if (grid->bc1 == RELPIC_BC_WINDOW) {
       if (!(grid->window_speed > 0.0) || grid->window_speed * grid->dt >= grid->dx[0])
         return fail(RELPIC_EINVAL, "create: window must advance less than one cell per step");
     }
-    const double cn = courant_number(grid->ndim, grid->dx, grid->dt, C, M);
+    const double cn = courant_number2(grid->ndim, grid->dx, grid->dt, C, CB, M);
     if (!(cn < 1.0)) {
       char buf[128];
       std::snprintf(buf, sizeof buf, "create: Courant number %.6f >= 1", cn);
@@ -526,17 +555,23 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
     s->prec = prec;
     s->esz = prec == RELPIC_FP32 ? 4 : 8;
     s->M = M;
-    for (int l = 0; l < M; ++l) s->C[l] = C[l];
+    for (int l = 0; l < M; ++l) {
+      s->C[l] = C[l];
+      s->CB[l] = CB[l];
+    }
+    s->correct = MBeff > 1;
     if (dev) s->dev = *dev;
     s->st = (hipStream_t)s->dev.stream;
     if (hipSetDevice(s->dev.device) != hipSuccess) {
       delete s;
       return fail(RELPIC_EDEVICE, "create: hipSetDevice failed");
     }
-    std::vector<double> taps;
-    if (M > 1) {
+    // the identity (one tap, 1) where no correction is needed, so a kernel that
+    // applies the taps anyway leaves J1 unchanged
+    std::vector<double> taps(1, 1.0);
+    if (s->correct) {
       const double tol = prec == RELPIC_FP64 ? 1e-16 : 1e-9;
-      if (!correction_taps(C, M, tol, kMaxTaps, taps)) {
+      if (!correction_taps(CB, M, tol, kMaxTaps, taps)) {
         delete s;
         return fail(RELPIC_EINVAL, "create: J1 correction does not converge within the tap limit");
       }
@@ -591,7 +626,7 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
       launch_reset_box(s->jbox + 1, s->st);
       e = hipGetLastError();
     }
-    if (e == hipSuccess && M > 1) {
+    if (e == hipSuccess) {
       std::vector<unsigned char> host(s->esz * taps.size());
       for (size_t i = 0; i < taps.size(); ++i) {
         if (prec == RELPIC_FP32) {
@@ -929,10 +964,15 @@ relpic_status relpic_e1_residual(relpic_sim *s, int species, int64_t slot, const
     const double kappa = s->dx[0] / s->grid.dt, r = s->dx[1] / s->dx[0];
     if (std::fabs(q->kappa - kappa) > 1e-9 * kappa || std::fabs(q->r - r) > 1e-9 * r)
       return fail(RELPIC_EINVAL, "e1_residual: kappa or r differ from the simulation's");
-    if (q->M != s->M) return fail(RELPIC_EINVAL, "e1_residual: axial operator differs from the simulation's");
+    // operators of q, zero-padded like the simulation's, must equal them
+    auto coef = [](int Mq, const double *Cq, int l) { return l < Mq ? ((Mq == 1 && !Cq) ? 1.0 : Cq[l]) : 0.0; };
+    if (q->M > s->M || q->MB > s->M || q->MB < 0)
+      return fail(RELPIC_EINVAL, "e1_residual: axial operator differs from the simulation's");
     for (int l = 0; l < s->M; ++l) {
-      const double c = (q->M == 1 && !q->C) ? 1.0 : q->C[l];
-      if (c != s->C[l]) return fail(RELPIC_EINVAL, "e1_residual: axial coefficients differ from the simulation's");
+      const double ce = coef(q->M, q->C, l);
+      const double cb = q->MB > 0 ? coef(q->MB, q->CB, l) : ce;
+      if (ce != s->C[l] || cb != s->CB[l])
+        return fail(RELPIC_EINVAL, "e1_residual: axial coefficients differ from the simulation's");
     }
     // the particle: on a node along x1 (the k-space field is for a charge on a node)
     int packed = -1;

@@ -73,8 +73,10 @@ struct relpic_sim {
   double dx[3] = {1, 1, 1};
   relpic_precision prec = RELPIC_FP64;
   size_t esz = 8;
-  int M = 1;
-  double C[relpic::kMaxM] = {1.0};
+  int M = 1;                        // stencil half-width of both axial operators (the shorter one zero-padded)
+  double C[relpic::kMaxM] = {1.0};   // d+ (E -> B): [k]_E1
+  double CB[relpic::kMaxM] = {1.0};  // d- (B -> E, Gauss, continuity): [k]_B1
+  bool correct = false;              // J1 correction on (d- wider than two points)
   relpic_device dev{};
   hipStream_t st = nullptr;
   long long N = 0;
@@ -167,12 +169,22 @@ inline double cell_volume(const relpic_sim *s) {
   return v;
 }
 
-// axial coefficients C_l c / dx1 (c: the time factor of the update)
+// axial coefficients C_l c / dx1 of the operator on E (d+, E -> B; c: the
+// time factor of the update)
 template <typename Real>
 inline Axial<Real> axial_scaled(const relpic_sim *s, double c) {
   Axial<Real> ax{};
   ax.M = s->M;
   for (int l = 0; l < s->M; ++l) ax.c[l] = (Real)(s->C[l] * c / s->dx[0]);
+  return ax;
+}
+
+// the same for the operator on B (d-, B -> E)
+template <typename Real>
+inline Axial<Real> axial_scaled_b(const relpic_sim *s, double c) {
+  Axial<Real> ax{};
+  ax.M = s->M;
+  for (int l = 0; l < s->M; ++l) ax.c[l] = (Real)(s->CB[l] * c / s->dx[0]);
   return ax;
 }
 

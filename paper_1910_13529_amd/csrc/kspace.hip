@@ -50,7 +50,8 @@ constexpr int kTsHalf = 224;            // nodes k = -kTsHalf .. kTsHalf (t up t
 
 struct KsParams {
   int M;
-  double C[kKsMaxM];
+  double C[kKsMaxM];   // operator on E, [k]_E1
+  double CB[kKsMaxM];  // operator on B, [k]_B1 (zero-padded to M)
   double kappa, r, beta;
   int order, tpow, gather_order;
 };
@@ -67,10 +68,15 @@ __host__ __device__ inline double sigma1(const KsParams &p, double kh) {
   return v;
 }
 
+__host__ __device__ inline double sigma1b(const KsParams &p, double kh) {
+  double v = 0.0;
+  for (int l = 1; l <= p.M; ++l) v += p.CB[l - 1] * sin((2 * l - 1) * kh);
+  return v;
+}
+
 __host__ __device__ inline double a_of(const KsParams &p, double kh, int nu) {
   const double tau = p.kappa * sin(p.beta * (kh + nu * kPi) / p.kappa);
-  const double s1 = sigma1(p, kh);
-  return p.r * p.r * (tau * tau - s1 * s1);
+  return p.r * p.r * (tau * tau - sigma1(p, kh) * sigma1b(p, kh));
 }
 
 __device__ inline double shat(double k, int order) {
@@ -107,7 +113,7 @@ __device__ inline void k2_integral(double A, double s, int tpow, double &re, dou
 // Re[(i / sigma1) Shat(kh + nu pi) I e^{i ph kh}]; with force = true the
 // self-force weight Shat_g(kh) replaces the phase factor
 __device__ inline double integrand(const KsParams &p, double kh, int nu, double ph, bool force) {
-  const double s1 = sigma1(p, kh);
+  const double s1 = sigma1b(p, kh);  // i / [k]_B1
   if (s1 == 0.0) return 0.0;
   const double A = a_of(p, kh, nu);
   const double sv = sin(2.0 * p.beta * (kh + nu * kPi) / p.kappa);
@@ -273,9 +279,11 @@ relpic_status check_params(const relpic_kspace *q, KsParams &p) {
     return fail(RELPIC_EINVAL, "kspace: need kappa > 1, r > 0, 0 < beta <= 1");
   if (q->shape_order < 0 || q->shape_order > 4 || q->tpow < 0 || q->tpow > 2 || q->nu_max < 0 || q->nu_max > 8)
     return fail(RELPIC_EINVAL, "kspace: bad shape order, transverse factor power or zone count");
+  if (q->MB < 0 || q->MB > kKsMaxM || (q->MB > 1 && !q->CB)) return fail(RELPIC_EINVAL, "kspace: bad operator on B");
   std::memset(&p, 0, sizeof(p));
-  p.M = q->M;
+  p.M = std::max(q->M, q->MB);
   for (int l = 0; l < q->M; ++l) p.C[l] = q->M == 1 && !q->C ? 1.0 : q->C[l];
+  for (int l = 0; l < p.M; ++l) p.CB[l] = q->MB == 0 ? p.C[l] : (l < q->MB ? (q->CB ? q->CB[l] : 1.0) : 0.0);
   p.kappa = q->kappa;
   p.r = q->r;
   p.beta = q->beta;

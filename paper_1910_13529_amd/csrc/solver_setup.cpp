@@ -40,7 +40,9 @@ static bool solve_dense(std::vector<double> A, std::vector<double> b, int n, std
 // with T(k) = kappa sin(pi k / kappa)/pi, subject to the order-p consistency
 // rows, via the Lagrange (KKT) system.  The integrals use the trapezoid rule
 // on `nq` intervals of [0, 1/2].
-bool fit_axial_coefficients(double kappa, int M, int p, double wk1, double nsg, int nq, std::vector<double> &C) {
+bool fit_axial_coefficients(double kappa, int M, int p, double wk1, double nsg, int nq, std::vector<double> &C,
+                            int target_kind) {
+  if (target_kind != 0 && target_kind != 1) return false;
   if (M < 1 || p < 2 || (p % 2) || p / 2 > M || kappa <= 1.0 || nq < 16) return false;
   const int r = p / 2;
   const int n = M + r;
@@ -51,7 +53,9 @@ bool fit_axial_coefficients(double kappa, int M, int p, double wk1, double nsg, 
     double wq = 0.5 / nq;
     if (q == 0 || q == nq) wq *= 0.5;
     const double w = std::exp(-std::log(2.0) * std::pow(2.0 * k / wk1, nsg)) * wq;
-    const double target = kappa * std::sin(kPi * k / kappa) / kPi;
+    // 0: [k1]_t; 1: [k1]_t^2 / [k]_Yee (the operator on E when the one on B is Yee)
+    double target = kappa * std::sin(kPi * k / kappa) / kPi;
+    if (target_kind == 1) target = k == 0.0 ? 0.0 : target * target / (std::sin(kPi * k) / kPi);
     for (int i = 0; i < M; ++i) s[i] = std::sin((2 * i + 1) * kPi * k);
     for (int i = 0; i < M; ++i) {
       b[i] += (2.0 / kPi) * w * s[i] * target;
@@ -87,9 +91,28 @@ double axial_symbol_max(const double *C, int M) {
   return best;
 }
 
+double axial_product_max(const double *CE, const double *CB, int M) {
+  // max over khat in [0, pi/2] of |sigma_E(khat) sigma_B(khat)|
+  double best = 0.0;
+  const int ns = 8192;
+  for (int q = 0; q <= ns; ++q) {
+    const double kh = 0.5 * kPi * q / ns;
+    double a = 0.0, b = 0.0;
+    for (int l = 1; l <= M; ++l) {
+      a += CE[l - 1] * std::sin((2 * l - 1) * kh);
+      b += CB[l - 1] * std::sin((2 * l - 1) * kh);
+    }
+    best = std::fmax(best, std::fabs(a * b));
+  }
+  return best;
+}
+
 double courant_number(int ndim, const double *dx, double dt, const double *C, int M) {
-  const double s1 = axial_symbol_max(C, M) / dx[0];
-  double sum = s1 * s1;
+  return courant_number2(ndim, dx, dt, C, C, M);
+}
+
+double courant_number2(int ndim, const double *dx, double dt, const double *CE, const double *CB, int M) {
+  double sum = axial_product_max(CE, CB, M) / (dx[0] * dx[0]);
   for (int d = 1; d < ndim; ++d) sum += 1.0 / (dx[d] * dx[d]);
   return dt * std::sqrt(sum);  // (dt/2) * sqrt(sum (2 sigma_d / dx_d)^2)
 }

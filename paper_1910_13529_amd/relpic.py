@@ -30,7 +30,7 @@ EXPORTS = (
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
     "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
     "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_self_force", "relpic_gather_particles", "relpic_e1_residual",
-    "relpic_kspace_e1_noalloc", "relpic_profile_read_species", "relpic_last_error",
+    "relpic_kspace_e1_noalloc", "relpic_profile_read_species", "relpic_fit_operator", "relpic_last_error",
 )
 KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes", "leap")
 
@@ -47,7 +47,8 @@ class Grid(ctypes.Structure):
 
 
 class Solver(ctypes.Structure):
-    _fields_ = [("M", ctypes.c_int), ("C", ctypes.POINTER(ctypes.c_double))]
+    _fields_ = [("M", ctypes.c_int), ("C", ctypes.POINTER(ctypes.c_double)), ("MB", ctypes.c_int),
+                ("CB", ctypes.POINTER(ctypes.c_double))]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -92,7 +93,8 @@ class LossBox(ctypes.Structure):
 class KSpaceParams(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("C", ctypes.POINTER(ctypes.c_double)), ("kappa", ctypes.c_double),
                 ("r", ctypes.c_double), ("beta", ctypes.c_double), ("shape_order", ctypes.c_int),
-                ("tpow", ctypes.c_int), ("nu_max", ctypes.c_int)]
+                ("tpow", ctypes.c_int), ("nu_max", ctypes.c_int), ("MB", ctypes.c_int),
+                ("CB", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -122,6 +124,7 @@ def load():
     for name in EXPORTS:
         getattr(L, name)  # every declared entry point must exist
     L.relpic_fit_coefficients.argtypes = [D, ctypes.c_int, ctypes.c_int, D, D, dp, dp]
+    L.relpic_fit_operator.argtypes = [D, ctypes.c_int, ctypes.c_int, D, D, ctypes.c_int, dp, dp]
     L.relpic_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Solver), ctypes.c_int, ctypes.POINTER(Device),
                                 ctypes.POINTER(P)]
     L.relpic_destroy.argtypes = [P]
@@ -196,6 +199,16 @@ def relpic_fit_coefficients(kappa, M, p=2, wk1=0.6, nsg=10.0):
     return C, err.value
 
 
+RELPIC_FIT_TIME, RELPIC_FIT_E_WITH_YEE_B = 0, 1
+
+
+def relpic_fit_operator(kappa, M, target=RELPIC_FIT_TIME, p=2, wk1=0.6, nsg=10.0):
+    C = np.zeros(M)
+    err = ctypes.c_double()
+    check(load().relpic_fit_operator(kappa, M, p, wk1, nsg, int(target), _dp(C), ctypes.byref(err)))
+    return C, err.value
+
+
 class TorchAllocator:
     """Device memory for the library from PyTorch's caching allocator."""
 
@@ -232,8 +245,9 @@ def _grid_struct(grid, g=None):
     return g
 
 
-def _solver_struct(solver_C, s=None):
-    """fills a Solver; returns it and the coefficient array it points to (keep it alive)"""
+def _solver_struct(solver_C, s=None, CB=None):
+    """fills a Solver (operator on E: solver_C; on B: CB, None = the same);
+    returns it and the coefficient arrays it points to (keep them alive)"""
     s = Solver() if s is None else s
     Carr = None
     if solver_C is not None and len(solver_C) > 1:
@@ -243,7 +257,15 @@ def _solver_struct(solver_C, s=None):
     else:
         s.M = 1
         s.C = None
-    return s, Carr
+    CBarr = None
+    if CB is None:
+        s.MB = 0
+        s.CB = None
+    else:
+        CBarr = np.ascontiguousarray(CB, dtype=np.float64)
+        s.MB = len(CBarr)
+        s.CB = _dp(CBarr)
+    return s, (Carr, CBarr)
 
 
 def _device_struct(device, stream, allocator):
@@ -256,10 +278,10 @@ def _device_struct(device, stream, allocator):
     return dev
 
 
-def relpic_create(grid, solver_C=None, precision=RELPIC_FP64, device=0, stream=None, allocator=None):
+def relpic_create(grid, solver_C=None, precision=RELPIC_FP64, device=0, stream=None, allocator=None, CB=None):
     L = load()
     g = _grid_struct(grid)
-    s, Carr = _solver_struct(solver_C)
+    s, Carr = _solver_struct(solver_C, CB=CB)
     dev = _device_struct(device, stream, allocator)
     h = ctypes.c_void_p()
     check(L.relpic_create(ctypes.byref(g), ctypes.byref(s), precision, ctypes.byref(dev), ctypes.byref(h)))
@@ -411,10 +433,13 @@ class SimOps:
                     nu_max=3):
         """(simulated E1 dx1/Q, k-space E1 dx1/q) at E1 points i1_rel around the particle in `slot`."""
         g = self.grid
-        C = getattr(self, "C", None) if C is None else C
+        if C is None:
+            C, CB = getattr(self, "C", None), getattr(self, "CB", None)
+        else:
+            CB = None
         kappa = g["dx"][0] / g["dt"] if kappa is None else kappa
         r = g["dx"][1] / g["dx"][0] if r is None else r
-        q, keep = _kspace_struct(C, kappa, r, beta, shape_order, tpow, nu_max)
+        q, keep = _kspace_struct(C, kappa, r, beta, shape_order, tpow, nu_max, CB)
         rel = np.ascontiguousarray(i1_rel, dtype=np.int32)
         sim = np.zeros(rel.size)
         th = np.zeros(rel.size)
@@ -439,15 +464,17 @@ class SimOps:
 class Sim(SimOps):
     """One simulation on one GPU.  grid: dict(ndim, n, dx, dt, window, window_speed)."""
 
-    def __init__(self, grid, C=None, precision="fp64", device=0, use_torch=True):
+    def __init__(self, grid, C=None, precision="fp64", device=0, use_torch=True, CB=None):
+        """C: the axial operator on E (and on B unless CB gives that one)."""
         self._init_geometry(grid, precision)
         self.C = None if C is None or len(C) <= 1 else np.array(C, dtype=np.float64)
+        self.CB = None if CB is None else np.array(CB, dtype=np.float64)
         self.allocator = None
         stream = None
         if use_torch:
             self.allocator, self.torch_stream = _torch_binding(device)
             stream = self.torch_stream.cuda_stream
-        self.h = relpic_create(grid, C, self.prec, device, stream, self.allocator)
+        self.h = relpic_create(grid, C, self.prec, device, stream, self.allocator, CB=CB)
 
     def close(self):
         if getattr(self, "h", None):
@@ -625,20 +652,26 @@ def adjoint_loss(adj, C):
     return _AdjointLoss.apply(C)
 
 
-def _kspace_struct(C, kappa, r, beta, order, tpow, nu_max):
+def _kspace_struct(C, kappa, r, beta, order, tpow, nu_max, CB=None):
     q = KSpaceParams()
     Carr = np.ascontiguousarray([1.0] if C is None else C, dtype=np.float64)
     q.M = Carr.size
     q.C = _dp(Carr)
     q.kappa, q.r, q.beta = float(kappa), float(r), float(beta)
     q.shape_order, q.tpow, q.nu_max = int(order), int(tpow), int(nu_max)
-    return q, Carr
+    CBarr = None
+    if CB is None:
+        q.MB, q.CB = 0, None
+    else:
+        CBarr = np.ascontiguousarray(CB, dtype=np.float64)
+        q.MB, q.CB = CBarr.size, _dp(CBarr)
+    return q, (Carr, CBarr)
 
 
-def kspace_e1(i1_rel, C=None, kappa=4.0, r=1.0, beta=1.0, order=2, tpow=0, nu_max=1, device=0):
+def kspace_e1(i1_rel, C=None, kappa=4.0, r=1.0, beta=1.0, order=2, tpow=0, nu_max=1, device=0, CB=None):
     """On-axis E1 dx1 / q of a streaming charge at E1 points i1_rel cells
     ahead of it (relpic_kspace_e1; FP64 quadrature on the GPU)."""
-    q, keep = _kspace_struct(C, kappa, r, beta, order, tpow, nu_max)
+    q, keep = _kspace_struct(C, kappa, r, beta, order, tpow, nu_max, CB)
     x = np.ascontiguousarray(np.atleast_1d(i1_rel), dtype=np.float64)
     out = np.zeros(x.size)
     dev = _device_struct(device, None, None)

@@ -170,3 +170,31 @@ print("STATUS", st, msg.decode())
     line = [ln for ln in r.stdout.splitlines() if ln.startswith("STATUS")][-1]
     assert line.split()[1] == str(relpic.RELPIC_ENOMEM), line
     assert "host allocation failed" in line
+
+
+def test_fit_operator_entry_point_targets():
+    # the library's App. C fit to [k1]_t^2 / [k]_Yee (the operator on E when
+    # the one on B is Yee) agrees with the oracle's fit to the same target
+    from oracle import fit
+    C, err = relpic.relpic_fit_operator(4.0, 16, relpic.RELPIC_FIT_E_WITH_YEE_B)
+    ref = fit.fit_coefficients(4.0, M=16, target=lambda k: fit.target_e_with_yee_b(k, 4.0), nq=2048)
+    assert np.abs(C - ref).max() < 1e-6 * np.abs(ref).max()
+    assert err < 1e-5
+    C0, _ = relpic.relpic_fit_operator(4.0, 16, relpic.RELPIC_FIT_TIME)
+    C1, _ = relpic.relpic_fit_coefficients(4.0, 16)
+    assert np.array_equal(C0, C1)
+    with pytest.raises(relpic.RelpicError):
+        relpic.relpic_fit_operator(4.0, 16, 7)
+
+
+def test_create_checks_courant_with_the_product_of_the_operators():
+    # Yee on B with the E operator fitted for it: [k]_E1 [k]_B1 = [k1]_t^2,
+    # whose maximum is (2/dx1)^2 sin^2(pi/(2 kappa)) -- stable where the
+    # same-operator customized solver at the same dt is too
+    C, _ = relpic.relpic_fit_operator(4.0, 16, relpic.RELPIC_FIT_E_WITH_YEE_B)
+    from oracle import dispersion
+    cn = dispersion.courant_number(None, (1.0, 1.0), 0.6, C1=C, CB1=(1.0,))
+    dt_lim = 0.6 / cn
+    with pytest.raises(relpic.RelpicError) as e:
+        relpic.relpic_create(_grid(dt=dt_lim * 1.001), solver_C=C, CB=[1.0])
+    assert e.value.status == relpic.RELPIC_EUNSTABLE
