@@ -233,6 +233,24 @@ relpic_status relpic_set_sort_interval(relpic_sim *sim, int64_t interval);
  * whether the fused update is in use. */
 relpic_status relpic_set_fused_fields(relpic_sim *sim, int enable, int *active);
 
+/* Self-consistent initial fields of the loaded charges streaming along x1 at
+ * beta (Sec. 2.1's fields in terms of the charge density, ultra-relativistic
+ * limit), so that a relativistic beam does not start in zero fields (which
+ * leaves a static image of opposite charge behind and radiates the sudden
+ * start).  For axial operators with [k]_E1 [k]_B1 = [beta k1]_t^2 the
+ * transverse field of every x1 slice is the lattice transverse Poisson field
+ * of that slice's charge (-lap_perp phi = rho, Yee x2/x3 differences,
+ * periodic), E_perp = -grad_perp phi, E1 = -(1 - beta^2) d1 phi, B = beta x E
+ * on B's lattice points (B3 at i1 + 1/2 from the E2 of i1 and i1 + 1).  rho
+ * is every species' charge at the current positions.  The part of a
+ * slice's charge that is uniform over x2 and x3 has no such field and is
+ * left out: the fields are exact for a beam whose slice charge is
+ * neutralized (e.g. by a co-moving, transversely uniform ballistic species
+ * of opposite charge), which is how a periodic transverse grid stands in for
+ * open space.  Overwrites E and B; only before the first step (else
+ * RELPIC_ESTATE); 0 < beta <= 1.  Synchronizing. */
+relpic_status relpic_init_beam_fields(relpic_sim *sim, double beta);
+
 /* FP64 diagnostics (synchronizing). */
 relpic_status relpic_diagnostics(relpic_sim *sim, relpic_diag *out);
 

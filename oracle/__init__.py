@@ -17,6 +17,8 @@ Contents
                          streaming along x1 on a periodic 2D grid (the
                          Sec. 2.1 response in terms of the density, every
                          wavenumber and aliased frequency on the lattice)
+  beam_init.py           self-consistent initial fields of charges streaming
+                         along x1 (Sec. 2.1, ultra-relativistic limit)
   dispersion.py          closed-form vacuum dispersion of the discrete
                          Maxwell operators (Eq. 4)
   field_loss.py          field loss around a moving bunch on the oracle's

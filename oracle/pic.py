@@ -105,6 +105,7 @@ class OracleSim:
         self.N = int(np.prod(self.n))
         self.dx = tuple(dx)
         self.dt = dt
+        self.window = bool(window)
 
     def close(self):
         if self._h:

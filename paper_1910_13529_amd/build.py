@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librelpic.so")
 SOURCES = ["capi.hip", "batch.hip", "adjoint.hip", "kernels_adjoint.hip", "kernels_field.hip", "kernels_leap.hip", "kernels_particle.hip", "kernels_batch.hip", "kernels_aux.hip",
-           "sort.hip", "kspace.hip", "solver_setup.cpp"]
+           "sort.hip", "kspace.hip", "init_fields.hip", "solver_setup.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics",

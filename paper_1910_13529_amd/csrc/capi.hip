@@ -59,6 +59,20 @@ void *dev_alloc(relpic_sim *s, size_t bytes) {
   return p;
 }
 
+// free one allocation made by dev_alloc (scratch of a set-up call)
+void dev_release(relpic_sim *s, void *p) {
+  if (!p) return;
+  for (size_t i = 0; i < s->owned.size(); ++i)
+    if (s->owned[i] == p) {
+      if (s->dev.free)
+        s->dev.free(p, s->dev.user);
+      else if (!s->dev.alloc)
+        (void)hipFree(p);
+      s->owned.erase(s->owned.begin() + (long)i);
+      return;
+    }
+}
+
 void dev_free_all(relpic_sim *s) {
   for (void *p : s->owned) {
     if (s->dev.free)

@@ -118,6 +118,7 @@ namespace relpic_host {
 using namespace relpic;
 
 void *dev_alloc(relpic_sim *s, size_t bytes);
+void dev_release(relpic_sim *s, void *p);
 void dev_free_all(relpic_sim *s);
 
 inline Geo make_geo(const relpic_sim *s) {

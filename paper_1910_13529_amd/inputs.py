@@ -170,3 +170,38 @@ def batch_bunch(run, npart=4096, sigma_cells=(5.0, 1.0)):
     u1 = sqrt(gamma^2 - 1), no transverse momentum."""
     center = (0.75 * run["n1"], run["n2"] // 2)
     return gaussian_bunch(run["seed"], npart, center, sigma_cells, run["gamma"], ndim=2, clip_sigmas=4.0)
+
+
+def config_drift3d(n=(256, 120, 120)):
+    """The paper's drifting-beam sample (Sec. 3.1): a tri-Gaussian electron
+    beam of 1 GeV (gamma = 1957), peak density n_b = 100 n_p, k_p sigma_z = 1,
+    k_p sigma_r = 0.5, no emittance or energy spread, in free space; dx1 = 0.05
+    c/omega_p, r = dx2/dx1 = 1, kappa = dx1/dt = 4, 8 particles per cell at the
+    peak; to omega_p t = 450 (36000 steps).  The window moves with the beam at
+    c; the beam centre sits at 0.6 n1 (the bunch, clipped at 4 sigma, fits with a margin)."""
+    dx = (0.05, 0.05, 0.05)
+    dt = dx[0] / 4.0
+    sig = (1.0, 0.5, 0.5)
+    n_peak = 100.0
+    ppc_peak = 8.0
+    vol = (2.0 * math.pi) ** 1.5 * sig[0] * sig[1] * sig[2]
+    dV = dx[0] * dx[1] * dx[2]
+    npart = int(round(n_peak * vol / (n_peak * dV / ppc_peak)))
+    return Workload("drift-3d", 3, tuple(n), dx, dt, True, "yee", 36000,
+                    {"npart": npart, "center": (0.6 * n[0], n[1] / 2, n[2] / 2), "sigma_phys": sig,
+                     "gamma": 1000.0 / 0.51099895, "espread": 0.0, "divergence": 0.0, "n_peak": n_peak})
+
+
+def transverse_partners(seed, cell, off, u, n):
+    """One partner per particle at the same x1, at a uniform random position
+    over the periodic transverse grid, with the same momentum: given the
+    opposite charge and no force (a ballistic species), the partners cancel
+    the transversely uniform part of every x1 slice's charge and current,
+    which a periodic transverse grid would otherwise turn into a sheet field
+    that open space does not have."""
+    rng = np.random.default_rng(seed)
+    X = cell + off
+    for d in range(1, X.shape[1]):
+        X[:, d] = rng.uniform(-0.5, n[d] - 0.5, X.shape[0])
+    c, o = split_positions(X)
+    return c, o, np.array(u, dtype=np.float64, copy=True)

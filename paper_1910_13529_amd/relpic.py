@@ -30,7 +30,8 @@ EXPORTS = (
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
     "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
     "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_self_force", "relpic_gather_particles", "relpic_e1_residual",
-    "relpic_kspace_e1_noalloc", "relpic_profile_read_species", "relpic_fit_operator", "relpic_last_error",
+    "relpic_kspace_e1_noalloc", "relpic_profile_read_species", "relpic_fit_operator", "relpic_init_beam_fields",
+    "relpic_last_error",
 )
 KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes", "leap")
 
@@ -168,6 +169,7 @@ def load():
     L.relpic_kspace_e1.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), I64, dp, dp]
     L.relpic_kspace_self_force.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), ctypes.c_int, dp]
     L.relpic_profile_read_species.argtypes = [P, ctypes.c_int, ctypes.POINTER(I64), dp]
+    L.relpic_init_beam_fields.argtypes = [P, D]
     L.relpic_kspace_e1_noalloc.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), I64, dp, dp]
     L.relpic_gather_particles.argtypes = [P, ctypes.c_int, I64, I64, dp]
     L.relpic_e1_residual.argtypes = [P, ctypes.c_int, I64, ctypes.POINTER(KSpaceParams), I64,
@@ -413,6 +415,10 @@ class SimOps:
         p = Profile()
         check(load().relpic_profile_read(self.h, ctypes.byref(p)))
         return {k: (int(p.launches[i]), float(p.total_ms[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def init_beam_fields(self, beta):
+        """Self-consistent fields of the loaded charges moving along x1 at beta (relpic_init_beam_fields)."""
+        check(load().relpic_init_beam_fields(self.h, float(beta)))
 
     def gather_particles(self, species, first=0, count=None):
         """E1..B3 (FP64, [count, 6]) at the particles of slots first .. first + count - 1."""
