@@ -98,10 +98,14 @@ def k2_integral(A, s, kind="yee", tpow=0):
 class KSpace:
     """On-axis E1 and self-force of a streaming point charge (2D)."""
 
-    def __init__(self, solver="yee", kappa=4.0, r=1.0, order=2, beta=1.0, C=None, tpow=0, nus=(-1, 0, 1), CB=None):
+    def __init__(self, solver="yee", kappa=4.0, r=1.0, order=2, beta=1.0, C=None, tpow=0, nus=(-1, 0, 1), CB=None,
+                 filt=None):
         """solver names the operator on E (symbol [k]_E1); CB, when given,
         the customized operator on B ([k]_B1, Sec. 3 allows them to differ),
-        else [k]_B1 = [k]_E1."""
+        else [k]_B1 = [k]_E1.  filt = (n, c): the current is smoothed along
+        x1 by n binomial (1, 2, 1)/4 passes and one compensator pass of
+        symbol 1 + c sin^2(k1 dx1/2), so the source carries the factor
+        cos^(2n)(khat) (1 + c sin^2 khat) of the grid wavenumber khat."""
         self.solver = solver
         self.kappa = float(kappa)
         self.r = float(r)
@@ -109,9 +113,16 @@ class KSpace:
         self.beta = float(beta)
         self.sigma1 = axial_symbol(solver, C, kappa)
         self.sigmaB = self.sigma1 if CB is None else axial_symbol("custom", CB, kappa)
+        self.filt = filt
         self.kind = transverse_kind(solver)
         self.tpow = tpow
         self.nus = tuple(nus)
+
+    def filter_factor(self, kh):
+        if self.filt is None:
+            return 1.0
+        n, c = self.filt
+        return math.cos(kh) ** (2 * n) * (1.0 + c * math.sin(kh) ** 2)
 
     # X dx1^2/4 on zone nu
     def xhat(self, kh, nu):
@@ -171,6 +182,7 @@ class KSpace:
                     if s1 == 0.0:
                         return 0.0
                     val = (1j / s1) * float(shape_hat(kh + nu * np.pi, self.order)) * self.ihat(kh, nu)
+                    val = val * self.filter_factor(kh)
                     return (val * complex(math.cos(ph * kh), math.sin(ph * kh))).real
                 tot += self._integrate(fn, nu)
             out.append(-tot / (2.0 * np.pi ** 2 * self.r))
@@ -187,7 +199,7 @@ class KSpace:
                 if s1 == 0.0:
                     return 0.0
                 val = (1j / s1) * float(shape_hat(kh, go)) * float(shape_hat(kh + nu * np.pi, self.order)) * self.ihat(kh, nu)
-                return val.real
+                return (val * self.filter_factor(kh)).real
             tot += self._integrate(fn, nu)
         return -tot / (2.0 * np.pi ** 2 * self.r)
 

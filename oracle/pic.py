@@ -65,6 +65,8 @@ def lib():
         L.orc_deposit_one.argtypes = [P, D, dp, dp, D]
         L.orc_correct_j1.argtypes = [P]
         L.orc_set_injection.argtypes = [P, ip, D, D, D, ctypes.c_uint64]
+        L.orc_set_filter.argtypes = [P, ctypes.c_int, D]
+        L.orc_filter_j.argtypes = [P]
         L.orc_max_threads.restype = ctypes.c_int
         L.orc_max_threads.argtypes = []
         L.orc_set_threads.argtypes = [ctypes.c_int]
@@ -128,6 +130,14 @@ class OracleSim:
     def set_injection(self, ppc, Q, qm, uth, seed):
         p = (ctypes.c_int * 3)(*(list(ppc) + [1] * (3 - len(ppc))))
         lib().orc_set_injection(self._h, p, float(Q), float(qm), float(uth), ctypes.c_uint64(seed))
+
+    def set_filter(self, npass, comp):
+        """Smooth the current along x1 every step: npass binomial passes and a
+        compensator of symbol 1 + comp sin^2(k dx1/2) (npass = 0: off)."""
+        lib().orc_set_filter(self._h, int(npass), float(comp))
+
+    def filter_j(self):
+        lib().orc_filter_j(self._h)
 
     def step(self, nsteps=1):
         lib().orc_step(self._h, int(nsteps))

@@ -83,6 +83,9 @@ typedef struct {
   double *g;
   long ng;
   int g_circular;
+  /* current smoothing along x1 (0 passes: off) */
+  int filt_npass;
+  double filt_comp;
   /* plasma injection at window shifts */
   int inj_on;
   int inj_ppc[3];
@@ -492,6 +495,53 @@ static void correct_j1(orc_sim *s) {
   }
 }
 
+/* Smoothing of the current along x1: npass binomial passes (1, 2, 1)/4 and
+ * one compensator pass (-c/4, 1 + c/2, -c/4), symbol
+ * cos^(2 npass)(k dx1/2) (1 + c sin^2(k dx1/2)).  x1 is periodic, or zero
+ * beyond the moving window.  Every component gets the same x1 filter, which
+ * commutes with the divergence, so Gauss's law holds for the filtered
+ * density. */
+static void filter_line(double *f, double *tmp, long n1, int window, double a, double b) {
+  for (long i = 0; i < n1; ++i) {
+    double lo, hi;
+    if (window) {
+      lo = (i > 0) ? f[i - 1] : 0.0;
+      hi = (i < n1 - 1) ? f[i + 1] : 0.0;
+    } else {
+      lo = f[wrapl(i - 1, n1)];
+      hi = f[wrapl(i + 1, n1)];
+    }
+    tmp[i] = a * lo + b * f[i] + a * hi;
+  }
+  for (long i = 0; i < n1; ++i) f[i] = tmp[i];
+}
+
+static void filter_j(orc_sim *s) {
+  long n1 = s->n[0];
+  long nlines = s->n[1] * s->n[2];
+#pragma omp parallel
+  {
+    double *tmp = (double *)malloc(sizeof(double) * n1);
+#pragma omp for schedule(static)
+    for (long ln = 0; ln < nlines; ++ln)
+      for (int c = J1; c <= J3; ++c) {
+        double *f = &s->F[c][n1 * ln];
+        for (int p = 0; p < s->filt_npass; ++p) filter_line(f, tmp, n1, s->window, 0.25, 0.5);
+        filter_line(f, tmp, n1, s->window, -0.25 * s->filt_comp, 1.0 + 0.5 * s->filt_comp);
+      }
+    free(tmp);
+  }
+}
+
+void orc_set_filter(void *h, int npass, double comp) {
+  orc_sim *s = (orc_sim *)h;
+  s->filt_npass = npass;
+  s->filt_comp = comp;
+}
+
+/* apply the current filter once (unit tests) */
+void orc_filter_j(void *h) { filter_j((orc_sim *)h); }
+
 static void field_half_b(orc_sim *s, double h) {
 #pragma omp parallel for collapse(2) schedule(static)
   for (long k = 0; k < s->n[2]; ++k)
@@ -640,6 +690,7 @@ void orc_step(void *h, long nsteps) {
     free(xn);
     free(un);
     if (s->correct) correct_j1(s);
+    if (s->filt_npass > 0) filter_j(s);
     field_half_b(s, 0.5 * s->dt);
     field_e(s);
     field_half_b(s, 0.5 * s->dt);

@@ -166,3 +166,26 @@ def test_continuous_limit_2d():
         assert abs(e0 / cont - 1.0) < 2e-2
         errs.append(abs(kall.e1([ip])[0] / cont - 1.0))
     assert errs[0] < 3e-3 and errs[1] < errs[0] / 3.0  # converges like (dx/xi)^2
+
+
+# ---- the 5-pass filter (Sec. 2.2, 2.3, 3; Table 2) --------------------------------
+
+FIVE_PASS = (4, 5.0)  # four (1, 2, 1)/4 passes and a compensator 1 + 5 sin^2(k dx1/2), along x1
+
+
+def test_five_pass_filter_reading_reproduces_all_printed_self_forces():
+    # The paper prints F1 with a "5 pass filter" for three solvers without
+    # defining it.  Four binomial passes and one compensator pass of symbol
+    # 1 + 5 sin^2(k1 dx1/2), applied to the current along x1, reproduces all
+    # three printed values: Yee -0.031 (Sec. 2.2), spectral 6.5e-6 (Sec. 2.3),
+    # customized 3.3e-8 (Sec. 3, Table 2; with the factor kappa of reading 3).
+    yee = kspace.KSpace("yee", 4.0, 1.0, order=2, nus=(0,), filt=FIVE_PASS).self_force()
+    spe = kspace.KSpace("spectral", 4.0, 1.0, order=2, nus=(-1, 1), filt=FIVE_PASS).self_force()
+    cus = kspace.KSpace("exact", 4.0, 1.0, order=2, nus=(-1, 1), filt=FIVE_PASS).self_force()
+    assert sig2(yee) == -0.031
+    assert sig2(spe) == 6.5e-6
+    assert sig2(4.0 * cus) == 3.3e-8
+    # the compensator that only flattens the k^2 term (c = n = 4) misses them all
+    alt = (4, 4.0)
+    assert sig2(kspace.KSpace("yee", 4.0, 1.0, order=2, nus=(0,), filt=alt).self_force()) != -0.031
+    assert sig2(kspace.KSpace("spectral", 4.0, 1.0, order=2, nus=(-1, 1), filt=alt).self_force()) != 6.5e-6
