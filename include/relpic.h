@@ -233,6 +233,21 @@ relpic_status relpic_set_sort_interval(relpic_sim *sim, int64_t interval);
  * whether the fused update is in use. */
 relpic_status relpic_set_fused_fields(relpic_sim *sim, int enable, int *active);
 
+/* Current filter (f1): the 5-pass low-pass filter with which Secs. 2.2-3 and
+ * Table 2 quote the self-force F1 (quadratic shape plus filter).  Reading:
+ * npass passes of the binomial (1/4, 1/2, 1/4) along x1 and one compensating
+ * pass (-c/4, 1 + c/2, -c/4), symbol cos^(2 npass)(k1 dx1/2) (1 + c
+ * sin^2(k1 dx1/2)); npass = 4, c = 5 reproduces all three printed filtered
+ * self-forces.  Applied every step to J1 (after the J1 correction), J2 and
+ * J3 on each x1 line the particles deposited on, before the E update; a line
+ * is zero beyond a moving window's ends and wraps when x1 is periodic.  The
+ * same filter is applied to the density of relpic_diagnostics, so that
+ * gauss_max measures Gauss's law for the filtered density, which the filtered
+ * current conserves.  npass = 0 turns the filter off (the default); npass
+ * in 0..16, c finite when npass > 0, n1 at most 4096 (RELPIC_EINVAL
+ * otherwise).  Single runs only: batches and the adjoint run unfiltered. */
+relpic_status relpic_set_current_filter(relpic_sim *sim, int npass, double comp);
+
 /* Self-consistent initial fields of the loaded charges streaming along x1 at
  * beta (Sec. 2.1's fields in terms of the charge density, ultra-relativistic
  * limit), so that a relativistic beam does not start in zero fields (which
@@ -265,8 +280,8 @@ relpic_status relpic_correction_halfwidth(relpic_sim *sim, int *halfwidth);
  * 0 push+deposit, 1 J1 correction, 2 B update (curl E), 3 E update (curl B),
  * 4 window shift and injection, 5 current added to E inside the deposit box
  * (or, after a fused update, cleared there), 6 merge of the push workgroups'
- * deposit boxes, 7 fused E and B update. */
-#define RELPIC_NUM_KERNEL_CLASSES 8
+ * deposit boxes, 7 fused E and B update, 8 current filter. */
+#define RELPIC_NUM_KERNEL_CLASSES 9
 typedef struct {
   int64_t launches[RELPIC_NUM_KERNEL_CLASSES];
   double total_ms[RELPIC_NUM_KERNEL_CLASSES];

@@ -203,6 +203,12 @@ void curl_e(relpic_sim *s, const Geo &g, Real *const Bin[3], Real *const Bout[3]
   launch_curl_e<Real>(s->ndim, g, f, Bin, Bout, axial_scaled<Real>(s, c), h2, h3, s->st);
 }
 
+// x1 widening of the deposit box that holds the current the E update adds:
+// the J1 correction's half-width and the filter's reach
+int current_pad(const relpic_sim *s) {
+  return (s->correct ? s->ng : 0) + (s->filt_npass > 0 ? s->filt_npass + 1 : 0);
+}
+
 template <typename Real>
 relpic_status do_steps(relpic_sim *s, long long nsteps) {
   if (nsteps == 0) return RELPIC_OK;
@@ -281,6 +287,13 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       launch_jcorr<Real>(g, f.J1, f.J1c, (const Real *)s->taps, s->ng, box, s->st);
       J1src = f.J1c;
     }
+    if (s->filt_npass > 0) {
+      // after the correction, on the current the E update takes
+      ProfScope ps(s, 8);
+      launch_filter_rows<Real>(g, const_cast<Real *>(J1src), f.J2, f.J3, box, s->correct ? s->ng : 0, s->filt_npass,
+                               (Real)(-0.25 * s->filt_comp), (Real)(1.0 + 0.5 * s->filt_comp), s->st);
+    }
+    const int jpad = current_pad(s);
     // E^{n+1} = E^n + dt (curl- B^{n+1/2} - J^{n+1/2})
     f.B1 = Bb[0];
     f.B2 = Bb[1];
@@ -295,12 +308,12 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       Real *Eout[3] = {(Real *)s->Ex[0], (Real *)s->Ex[1], (Real *)s->Ex[2]};
       {
         ProfScope ps(s, 7);
-        launch_leap<Real>(g, Ein, Eout, Bb, Ba, J1src, f.J2, f.J3, box, s->correct ? s->ng : 0, (Real)dt, axE, e2, e3,
+        launch_leap<Real>(g, Ein, Eout, Bb, Ba, J1src, f.J2, f.J3, box, jpad, (Real)dt, axE, e2, e3,
                           axial_scaled<Real>(s, fb), (Real)(fb / s->dx[1]), (Real)(fb / s->dx[2]), s->st);
       }
       {
         ProfScope ps(s, 5);
-        launch_clear_j<Real>(g, f, box, s->correct ? s->ng : 0, next, s->st);
+        launch_clear_j<Real>(g, f, box, jpad, next, s->st);
       }
       for (int d = 0; d < 3; ++d) std::swap(s->F[d], s->Ex[d]);
       b_ahead = !last;
@@ -312,7 +325,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       }
       {
         ProfScope ps(s, 5);
-        launch_add_j<Real>(g, f, J1src, (Real)dt, box, s->correct ? s->ng : 0, next, s->st);
+        launch_add_j<Real>(g, f, J1src, (Real)dt, box, jpad, next, s->st);
       }
     }
     swapB();
@@ -378,6 +391,9 @@ relpic_status do_diag(relpic_sim *s, relpic_diag *out) {
                               (unsigned long long *)(s->dbuf + 5), s->st);
     launch_diag_rho<Real>(s->ndim, g, parts<Real>(sp), sp.Q / dV, s->rho, s->st);
   }
+  if (s->filt_npass > 0)  // Gauss's law holds for the filtered density
+    launch_filter_rows<double>(g, s->rho, nullptr, nullptr, nullptr, 0, s->filt_npass, -0.25 * s->filt_comp,
+                               1.0 + 0.5 * s->filt_comp, s->st);
   Axial<double> c1{};
   c1.M = s->M;
   for (int l = 0; l < s->M; ++l) c1.c[l] = s->CB[l] / s->dx[0];  // Gauss: the operator on B
@@ -1077,6 +1093,19 @@ relpic_status relpic_set_sort_interval(relpic_sim *s, int64_t interval) {
     if (relpic_status r = check_sim(s)) return r;
     if (interval < 0) return fail(RELPIC_EINVAL, "sort interval must be >= 0");
     s->sort_interval = interval;
+    return RELPIC_OK;
+  });
+}
+
+relpic_status relpic_set_current_filter(relpic_sim *s, int npass, double comp) {
+  return guarded("set_current_filter", [&]() -> relpic_status {
+    if (relpic_status r = check_sim(s)) return r;
+    if (npass < 0 || npass > 16) return fail(RELPIC_EINVAL, "current filter: npass must be in 0..16");
+    if (npass > 0 && !std::isfinite(comp)) return fail(RELPIC_EINVAL, "current filter: compensator must be finite");
+    if (npass > 0 && s->n[0] > kFilterMaxLine)
+      return fail(RELPIC_EINVAL, "current filter: n1 exceeds the longest line it stages (4096)");
+    s->filt_npass = npass;
+    s->filt_comp = npass > 0 ? comp : 0.0;
     return RELPIC_OK;
   });
 }

@@ -89,6 +89,8 @@ struct relpic_sim {
   long long blockbox_n = 0;
   void *taps = nullptr;
   int ng = 0;
+  int filt_npass = 0;      // current filter: binomial passes along x1 (0: off)
+  double filt_comp = 0.0;  // and the compensator's c: (-c/4, 1 + c/2, -c/4)
   std::vector<Species> sp;
   long long step = 0, ws = 0;
   long long sort_interval = 25;  // re-sort every this many steps (0: only after loads)

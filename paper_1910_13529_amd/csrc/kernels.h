@@ -29,6 +29,14 @@ void launch_add_j(const Geo &g, const Fields<Real> &f, const Real *J1src, Real d
 template <typename Real>
 void launch_jcorr(const Geo &g, const Real *J1, Real *J1c, const Real *taps, int ng, const JBox *box,
                   hipStream_t st);
+// Current filter along x1, in place on each non-null array: npass passes of
+// (1/4, 1/2, 1/4) and one of (ca, cb, ca), over the x1 lines of the box
+// (box null: every line of the grid).  Input: the box's x1 range widened by
+// in_pad, taken as zero outside it; output: that range widened by npass + 1.
+constexpr int kFilterMaxLine = 4096;  // longest x1 line (n1) the filter stages in LDS
+template <typename Real>
+void launch_filter_rows(const Geo &g, Real *A0, Real *A1, Real *A2, const JBox *box, int in_pad, int npass, Real ca,
+                        Real cb, hipStream_t st);
 // new leading slab after a window shift: E = 0, B (f.B*, at n + 1/2) such
 // that B^{n+1} = 0 there, other B buffer Bx cleared
 template <typename Real>

@@ -328,6 +328,81 @@ __global__ __launch_bounds__(256) void k_jcorr_rows(Geo g, const Real *J1, Real 
   }
 }
 
+// Current filter (the 5-pass smoothing with which Secs. 2.2-3 quote the
+// filtered self-force): on each x1 line of the box, npass passes of the binomial
+// (1/4, 1/2, 1/4) and then one compensating pass (ca, cb, ca), in place.  A
+// pass treats the line as zero beyond a moving window's ends and wraps on a
+// periodic line.  The input is the box's x1 range widened by in_pad (cells
+// outside it are taken as zero whatever the buffer holds there, e.g. stale
+// J1c); the output, written back, is that range widened by npass + 1, which
+// holds the whole support of the result.  One workgroup per (line,
+// component): the line is staged in LDS, and a pass reads every cell's three
+// operands into registers, waits, and writes the results back.
+constexpr int kFilterPer = kFilterMaxLine / 256;
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_filter_rows(Geo g, Real *A0, Real *A1, Real *A2, const JBox *box,
+                                                     int in_pad, int npass, Real ca, Real cb) {
+  extern __shared__ __align__(16) unsigned char fl_lds[];
+  Real *line = reinterpret_cast<Real *>(fl_lds);
+  JBox b;
+  if (box) {
+    b = *box;
+  } else {
+    b.lo[0] = b.lo[1] = b.lo[2] = 0;
+    b.hi[0] = g.n1 - 1;
+    b.hi[1] = g.n2 - 1;
+    b.hi[2] = g.n3 - 1;
+  }
+  int va, vb, oa, ob;
+  if (!box_x1(g, b, in_pad, va, vb)) return;  // whole workgroup
+  box_x1(g, b, in_pad + npass + 1, oa, ob);
+  const int L = ob - oa + 1;                  // at most n1 <= kFilterMaxLine
+  const bool wrap = !g.window && L >= g.n1;   // a whole periodic line (oa == 0)
+  const int vw = vb - va;
+  const long long w2 = b.hi[1] - b.lo[1] + 1, rows = w2 * (b.hi[2] - b.lo[2] + 1);
+  for (long long r = blockIdx.x; r < 3 * rows; r += gridDim.x) {
+    const int comp = (int)(r / rows);
+    Real *A = comp == 0 ? A0 : (comp == 1 ? A1 : A2);
+    if (!A) continue;  // uniform over the workgroup
+    const long long rr = r - comp * rows;
+    const int i2 = b.lo[1] + (int)(rr % w2), i3 = b.lo[2] + (int)(rr / w2);
+    const long long row = (long long)g.n1 * (i2 + (long long)g.n2 * i3);
+    for (int t = threadIdx.x; t < L; t += blockDim.x) {
+      const int l = oa + t;
+      int d = l - va;
+      if (wrap) {
+        d %= g.n1;
+        d = d < 0 ? d + g.n1 : d;
+      }
+      line[t] = (d >= 0 && d <= vw) ? A[row + col_of(g, l)] : Real(0);
+    }
+    __syncthreads();
+    for (int p = 0; p <= npass; ++p) {
+      const Real a = p < npass ? Real(0.25) : ca, c = p < npass ? Real(0.5) : cb;
+      Real v[kFilterPer];
+#pragma unroll
+      for (int k = 0; k < kFilterPer; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        if (t < L) {
+          const Real lo = t > 0 ? line[t - 1] : (wrap ? line[L - 1] : Real(0));
+          const Real hi = t < L - 1 ? line[t + 1] : (wrap ? line[0] : Real(0));
+          v[k] = a * lo + c * line[t] + a * hi;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kFilterPer; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        if (t < L) line[t] = v[k];
+      }
+      __syncthreads();
+    }
+    for (int t = threadIdx.x; t < L; t += blockDim.x) A[row + col_of(g, oa + t)] = line[t];
+    __syncthreads();
+  }
+}
+
 // Window shift after step n, with g the geometry before the shift.  The
 // step's second B half step, B^{n+1} = B^{n+1/2} - (dt/2) curl+ E^{n+1}, is
 // taken on the old window, and the window then moves: the back slab (window
@@ -558,6 +633,13 @@ void launch_shift_fused(const Geo &g, Real *const E[3], Real *const X[3], Real *
                                                                     Y[2], col, ch, f2m1);
 }
 
+template <typename Real>
+void launch_filter_rows(const Geo &g, Real *A0, Real *A1, Real *A2, const JBox *box, int in_pad, int npass, Real ca,
+                        Real cb, hipStream_t st) {
+  const size_t lds = sizeof(Real) * (size_t)g.n1;  // the widened range is at most one line
+  k_filter_rows<Real><<<4096, 256, lds, st>>>(g, A0, A1, A2, box, in_pad, npass, ca, cb);
+}
+
 void launch_reset_box(JBox *b, hipStream_t st) { k_reset_box<<<1, 64, 0, st>>>(b); }
 
 #define RELPIC_INST_FIELD(Real)                                                                                   \
@@ -572,6 +654,8 @@ void launch_reset_box(JBox *b, hipStream_t st) { k_reset_box<<<1, 64, 0, st>>>(b
                                          const Axial<Real> &, Real, hipStream_t);                                 \
   template void launch_jcorr<Real>(const Geo &, const Real *, Real *, const Real *, int, const JBox *,            \
                                    hipStream_t);                                                                  \
+  template void launch_filter_rows<Real>(const Geo &, Real *, Real *, Real *, const JBox *, int, int, Real, Real,  \
+                                         hipStream_t);                                                            \
   template void launch_new_slab<Real>(const Geo &, const Fields<Real> &, Real *const[3], int, const Axial<Real> &, \
                                       hipStream_t);
 

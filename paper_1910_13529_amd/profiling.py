@@ -28,6 +28,7 @@ CLASS_OF = (
     ("k_batch_jcorr", "batch_jcorr"), ("k_batch_add_j", "batch_add_j"), ("k_batch_merge", "batch_merge"),
     ("k_merge_boxes", "merge_boxes"), ("k_push_deposit", "push_deposit"), ("k_curl_e", "curl_e"), ("k_curl_b", "curl_b"),
     ("k_jcorr", "jcorr"), ("k_add_j", "add_j"), ("k_clear_j", "add_j"), ("k_new_slab", "window"), ("k_shift_fused", "window"), ("k_leap", "leap"),
+    ("k_filter_rows", "filter"),
 )
 
 

@@ -25,7 +25,7 @@ EXPORTS = (
     "relpic_set_injection", "relpic_set_background_rho", "relpic_step", "relpic_sync", "relpic_read_field",
     "relpic_write_field", "relpic_field_device_ptr", "relpic_read_particles", "relpic_diagnostics",
     "relpic_get_step", "relpic_correction_halfwidth", "relpic_profile_enable", "relpic_profile_read",
-    "relpic_sort_particles", "relpic_set_sort_interval", "relpic_set_fused_fields", "relpic_batch_create", "relpic_batch_destroy",
+    "relpic_sort_particles", "relpic_set_sort_interval", "relpic_set_fused_fields", "relpic_set_current_filter", "relpic_batch_create", "relpic_batch_destroy",
     "relpic_batch_run", "relpic_batch_step", "relpic_batch_sync", "relpic_batch_set_graph_steps",
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
     "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
@@ -33,7 +33,7 @@ EXPORTS = (
     "relpic_kspace_e1_noalloc", "relpic_profile_read_species", "relpic_fit_operator", "relpic_init_beam_fields",
     "relpic_last_error",
 )
-KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes", "leap")
+KERNEL_CLASSES = ("push_deposit", "jcorr", "curl_e", "curl_b", "window", "add_j", "merge_boxes", "leap", "filter")
 
 
 class RelpicError(RuntimeError):
@@ -143,6 +143,7 @@ def load():
     L.relpic_sort_particles.argtypes = [P]
     L.relpic_set_sort_interval.argtypes = [P, I64]
     L.relpic_set_fused_fields.argtypes = [P, ctypes.c_int, ip]
+    L.relpic_set_current_filter.argtypes = [P, ctypes.c_int, D]
     L.relpic_diagnostics.argtypes = [P, ctypes.POINTER(Diag)]
     L.relpic_get_step.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.relpic_correction_halfwidth.argtypes = [P, ip]
@@ -390,6 +391,10 @@ class SimOps:
 
     def set_sort_interval(self, n):
         check(load().relpic_set_sort_interval(self.h, int(n)))
+
+    def set_current_filter(self, npass, comp):
+        """Current filter along x1: npass binomial passes and a compensator with c = comp (npass 0: off)."""
+        check(load().relpic_set_current_filter(self.h, int(npass), float(comp)))
 
     def set_fused_fields(self, enable):
         """Fused E and B update (3D grids that qualify); returns whether it is active."""
