@@ -189,3 +189,125 @@ def test_five_pass_filter_reading_reproduces_all_printed_self_forces():
     alt = (4, 4.0)
     assert sig2(kspace.KSpace("yee", 4.0, 1.0, order=2, nus=(0,), filt=alt).self_force()) != -0.031
     assert sig2(kspace.KSpace("spectral", 4.0, 1.0, order=2, nus=(-1, 1), filt=alt).self_force()) != 6.5e-6
+
+
+# ---- off-axis fields and the 3D integral (Eq. 9 with the x2 and x3 integrals) ----
+
+@pytest.mark.parametrize("tpow", [0, 1, 2])
+def test_k2_integral_n_on_axis_is_app_d(tpow):
+    for A in (-3.0, -0.2, 0.1, 0.5, 0.9, 1.5, 7.0):
+        for s in (1.0, -1.0):
+            a = kspace.k2_integral(A, s, "yee", tpow)
+            b = kspace.k2_integral_n(A, s, tpow, 0)
+            assert abs(a - b) < 1e-13 * max(1.0, abs(a))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5])
+@pytest.mark.parametrize("tpow", [0, 1, 2])
+def test_k2_integral_n_off_axis_no_pole(n, tpow):
+    for A in (-3.0, -0.2, 1.5, 7.0):
+        f = lambda t: (1 - 0.5 * math.sin(t) ** 2) ** tpow * A * math.cos(2 * n * t) / (A - math.sin(t) ** 2)
+        num, _ = integrate.quad(f, -math.pi / 2, math.pi / 2, epsabs=1e-14, limit=200)
+        assert abs(kspace.k2_integral_n(A, 1.0, tpow, n) - num) < 1e-12
+
+
+@pytest.mark.parametrize("A", [0.2, 0.7])
+@pytest.mark.parametrize("s", [1.0, -1.0])
+def test_k2_integral_n_off_axis_causal_pole(A, s):
+    # finite eps, then eps -> 0, at transverse node 3 with the quadratic deposit factor
+    eps, n = 1e-4, 3
+    f = lambda t: (1 - 0.5 * math.sin(t) ** 2) * A * math.cos(2 * n * t) / (A + 1j * eps * s - math.sin(t) ** 2)
+    pole = math.asin(math.sqrt(A))
+    pts = sorted([-pole, pole] + [sg * pole + d * eps for sg in (-1, 1) for d in (-30, -3, 3, 30)])
+    re, _ = integrate.quad(lambda t: f(t).real, -math.pi / 2, math.pi / 2, points=pts, limit=2000, epsabs=1e-10)
+    im, _ = integrate.quad(lambda t: f(t).imag, -math.pi / 2, math.pi / 2, points=pts, limit=2000, epsabs=1e-10)
+    exact = kspace.k2_integral_n(A, s, 1, n)
+    assert abs(complex(re, im) - exact) < 2e-3 * abs(exact)
+
+
+@pytest.mark.parametrize("tpow", [0, 2])
+def test_k2_integral_n_transverse_sum_rule(tpow):
+    # summed over every transverse node the field is the x2-uniform (1D) one:
+    # sum_n cos(2 n theta) = pi delta(theta) on a period, so sum_n Ihat_n = pi T(0) = pi
+    for A in (-2.0, -0.4, 1.8, 6.0):
+        tot = sum(kspace.k2_integral_n(A, 1.0, tpow, n) for n in range(-200, 201))
+        assert abs(tot - math.pi) < 1e-12
+
+
+def test_off_axis_space_charge_field_is_antisymmetric_and_decays():
+    ks = kspace.KSpace("yee", 2.0, 1.0, order=2, beta=0.5, nus=(0,))
+    for i2 in (1, 4):
+        e = ks.e1(np.arange(-5, 5), i2=i2)
+        assert np.abs(e + e[::-1]).max() < 1e-12 * np.abs(e).max()
+    assert abs(ks.e1([2], i2=6)[0]) < abs(ks.e1([2], i2=1)[0])
+
+
+def test_continuous_limit_2d_off_axis():
+    # E1 = lambda/(2 pi) gamma xi / (gamma^2 xi^2 + x2^2) off axis too (reading 4's units)
+    gamma = 1.2
+    beta = math.sqrt(1 - 1 / gamma ** 2)
+    ks = kspace.KSpace("yee", 2.0, 1.0, order=2, beta=beta, nus=(-2, -1, 0, 1, 2))
+    for ip, i2 in ((15, 10), (20, 25)):
+        xi = ip + 0.5
+        cont = gamma * xi / (2 * math.pi * (gamma ** 2 * xi ** 2 + i2 ** 2))
+        assert abs(ks.e1([ip], i2=i2)[0] / cont - 1.0) < 1e-2
+
+
+@pytest.mark.parametrize("kh,i2,i3", [(0.3, 0, 0), (1.0, 0, 0), (0.7, 2, 1), (1.2, 1, 3)])
+def test_3d_transverse_integral_matches_double_quadrature(kh, i2, i3):
+    # no pole (beta = 0.5, nu1 = 0: X < 0): the x3 closed form and the x2
+    # quadrature against a plain double quadrature of the x2, x3 integral
+    k3 = kspace.KSpace3D("yee", 2.0, 1.3, 0.8, order=2, beta=0.5, tpow=1, nus=(0,))
+    X = k3.xhat(kh, 0)
+    assert X < 0
+    T = lambda t: 1 - 0.5 * math.sin(t) ** 2
+    f = lambda t3, t2: (T(t2) * T(t3) * X * math.cos(2 * i2 * t2) * math.cos(2 * i3 * t3)
+                        / (X - math.sin(t2) ** 2 / 1.3 ** 2 - math.sin(t3) ** 2 / 0.8 ** 2))
+    num = integrate.dblquad(f, -math.pi / 2, math.pi / 2, -math.pi / 2, math.pi / 2, epsabs=1e-13)[0]
+    v = k3.i3(kh, 0, i2, i3)
+    assert abs(v.imag) < 1e-14 and abs(v.real - num) < 1e-11 * max(1.0, abs(num))
+
+
+@pytest.mark.parametrize("s", [1.0, -1.0])
+def test_3d_transverse_integral_causal_pole(s):
+    # X > 0 (a Cerenkov pole inside the x2, x3 zone): the nested closed form
+    # against a double quadrature at X + i eps s, eps -> 0
+    k3 = kspace.KSpace3D("yee", 4.0, 1.0, 1.0, order=2, beta=1.0, nus=(0,))
+    kh = 0.9
+    X = k3.xhat(kh, 0)
+    assert 0 < X < 1
+    eps = 2e-3
+    g = lambda t3, t2: X / (X + 1j * eps * s - math.sin(t2) ** 2 - math.sin(t3) ** 2)
+    re = integrate.dblquad(lambda a, b: g(a, b).real, 0, math.pi / 2, 0, math.pi / 2, epsabs=1e-9)[0] * 4
+    im = integrate.dblquad(lambda a, b: g(a, b).imag, 0, math.pi / 2, 0, math.pi / 2, epsabs=1e-9)[0] * 4
+    # X is even in khat and s = sign(sin(beta k1 dt)) odd: -khat carries the other prescription
+    exact = k3.i3(kh, 0, 0, 0) if s == k3.sgn(kh, 0) else k3.i3(-kh, 0, 0, 0)
+    assert abs(complex(re, im) - exact) < 2e-2 * abs(exact)
+    assert np.sign(exact.imag) == -s
+
+
+def test_3d_transverse_sum_rule_gives_the_2d_integrand():
+    # summed over the x3 nodes the 3D transverse integral is pi times the 2D one (x2 only)
+    k3 = kspace.KSpace3D("yee", 2.0, 1.3, 0.8, order=2, beta=0.5, tpow=2, nus=(0,))
+    for kh, i2 in ((0.8, 0), (1.3, 2)):
+        X = k3.xhat(kh, 0)
+        tot = sum(k3.i3(kh, 0, i2, i3) for i3 in range(-40, 41))
+        ref = math.pi * kspace.k2_integral_n(1.3 ** 2 * X, 1.0, 2, i2)
+        assert abs(tot - ref) < 1e-10 * abs(ref)
+
+
+def test_3d_static_limit_is_coulomb():
+    # beta -> 0 with the aliased zones: the lattice field of a point charge
+    # approaches q/(4 pi xi^2) on axis, with an error falling like (dx/xi)^2
+    k3 = kspace.KSpace3D("yee", 2.0, 1.0, 1.0, order=2, beta=1e-3, nus=tuple(range(-4, 5)))
+    err = [abs(k3.e1([ip])[0] * 4 * math.pi * (ip + 0.5) ** 2 - 1.0) for ip in (8, 16)]
+    assert err[0] < 0.04 and err[1] < err[0] / 3.0
+    # cells that are not cubes (dx2 != dx3 != dx1): the same limit in units of dx1
+    k3 = kspace.KSpace3D("yee", 2.0, 1.0, 2.0, order=2, beta=1e-3, nus=tuple(range(-4, 5)))
+    assert abs(k3.e1([16])[0] * 4 * math.pi * 16.5 ** 2 - 1.0) < 0.02
+
+
+def test_3d_space_charge_field_is_antisymmetric():
+    k3 = kspace.KSpace3D("yee", 2.0, 1.0, 1.0, order=2, beta=0.5, nus=(0,))
+    e = k3.e1([-3, -1, 0, 2], i2=1, i3=2)
+    assert abs(e[0] + e[3]) < 1e-11 * abs(e[0]) and abs(e[1] + e[2]) < 1e-11 * abs(e[1])
