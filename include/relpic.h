@@ -458,6 +458,21 @@ relpic_status relpic_kspace_e1(const relpic_kspace *q, const relpic_device *dev,
 relpic_status relpic_kspace_self_force(const relpic_kspace *q, const relpic_device *dev, int gather_order,
                                        double *out);
 
+/* E1 at any E1 point of a 2D or a 3D grid (Eq. 9 with the x2 and x3
+ * integrals; off axis, Sec. 2.2 gives only i2 = 0 and notes the other rows
+ * follow from the same integral).  ndim = 2: out[k] = E1 dx1 / q at
+ * (i1_rel[k] + 1/2, i2[k]) relative to the particle's node (i3 and r3
+ * unused, i3 may be NULL); ndim = 3: out[k] = E1 dx1^2 / q at (i1_rel[k] +
+ * 1/2, i2[k], i3[k]), q->r = dx2/dx1, r3 = dx3/dx1 > 0.  The transverse
+ * operators are Yee's and tpow applies to each transverse direction; the
+ * axial operators, beta, shape and zones as for relpic_kspace_e1 (with i2 =
+ * 0 in 2D it returns the same quantity).  FP64 quadrature: in 3D the x3
+ * integral is in closed form and the x2 integral a tanh-sinh rule inside
+ * every k1 node (about 1e7 integrand evaluations per point).  npts <= 2^20;
+ * |i2|, |i3| <= 100000.  Synchronizing; dev may be NULL. */
+relpic_status relpic_kspace_field(const relpic_kspace *q, const relpic_device *dev, int ndim, double r3, int64_t npts,
+                                  const double *i1_rel, const int32_t *i2, const int32_t *i3, double *out);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid device allocation): relpic_kspace_e1
  * without any device or host heap allocation.  Same arguments and results

@@ -22,6 +22,20 @@
 // The self-force (Eqs. 19, 25) weights the same integrand by the gather's
 // unaliased shape Shat_g(khat) instead of the staggering phase.
 //
+// Off axis (E1 at transverse node i2) the theta integral carries
+// cos(2 i2 theta); by residues, with phi = 2 theta and a = 2A - 1,
+//   int_{-pi}^{pi} cos(n phi) / (a + cos phi) dphi = 2 pi z^|n| / w,  z = w - a,
+// w = sign(a) sqrt(a^2 - 1) for |a| > 1 and w = i s sqrt(1 - a^2) on the
+// pole (the causal root), and T = (3 + cos phi)/4 is divided out by
+// polynomial division (k2n).  In 3D (Eq. 9 with both transverse
+// integrals),
+//   E1 dx1^2 / q = -1/(2 pi^3 r2 r3) sum_nu int dkhat
+//                  Re[(i / sigmaB) Shat I3 e^{i khat (2 i1' + 1)}],
+//   I3 = 2 r3^2 X int_0^{pi/2} dtheta2 T2 cos(2 i2 theta2) J(r3^2 (X - sin^2 theta2 / r2^2)),
+// X = tau^2 - sigmaE sigmaB and J(A) = k2n(A) / A the x3 integral without
+// its factor A; the theta2 integral is tanh-sinh on panels split where its
+// argument crosses 0 and 1 (closed form), inside every k1 node.
+//
 // The host splits [-pi/2, pi/2] of each zone nu at every point where the
 // integrand is singular or changes form (A = 0, A = 1, sin(beta k1' dt) = 0,
 // khat = 0); the device integrates each panel with tanh-sinh quadrature,
@@ -54,6 +68,7 @@ struct KsParams {
   double CB[kKsMaxM];  // operator on B, [k]_B1 (zero-padded to M)
   double kappa, r, beta;
   int order, tpow, gather_order;
+  double r3;  // dx3 / dx1 (3D)
 };
 
 struct Panel {
@@ -110,6 +125,93 @@ __device__ inline void k2_integral(double A, double s, int tpow, double &re, dou
   im = h * h * bi;
 }
 
+struct Cplx {
+  double re, im;
+};
+__device__ inline Cplx cmul(Cplx a, Cplx b) { return Cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline Cplx cdiv(Cplx a, Cplx b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return Cplx{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// Off-axis theta integral divided by A:
+//   J_n(A) = int_{-pi/2}^{pi/2} dtheta T^tpow cos(2 n theta) / (A + i0 s - sin^2 theta)
+// (so that the 2D integrand's Ihat_n = A J_n); zero at the integrable
+// branch points A = 0, 1 themselves
+__device__ inline Cplx k2n_over_a(double A, double s, int tpow, int n) {
+  n = n < 0 ? -n : n;
+  const double a = 2.0 * A - 1.0;
+  Cplx w;
+  if (fabs(a) > 1.0)
+    w = Cplx{copysign(sqrt(a * a - 1.0), a), 0.0};
+  else
+    w = Cplx{0.0, s * sqrt(1.0 - a * a)};
+  if (w.re == 0.0 && w.im == 0.0) return Cplx{0.0, 0.0};
+  const Cplx z{w.re - a, w.im};
+  Cplx zn{1.0, 0.0};
+  for (int k = 0; k < n; ++k) zn = cmul(zn, z);
+  Cplx In = cdiv(zn, w);  // int_{-pi}^{pi} cos(n phi) / (a + cos phi) dphi = 2 pi z^n / w
+  In.re *= 2.0 * kPi;
+  In.im *= 2.0 * kPi;
+  const double d0 = n == 0 ? 2.0 * kPi : 0.0, d1 = n == 1 ? kPi : 0.0;
+  // theta -> phi = 2 theta turns dtheta / (A - sin^2) into dphi / (a + cos phi)
+  Cplx J;
+  if (tpow == 0) {
+    J = In;
+  } else if (tpow == 1) {
+    J = Cplx{0.25 * (d0 + (3.0 - a) * In.re), 0.25 * (3.0 - a) * In.im};
+  } else {
+    const double c = (3.0 - a) * (3.0 - a) / 16.0;
+    J = Cplx{(a * d0 + d1 + 2.0 * (3.0 - a) * d0) / 16.0 + c * In.re, c * In.im};
+  }
+  return J;
+}
+
+// tanh-sinh rule of the inner (theta2) integral: step 1/32, t up to 3
+constexpr double kTsStepIn = 1.0 / 32.0;
+constexpr int kTsHalfIn = 96;
+
+// I3 of zone nu at khat (3D transverse integral, x3 closed form, x2 tanh-sinh)
+__device__ inline Cplx i3_integral(const KsParams &p, double X, double s, int i2, int i3) {
+  if (X == 0.0) return Cplx{0.0, 0.0};
+  const double r2 = p.r, r3 = p.r3;
+  // panels of [0, pi/2]: split where r3^2 (X - sin^2 / r2^2) = 0 or 1
+  double bp[4];
+  int nb = 0;
+  bp[nb++] = 0.0;
+  const double v0 = r2 * r2 * X, v1 = r2 * r2 * (X - 1.0 / (r3 * r3));
+  // v1 < v0, so the A3 = 1 point comes first
+  if (v1 > 0.0 && v1 < 1.0) bp[nb++] = asin(sqrt(v1));
+  if (v0 > 0.0 && v0 < 1.0) bp[nb++] = asin(sqrt(v0));
+  bp[nb++] = 0.5 * kPi;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b + 1 < nb; ++b) {
+    const double lo = bp[b], hi = bp[b + 1];
+    if (hi - lo < 1e-15) continue;
+    const double half = 0.5 * (hi - lo);
+    for (int k = -kTsHalfIn; k <= kTsHalfIn; ++k) {
+      const double u = k * kTsStepIn;
+      const double q = 0.5 * kPi * sinh(u);
+      const double ch = cosh(q);
+      const double wt = kTsStepIn * 0.5 * kPi * cosh(u) / (ch * ch);
+      const double e = 2.0 / (1.0 + exp(2.0 * fabs(q)));
+      const double t2 = q >= 0.0 ? hi - half * e : lo + half * e;
+      if (!(t2 > lo && t2 < hi)) continue;
+      const double st = sin(t2);
+      const double A3 = r3 * r3 * (X - st * st / (r2 * r2));
+      if (A3 == 0.0) continue;
+      double T2 = 1.0;
+      for (int j = 0; j < p.tpow; ++j) T2 *= 1.0 - 0.5 * st * st;
+      const Cplx J = k2n_over_a(A3, s, p.tpow, i3);
+      const double f = half * wt * T2 * cos(2.0 * i2 * t2);
+      re += f * J.re;
+      im += f * J.im;
+    }
+  }
+  const double pre = 2.0 * r3 * r3 * X;
+  return Cplx{pre * re, pre * im};
+}
+
 // Re[(i / sigma1) Shat(kh + nu pi) I e^{i ph kh}]; with force = true the
 // self-force weight Shat_g(kh) replaces the phase factor
 __device__ inline double integrand(const KsParams &p, double kh, int nu, double ph, bool force) {
@@ -154,6 +256,58 @@ __global__ __launch_bounds__(256) void k_kspace(KsParams p, const Panel *panels,
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) out[blockIdx.x] = -(part[0] + part[1] + part[2] + part[3]) / (2.0 * kPi * kPi * p.r);
+}
+
+// One point of relpic_kspace_field: phase 2 i1' + 1 and the transverse nodes
+struct KsPoint {
+  double ph;
+  int i2, i3;
+};
+
+// 2D off axis and 3D: one workgroup per output point
+__global__ __launch_bounds__(256) void k_kspace_field(KsParams p, const Panel *panels, int npanels,
+                                                      const KsPoint *pts, int ndim, double *out) {
+  const KsPoint pt = pts[blockIdx.x];
+  const int per = 2 * kTsHalf + 1;
+  const long long total = (long long)npanels * per;
+  double acc = 0.0;
+  for (long long t = threadIdx.x; t < total; t += blockDim.x) {
+    const Panel pn = panels[t / per];
+    const int k = (int)(t % per) - kTsHalf;
+    const double u = k * kTsStep;
+    const double q = 0.5 * kPi * sinh(u);
+    const double ch = cosh(q);
+    const double wt = kTsStep * 0.5 * kPi * cosh(u) / (ch * ch);
+    const double half = 0.5 * (pn.b - pn.a);
+    const double e = 2.0 / (1.0 + exp(2.0 * fabs(q)));
+    const double kh = q >= 0.0 ? pn.b - half * e : pn.a + half * e;
+    if (!(kh > pn.a && kh < pn.b)) continue;
+    const double sB = sigma1b(p, kh);
+    if (sB == 0.0) continue;
+    const double sv = sin(2.0 * p.beta * (kh + pn.nu * kPi) / p.kappa);
+    const double sg = sv > 0.0 ? 1.0 : (sv < 0.0 ? -1.0 : 0.0);
+    Cplx I;
+    if (ndim == 3) {
+      const double X = a_of(p, kh, pn.nu) / (p.r * p.r);
+      I = i3_integral(p, X, sg, pt.i2, pt.i3);
+    } else {
+      const double A = a_of(p, kh, pn.nu);
+      const Cplx J = k2n_over_a(A, sg, p.tpow, pt.i2);
+      I = Cplx{A * J.re, A * J.im};
+    }
+    const double w = shat(kh + pn.nu * kPi, p.order) / sB;
+    const double vr = -I.im * w, vi = I.re * w;  // (i / sB) I Shat
+    acc += half * wt * (vr * cos(pt.ph * kh) - vi * sin(pt.ph * kh));
+  }
+  __shared__ double part[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tot = part[0] + part[1] + part[2] + part[3];
+    out[blockIdx.x] = ndim == 3 ? -tot / (2.0 * kPi * kPi * kPi * p.r * p.r3) : -tot / (2.0 * kPi * kPi * p.r);
+  }
 }
 
 // A fixed-capacity list (no heap allocation): panel breakpoints and panels
@@ -208,15 +362,25 @@ constexpr int kMaxBreaks = 256;  // breakpoints of one zone
 // Panels between consecutive breakpoints (A = 0, A = 1, sin(beta k1' dt) = 0,
 // the zone edges and 0) of every zone nu = -nu_max .. nu_max, written to out;
 // false if more than cap panels (or breakpoints) are needed.
+// In 3D the levels of A = r2^2 X where the theta2 integrand changes form:
+// X = 0, 1/r3^2, 1/r2^2, 1/r2^2 + 1/r3^2.
 template <typename L>
-bool make_panels_into(const KsParams &p, int nu_max, L &out) {
+bool make_panels_into(const KsParams &p, int nu_max, L &out, int ndim = 2) {
   const double lo = -0.5 * kPi, hi = 0.5 * kPi;
+  const double q23 = ndim == 3 ? p.r * p.r / (p.r3 * p.r3) : 0.0;
+  const double lev3[4] = {0.0, q23, 1.0, 1.0 + q23};
+  const double lev2[2] = {0.0, 1.0};
+  const double *levels = ndim == 3 ? lev3 : lev2;
+  const int nlev = ndim == 3 ? 4 : 2;
   for (int nu = -nu_max; nu <= nu_max; ++nu) {
     FixedList<double, kMaxBreaks> bp;
     bp.push(lo);
     bp.push(0.0);
     bp.push(hi);
-    for (double lev : {0.0, 1.0}) roots([&](double k) { return a_of(p, k, nu) - lev; }, lo, hi, 4000, bp);
+    for (int li = 0; li < nlev; ++li) {
+      const double lev = levels[li];
+      roots([&](double k) { return a_of(p, k, nu) - lev; }, lo, hi, 4000, bp);
+    }
     roots([&](double k) { return std::sin(2.0 * p.beta * (k + nu * kPi) / p.kappa); }, lo, hi, 4000, bp);
     if (bp.overflow) return false;
     std::sort(bp.v, bp.v + bp.n);
@@ -234,9 +398,9 @@ struct PanelVec {
   void push(const Panel &x) { v.push_back(x); }
 };
 
-std::vector<Panel> make_panels(const KsParams &p, int nu_max) {
+std::vector<Panel> make_panels(const KsParams &p, int nu_max, int ndim = 2) {
   PanelVec out;
-  make_panels_into(p, nu_max, out);
+  make_panels_into(p, nu_max, out, ndim);
   return out.v;
 }
 
@@ -367,6 +531,67 @@ relpic_status relpic_kspace_self_force(const relpic_kspace *q, const relpic_devi
     p.gather_order = gather_order;
     std::vector<double> phase(1, 0.0);
     return run(p, q->nu_max, dev, phase, 1, out);
+  });
+}
+
+relpic_status relpic_kspace_field(const relpic_kspace *q, const relpic_device *dev, int ndim, double r3, int64_t npts,
+                                  const double *i1_rel, const int32_t *i2, const int32_t *i3, double *out) {
+  return guarded("kspace_field", [&]() -> relpic_status {
+    KsParams p;
+    if (relpic_status e = check_params(q, p)) return e;
+    if (ndim != 2 && ndim != 3) return fail(RELPIC_EINVAL, "kspace_field: ndim must be 2 or 3");
+    if (ndim == 3 && !(r3 > 0.0)) return fail(RELPIC_EINVAL, "kspace_field: need r3 > 0");
+    if (npts < 1 || npts > (1 << 20) || !i1_rel || !i2 || (ndim == 3 && !i3) || !out)
+      return fail(RELPIC_EINVAL, "kspace_field: bad points");
+    p.r3 = ndim == 3 ? r3 : 1.0;
+    std::vector<KsPoint> pts((size_t)npts);
+    for (int64_t i = 0; i < npts; ++i) {
+      if (!std::isfinite(i1_rel[i]) || std::fabs(i1_rel[i]) > 1e6 || std::abs(i2[i]) > 100000 ||
+          (ndim == 3 && std::abs(i3[i]) > 100000))
+        return fail(RELPIC_EINVAL, "kspace_field: bad index");
+      pts[i] = KsPoint{2.0 * i1_rel[i] + 1.0, i2[i], ndim == 3 ? i3[i] : 0};
+    }
+    const std::vector<Panel> panels = make_panels(p, q->nu_max, ndim);
+    const int dv = dev ? dev->device : 0;
+    HIP_OK(hipSetDevice(dv));
+    hipStream_t st = dev ? (hipStream_t)dev->stream : nullptr;
+    auto dalloc = [&](size_t bytes) -> void * {
+      void *ptr = nullptr;
+      if (dev && dev->alloc)
+        ptr = dev->alloc(bytes, dev->user);
+      else if (hipMalloc(&ptr, bytes) != hipSuccess)
+        ptr = nullptr;
+      return ptr;
+    };
+    auto dfree = [&](void *ptr) {
+      if (!ptr) return;
+      if (dev && dev->free)
+        dev->free(ptr, dev->user);
+      else if (!(dev && dev->alloc))
+        (void)hipFree(ptr);
+    };
+    Panel *dp = (Panel *)dalloc(sizeof(Panel) * panels.size());
+    KsPoint *dpt = (KsPoint *)dalloc(sizeof(KsPoint) * pts.size());
+    double *dout = (double *)dalloc(sizeof(double) * pts.size());
+    relpic_status rc = RELPIC_OK;
+    if (!dp || !dpt || !dout) {
+      rc = fail(RELPIC_ENOMEM, "kspace_field: allocation failed");
+    } else {
+      hipError_t e = hipMemcpyAsync(dp, panels.data(), sizeof(Panel) * panels.size(), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dpt, pts.data(), sizeof(KsPoint) * pts.size(), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) {
+        k_kspace_field<<<(unsigned)pts.size(), 256, 0, st>>>(p, dp, (int)panels.size(), dpt, ndim, dout);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(double) * pts.size(), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) rc = fail(RELPIC_EDEVICE, std::string("kspace_field: ") + hipGetErrorString(e));
+    }
+    dfree(dp);
+    dfree(dpt);
+    dfree(dout);
+    return rc;
   });
 }
 

@@ -29,7 +29,7 @@ EXPORTS = (
     "relpic_batch_run", "relpic_batch_step", "relpic_batch_sync", "relpic_batch_set_graph_steps",
     "relpic_batch_set_tiling", "relpic_batch_get_tiling", "relpic_batch_autotune", "relpic_batch_read_field",
     "relpic_adj_create", "relpic_adj_destroy", "relpic_adj_load_particles", "relpic_adj_forward",
-    "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_self_force", "relpic_gather_particles", "relpic_e1_residual",
+    "relpic_adj_backward", "relpic_adj_sim", "relpic_kspace_e1", "relpic_kspace_field", "relpic_kspace_self_force", "relpic_gather_particles", "relpic_e1_residual",
     "relpic_kspace_e1_noalloc", "relpic_profile_read_species", "relpic_fit_operator", "relpic_init_beam_fields",
     "relpic_last_error",
 )
@@ -168,6 +168,8 @@ def load():
     L.relpic_adj_backward.argtypes = [P, dp]
     L.relpic_adj_sim.argtypes = [P, ctypes.POINTER(P)]
     L.relpic_kspace_e1.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), I64, dp, dp]
+    L.relpic_kspace_field.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), ctypes.c_int, D, I64, dp,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp]
     L.relpic_kspace_self_force.argtypes = [ctypes.POINTER(KSpaceParams), ctypes.POINTER(Device), ctypes.c_int, dp]
     L.relpic_profile_read_species.argtypes = [P, ctypes.c_int, ctypes.POINTER(I64), dp]
     L.relpic_init_beam_fields.argtypes = [P, D]
@@ -687,6 +689,24 @@ def kspace_e1(i1_rel, C=None, kappa=4.0, r=1.0, beta=1.0, order=2, tpow=0, nu_ma
     out = np.zeros(x.size)
     dev = _device_struct(device, None, None)
     check(load().relpic_kspace_e1(ctypes.byref(q), ctypes.byref(dev), x.size, _dp(x), _dp(out)))
+    return out
+
+
+def kspace_field(i1_rel, i2=0, i3=None, C=None, kappa=4.0, r=1.0, r3=None, beta=1.0, order=2, tpow=0, nu_max=1,
+                 device=0, CB=None):
+    """E1 at E1 points (i1_rel + 1/2, i2[, i3]) of a 2D grid (i3 and r3 None:
+    E1 dx1 / q) or a 3D grid (E1 dx1^2 / q, r3 = dx3/dx1), by
+    relpic_kspace_field."""
+    q, keep = _kspace_struct(C, kappa, r, beta, order, tpow, nu_max, CB)
+    x = np.ascontiguousarray(np.atleast_1d(i1_rel), dtype=np.float64)
+    j2 = np.ascontiguousarray(np.broadcast_to(np.asarray(i2, dtype=np.int32), x.shape))
+    ndim = 2 if i3 is None else 3
+    j3 = np.ascontiguousarray(np.broadcast_to(np.asarray(0 if i3 is None else i3, dtype=np.int32), x.shape))
+    out = np.zeros(x.size)
+    dev = _device_struct(device, None, None)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    check(load().relpic_kspace_field(ctypes.byref(q), ctypes.byref(dev), ndim, float(1.0 if r3 is None else r3), x.size,
+                                     _dp(x), j2.ctypes.data_as(ip), j3.ctypes.data_as(ip), _dp(out)))
     return out
 
 

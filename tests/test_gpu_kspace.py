@@ -64,3 +64,57 @@ def test_self_forces_printed_and_oracle():
     oc = kspace.KSpace("custom", 4.0, 1.0, order=2, C=TABLE1).self_force()
     log("customized self-force %.12g (oracle %.12g)" % (fc, oc))
     assert abs(fc - oc) < TOL * abs(oc)
+
+
+# ---- off-axis rows and the 3D integral (relpic_kspace_field) ------------------------
+
+def test_field_on_axis_equals_e1():
+    # same panels and nodes, the theta integral by the residue form instead of
+    # App. D's: the two agree to rounding except next to the 1/sqrt(1 - A)
+    # points, where the difference is the ~1e-8 of the docstring
+    from paper_1910_13529_amd.relpic import kspace_e1, kspace_field
+    for C, tpow in ((None, 0), (TABLE1, 2)):
+        a = kspace_e1(I1, C=C, tpow=tpow, nu_max=1)
+        b = kspace_field(I1, i2=0, C=C, tpow=tpow, nu_max=1)
+        assert np.abs(a - b).max() < TOL * np.abs(a).max()
+
+
+@pytest.mark.parametrize("solver,beta,tpow,i2", [
+    ("yee", 1.0, 0, 1), ("yee", 1.0, 2, 3), ("yee", 0.6, 1, 2), ("yee", 1.0, 1, 7), ("custom", 1.0, 0, 2),
+    ("custom", 1.0, 2, 5),
+])
+def test_field_2d_off_axis_matches_oracle(solver, beta, tpow, i2):
+    from paper_1910_13529_amd.relpic import kspace_field
+    C = TABLE1 if solver == "custom" else None
+    ip = np.arange(-12, 5, dtype=np.float64)
+    g = kspace_field(ip, i2=i2, C=C, beta=beta, tpow=tpow, nu_max=1)
+    o = kspace.KSpace(solver, 4.0, 1.0, order=2, beta=beta, C=C, tpow=tpow, nus=(-1, 0, 1)).e1(ip, i2=i2)
+    err = np.abs(g - o).max() / np.abs(o).max()
+    log("off axis %s beta=%g q=%d i2=%d: max |E1| %.4g, rel err %.3g" % (solver, beta, tpow, i2, np.abs(o).max(), err))
+    assert err < TOL
+
+
+# 3D: the x2 integral is a nested quadrature on both sides (tanh-sinh inside
+# every k1 node on the GPU, adaptive Gauss-Kronrod in the oracle), so the
+# bar is 1e-6 of the largest value
+TOL3 = 1e-6
+PTS3 = [(-3, 0, 0), (-1, 1, 0), (0, 0, 2), (2, 1, 1), (-6, 2, 1)]
+
+
+@pytest.mark.parametrize("solver,beta,tpow,r2,r3,nus", [
+    ("yee", 1.0, 1, 1.0, 1.3, (-1, 0, 1)),
+    ("yee", 0.5, 0, 1.2, 0.9, (0,)),
+    ("custom", 1.0, 2, 1.0, 1.0, (-1, 0, 1)),
+])
+def test_field_3d_matches_oracle(solver, beta, tpow, r2, r3, nus):
+    from paper_1910_13529_amd.relpic import kspace_field
+    C = TABLE1 if solver == "custom" else None
+    ip = np.array([p[0] for p in PTS3], dtype=np.float64)
+    j2 = np.array([p[1] for p in PTS3], dtype=np.int32)
+    j3 = np.array([p[2] for p in PTS3], dtype=np.int32)
+    g = kspace_field(ip, i2=j2, i3=j3, C=C, r=r2, r3=r3, beta=beta, tpow=tpow, nu_max=max(nus))
+    k3 = kspace.KSpace3D(solver, 4.0, r2, r3, order=2, beta=beta, C=C, tpow=tpow, nus=nus)
+    o = np.array([k3.e1([a], i2=b, i3=c)[0] for a, b, c in PTS3])
+    err = np.abs(g - o).max() / np.abs(o).max()
+    log("3D %s beta=%g q=%d r2=%g r3=%g: %s vs %s, rel err %.3g" % (solver, beta, tpow, r2, r3, g, o, err))
+    assert err < TOL3
