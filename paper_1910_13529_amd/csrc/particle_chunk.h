@@ -159,25 +159,30 @@ __device__ __forceinline__ Real interp_lds(const StaggerL &s, const Real wN[3][3
 
 // Esirkepov shape arrays on four nodes starting at old cell + base:
 // S0 at x^n, DS = S(x^{n+1}) - S(x^n); cum = running sum of DS.
+// The cell moves by sh in {-1, 0, 1}.  Node base + a (a = 0..3) relative to
+// the old cell, base = -2 when the particle moved down a cell, else -1: the
+// old weights sit on a = 0..2, or on a = 1..3 after a move down; the new
+// ones (node base + a - sh of the new cell) on a = 0..2, or on a = 1..3
+// after a move up.  Selecting with the two flags (rather than comparing
+// every node index) keeps the number of lane masks, and of the scalar
+// registers holding them, at two.
 template <typename Real>
 __device__ __forceinline__ int esirkepov_1d(Real o0, int sh, Real o1, Real S0[4], Real DS[4], Real cum[4]) {
   Real w0[3], w1[3];
   qw(o0, w0);
   qw(o1, w1);
-  const int base = sh < 0 ? -2 : -1;
+  const bool dn = sh < 0, up = sh > 0;
+  const Real s0[4] = {dn ? Real(0) : w0[0], dn ? w0[0] : w0[1], dn ? w0[1] : w0[2], dn ? w0[2] : Real(0)};
+  const Real s1[4] = {up ? Real(0) : w1[0], up ? w1[0] : w1[1], up ? w1[1] : w1[2], up ? w1[2] : Real(0)};
   Real run = 0;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int k = base + a;  // node relative to the old cell
-    const int k1 = k - sh;   // node relative to the new cell
-    const Real s0 = (k >= -1 && k <= 1) ? w0[k + 1] : Real(0);
-    const Real s1 = (k1 >= -1 && k1 <= 1) ? w1[k1 + 1] : Real(0);
-    S0[a] = s0;
-    DS[a] = s1 - s0;
+    S0[a] = s0[a];
+    DS[a] = s1[a] - s0[a];
     run += DS[a];
     cum[a] = run;
   }
-  return base;
+  return dn ? -2 : -1;
 }
 
 // Where deposits go: the workgroup's LDS tile if it covers the point, else
