@@ -501,7 +501,9 @@ relpic_status relpic_kspace_e1_noalloc(const relpic_kspace *q, const relpic_devi
 relpic_status relpic_gather_particles(relpic_sim *sim, int species, int64_t first, int64_t count, double *EB);
 
 /* The simulated on-axis E1 around one particle next to the k-space
- * prediction for the same points (Eq. 13, 2D runs only).  The particle (slot
+ * prediction for the same points (Eq. 13 in 2D; in 3D Eq. 9 with both
+ * transverse integrals, relpic_kspace_field at r3 = dx3/dx1, and the values
+ * are E1 dx1^2 / Q instead of E1 dx1 / Q).  The particle (slot
  * `slot` of `species`) must sit on an x1 node (|offset1| <= 1e-6, else
  * RELPIC_ERANGE; a beta = 1 charge returns to a node every kappa steps when
  * kappa is an integer).  For each k, sim_out[k] = E1 dx1 / Q at the E1

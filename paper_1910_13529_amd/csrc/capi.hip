@@ -984,7 +984,6 @@ relpic_status relpic_e1_residual(relpic_sim *s, int species, int64_t slot, const
                                  const int32_t *i1_rel, double *sim_out, double *theory_out) {
   return guarded("e1_residual", [&]() -> relpic_status {
     if (relpic_status r = check_sim(s)) return r;
-    if (s->ndim != 2) return fail(RELPIC_EINVAL, "e1_residual: the k-space field is the 2D one (Eq. 13)");
     if (species < 0 || species >= (int)s->sp.size()) return fail(RELPIC_EINVAL, "e1_residual: bad species");
     Species &sp = s->sp[species];
     if (slot < 0 || slot >= sp.n) return fail(RELPIC_ERANGE, "e1_residual: particle slot out of range");
@@ -1042,7 +1041,8 @@ relpic_status relpic_e1_residual(relpic_sim *s, int species, int64_t slot, const
       }
     }
     std::vector<double> rel((size_t)npts);
-    const double scale = s->dx[0] / sp.Q;
+    // E1 dx1 / Q in 2D, E1 dx1^2 / Q in 3D (the k-space field's normalization)
+    const double scale = (s->ndim == 3 ? s->dx[0] * s->dx[0] : s->dx[0]) / sp.Q;
     for (int64_t k = 0; k < npts; ++k) {
       long long l = (long long)c1 + i1_rel[k];
       if (s->grid.bc1 == RELPIC_BC_WINDOW) {
@@ -1055,7 +1055,11 @@ relpic_status relpic_e1_residual(relpic_sim *s, int species, int64_t slot, const
     }
     relpic_kspace qq = *q;
     relpic_device dv = s->dev;
-    return relpic_kspace_e1(&qq, &dv, npts, rel.data(), theory_out);
+    if (s->ndim == 2) return relpic_kspace_e1(&qq, &dv, npts, rel.data(), theory_out);
+    // 3D: the particle's own (x2, x3) row of the 3D field (Eq. 9 with both transverse integrals)
+    const std::vector<int32_t> zero((size_t)npts, 0);
+    return relpic_kspace_field(&qq, &dv, 3, s->dx[2] / s->dx[0], npts, rel.data(), zero.data(), zero.data(),
+                               theory_out);
   });
 }
 

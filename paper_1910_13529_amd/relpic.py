@@ -444,7 +444,8 @@ class SimOps:
 
     def e1_residual(self, species, slot, i1_rel, C=None, kappa=None, r=None, beta=1.0, shape_order=2, tpow=1,
                     nu_max=3):
-        """(simulated E1 dx1/Q, k-space E1 dx1/q) at E1 points i1_rel around the particle in `slot`."""
+        """(simulated, k-space) E1 at E1 points i1_rel on the particle's row around the particle in
+        `slot`: E1 dx1 / Q in 2D, E1 dx1^2 / Q in 3D (relpic_e1_residual)."""
         g = self.grid
         if C is None:
             C, CB = getattr(self, "C", None), getattr(self, "CB", None)

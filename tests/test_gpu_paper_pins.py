@@ -8,7 +8,9 @@
   and line-out element by element, and the k-space side matches the
   oracle's quadrature;
 * the GPU's own Yee self-force, extrapolated over the transverse width as in
-  the oracle pin, reproduces the k-space F1 with the PIC's gather (Eq. 19).
+  the oracle pin, reproduces the k-space F1 with the PIC's gather (Eq. 19);
+* in 3D the line-out matches the oracle's field and its k-space side the 3D
+  k-space oracle.
 """
 import math
 
@@ -134,3 +136,32 @@ def test_e1_residual_rejects_mismatched_theory():
     with pytest.raises(RelpicError):
         g.e1_residual(sid, 0, [0])
     g.sync()
+
+
+def test_gpu_e1_residual_3d_matches_oracle():
+    # 3D: the line-out on the particle's row against the FP64 oracle's field,
+    # and the theory side against the 3D k-space oracle (x3 closed form, x2
+    # and k1 quadrature); Yee, kappa = 4, r2 = r3 = 1, a beta -> 1 charge on
+    # a node after 40 steps (ten window shifts)
+    from paper_1910_13529_amd.relpic import Sim
+    n = (48, 16, 16)
+    grid = dict(ndim=3, n=n, dx=(1.0, 1.0, 1.0), dt=0.25, window=True, window_speed=1.0)
+    g = Sim(grid, precision="fp64")
+    sid = g.add_species(0.0, 1.0, 1)
+    g.load_particles(sid, np.array([[24, 8, 8]], dtype=np.int32), np.zeros((1, 3)), np.array([[1e8, 0.0, 0.0]]))
+    g.step(40)
+    o = OracleSim(n, (1.0, 1.0, 1.0), 0.25, window=True, vwin=1.0)
+    o.add_particles(np.array([[24.0, 8.0, 8.0]]), np.array([[1e8, 0.0, 0.0]]), 1.0, 0.0)
+    o.step(40)
+    x, _, _ = o.particles()
+    rel = np.array([-6, -3, -1, 0, 2], dtype=np.int32)
+    sim, th = g.e1_residual(sid, 0, rel, beta=1.0, shape_order=2, tpow=1, nu_max=1)
+    ip = int(round(x[0, 0])) - o.window_start
+    line = o.field("E1")[8, 8, ip + rel]
+    assert np.abs(sim - line).max() < 1e-12 * np.abs(line).max()
+    k3 = kspace.KSpace3D("yee", 4.0, 1.0, 1.0, order=2, beta=1.0, tpow=1, nus=(-1, 0, 1))
+    ref = np.array([k3.e1([v])[0] for v in rel])
+    log("3D residual: sim %s theory %s oracle theory %s" % (sim, th, ref))
+    assert np.abs(th - ref).max() < 1e-6 * np.abs(ref).max()
+    g.close()
+    o.close()
