@@ -176,7 +176,10 @@ relpic_status relpic_load_particles(relpic_sim *sim, int species, int64_t n, con
  * ppc[d] particles per cell per dimension on a regular sub-lattice
  * (offsets (a + 1/2)/ppc - 1/2), momenta uth * N(0,1) per component drawn
  * from splitmix64 stream `seed` (counter = running injected-particle index *
- * 3 + component, Box-Muller on consecutive uniforms). */
+ * 3 + component, Box-Muller on consecutive uniforms).  The index and the
+ * particle ids count a slab's particles in row order (x2 fastest, then x3,
+ * the sub-lattice point fastest within a cell); a species sorted by tiles
+ * stores them in its tile order instead. */
 relpic_status relpic_set_injection(relpic_sim *sim, int species, const int *ppc, double uth, uint64_t seed);
 
 /* Immobile background charge density (node-centred, dense layout above,

@@ -354,7 +354,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
           break;
         }
         launch_inject_slab<Real>(s->ndim, g2, parts<Real>(sp), sp.id, sp.n, s->n[0] - 3, sp.ppc[0], sp.ppc[1],
-                                 sp.ppc[2], sp.uth, sp.seed, sp.inj_count, sp.next_id, s->st);
+                                 sp.ppc[2], sp.uth, sp.seed, sp.inj_count, sp.next_id, sp.tile_keys, s->st);
         sp.n += nnew;
         sp.next_id += nnew;
         sp.inj_count += (unsigned long long)nnew;

@@ -237,27 +237,44 @@ __device__ __forceinline__ double normal_k(unsigned long long seed, unsigned lon
   return sqrt(-2.0 * log(a)) * cospi(2.0 * b);
 }
 
+// A slab of ppc1 x ppc2 x ppc3 particles per cell in window cell win_cell.
+// Particle r of the slab in row order (cell index i2 + n2 i3, then the
+// sub-lattice point) carries id id0 + r and the thermal momenta of counter
+// counter0 + r.  tiles = 0 stores them in that order; tiles = 1 (3D, n2 and
+// n3 multiples of 4) stores the cells in the order of the tile sort key
+// (4 x 4 transverse blocks, x3 block major; x3 major inside a block), so a
+// push chunk of freshly injected particles covers a compact box before the
+// next re-sort instead of a long x2 row.
 template <typename Real>
 __global__ void k_inject(int ndim, Geo g, Particles<Real> p, int *id, long long first, int win_cell, int ppc1,
                          int ppc2, int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
-                         long long id0) {
+                         long long id0, int tiles) {
   const long long per = (long long)ppc1 * ppc2 * ppc3;
   const long long total = per * g.n2 * g.n3;
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= total) return;
   const long long q = t % per;
-  const long long rc = t / per;
-  const int i2 = (int)(rc % g.n2);
-  const int i3 = (int)(rc / g.n2);
+  const long long rc = t / per;  // the cell's place in storage order
+  int i2, i3;
+  if (tiles) {
+    const long long T = rc >> 4;
+    const int L = (int)(rc & 15), nt2 = g.n2 >> 2;
+    i2 = (int)(T % nt2) * 4 + (L & 3);
+    i3 = (int)(T / nt2) * 4 + (L >> 2);
+  } else {
+    i2 = (int)(rc % g.n2);
+    i3 = (int)(rc / g.n2);
+  }
+  const long long r = ((long long)i3 * g.n2 + i2) * per + q;  // row-order index
   const int a = (int)(q % ppc1), b = (int)((q / ppc1) % ppc2), c = (int)(q / ((long long)ppc1 * ppc2));
   const long long k = first + t;
   const int s1 = col_of(g, win_cell);
   p.cell[k] = s1 + g.n1 * (i2 + g.n2 * i3);
-  id[k] = (int)(id0 + t);
+  id[k] = (int)(id0 + r);
   p.o1[k] = (Real)((a + 0.5) / ppc1 - 0.5);
   p.o2[k] = (Real)((b + 0.5) / ppc2 - 0.5);
   if (ndim == 3) p.o3[k] = (Real)((c + 0.5) / ppc3 - 0.5);
-  const unsigned long long ctr = counter0 + (unsigned long long)t;
+  const unsigned long long ctr = counter0 + (unsigned long long)r;
   p.u1[k] = (Real)(uth * normal_k(seed, 3ULL * ctr + 0ULL));
   p.u2[k] = (Real)(uth * normal_k(seed, 3ULL * ctr + 1ULL));
   p.u3[k] = (Real)(uth * normal_k(seed, 3ULL * ctr + 2ULL));
@@ -307,10 +324,11 @@ void launch_diag_gauss(int ndim, const Geo &g, const Fields<Real> &f, const Axia
 template <typename Real>
 void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, int *id, long long first, int win_cell, int ppc1,
                         int ppc2, int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
-                        long long id0, hipStream_t st) {
+                        long long id0, bool tile_order, hipStream_t st) {
   const long long total = (long long)ppc1 * ppc2 * ppc3 * g.n2 * g.n3;
+  const int tiles = tile_order && ndim == 3 && g.n2 % 4 == 0 && g.n3 % 4 == 0 ? 1 : 0;
   k_inject<Real><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(ndim, g, p, id, first, win_cell, ppc1, ppc2, ppc3,
-                                                                    uth, seed, counter0, id0);
+                                                                    uth, seed, counter0, id0, tiles);
 }
 
 #define RELPIC_INST_AUX(Real)                                                                                      \
@@ -321,7 +339,7 @@ void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, int *id, long
   template void launch_diag_gauss<Real>(int, const Geo &, const Fields<Real> &, const Axial<double> &, double,      \
                                         double, const double *, const double *, int, double *, hipStream_t);       \
   template void launch_inject_slab<Real>(int, const Geo &, Particles<Real>, int *, long long, int, int, int, int,   \
-                                         double, unsigned long long, unsigned long long, long long, hipStream_t);
+                                         double, unsigned long long, unsigned long long, long long, bool, hipStream_t);
 
 RELPIC_INST_AUX(float)
 RELPIC_INST_AUX(double)
