@@ -147,7 +147,9 @@ struct Ctx {
     JBox *next = s->jbox + ((n + 1) & 1);
     if (!s->sp.empty() && a->nparts > 0) {
       Species &sp = s->sp[0];
-      const long long nb = push_blocks(sp.n, sp.K);
+      PushChunks pc;  // runs of 256 K particles in array order
+      pc.K = sp.K;
+      const long long nb = push_grid(pc, sp.n);
       if (nb > s->blockbox_n) {
         s->blockbox = (JBox *)dev_alloc(s, sizeof(JBox) * (size_t)nb);
         if (!s->blockbox) return fail(RELPIC_ENOMEM, "adjoint: allocation of workgroup boxes failed");
@@ -155,7 +157,7 @@ struct Ctx {
       }
       const Fields<Real> f = fields_with(E, bn);
       const HalfB<Real> Bh{bc[0], bc[1], bc[2]};
-      launch_push_deposit<Real>(2, g, f, Bh, parts<Real>(sp), push_params<Real>(s, sp, 0), sp.K, false, s->blockbox,
+      launch_push_deposit<Real>(2, g, f, Bh, parts<Real>(sp), push_params<Real>(s, sp, 0), pc, false, s->blockbox,
                                 s->err, s->st);
       launch_merge_boxes(s->blockbox, nb, box, s->st);
     }

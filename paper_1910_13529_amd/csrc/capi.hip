@@ -132,6 +132,7 @@ template <typename Real>
 relpic_status do_sort(relpic_sim *s, Species &sp) {
   sp.dirty = false;
   sp.sorted_at = s->step;
+  sp.ntiles = sp.n_tiled = 0;
   if (sp.n <= 1) return RELPIC_OK;
   Particles<Real> src = parts<Real>(sp);
   const Geo g = make_geo(s);
@@ -176,13 +177,31 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
     sp.tile_keys = want;
     return do_sort<Real>(s, sp);
   }
+  sp.ntiles = sp.n_tiled = 0;
   if (tiles) {
     // chunks of 256 K particles, at most one tile's worth: a chunk then spans
     // parts of at most two x1-neighbouring tiles, whose cells with the
     // deposit halo (3D FP32: 20 x 8 x 8, FP64: 12 x 8 x 8) fit the push's
-    // LDS tile
+    // LDS tile; used for particles appended after this sort
     const double per_tile = ppc * (double)((s->ndim == 3 ? 16 : 4) << tx);
     sp.K = per_tile >= 2048.0 ? 8 : (per_tile >= 1024.0 ? 4 : (per_tile >= 512.0 ? 2 : 1));
+    // the sorted particles are pushed one sort tile per workgroup: the
+    // chunk's cells are exactly one tile (plus the particles' drift since)
+    if (s->ndim == 3 && sp.n > 0) {
+      const long long nt1 = (g.n1 + (1 << tx) - 1) >> tx, nt2 = (g.n2 + 3) / 4, nt3 = (g.n3 + 3) / 4;
+      const long long ntiles = nt1 * nt2 * nt3;
+      if (ntiles > sp.tiles_cap) {
+        sp.tile_first = (int *)dev_alloc(s, sizeof(int) * (size_t)ntiles);
+        sp.tile_end = (int *)dev_alloc(s, sizeof(int) * (size_t)ntiles);
+        if (!sp.tile_first || !sp.tile_end) return fail(RELPIC_ENOMEM, "sort: tile range allocation failed");
+        sp.tiles_cap = ntiles;
+      }
+      HIP_OK(hipMemsetAsync(sp.tile_first, 0, sizeof(int) * (size_t)ntiles, s->st));
+      HIP_OK(hipMemsetAsync(sp.tile_end, 0, sizeof(int) * (size_t)ntiles, s->st));
+      launch_tile_ranges(sp.keys2, sp.n, 4 + tx, ntiles, sp.tile_first, sp.tile_end, s->st);
+      sp.ntiles = ntiles;
+      sp.n_tiled = sp.n;
+    }
   } else {
     // row order: 1024-particle chunks at most (2048 measured 6% slower on a
     // dense bunch, 512 2% slower)
@@ -263,7 +282,13 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
     for (size_t si = 0; si < s->sp.size(); ++si) {
       Species &sp = s->sp[si];
       const PushParams<Real> q = push_params<Real>(s, sp, shift);
-      const long long nb = push_blocks(sp.n, sp.K);
+      PushChunks pc;
+      pc.first = sp.tile_first;
+      pc.end = sp.tile_end;
+      pc.ntiles = sp.ntiles;
+      pc.nsorted = sp.n_tiled;
+      pc.K = sp.K;
+      const long long nb = push_grid(pc, sp.n);
       if (nb > s->blockbox_n) {
         s->blockbox = (JBox *)dev_alloc(s, sizeof(JBox) * (size_t)nb);
         if (!s->blockbox) {
@@ -274,7 +299,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       }
       {
         ProfScope ps(s, 0 + 64 * (int)(si + 1));
-        launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, sp.K, sp.tile_keys, s->blockbox, s->err,
+        launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, pc, sp.tile_keys, s->blockbox, s->err,
                                   s->st);
       }
       ProfScope ps(s, 6);

@@ -34,6 +34,9 @@ struct Species {
   long long sorted_at = 0;  // step of the last sort
   int K = 1;           // particles per thread in the push kernel
   bool tile_keys = false;  // sort key order: 3D tiles (sparse) or rows (dense)
+  // index ranges of the sort tiles after the last tile sort (push chunks)
+  int *tile_first = nullptr, *tile_end = nullptr;
+  long long tiles_cap = 0, ntiles = 0, n_tiled = 0;
   bool inject = false;
   int ppc[3] = {1, 1, 1};
   double uth = 0.0;

@@ -67,13 +67,25 @@ void launch_leap(const Geo &g, Real *const Ein[3], Real *const Eout[3], Real *co
 
 // K particles per thread; each workgroup handles a contiguous chunk of
 // 256 * K particles (sorted by cell for the LDS-tiled deposit to pay off);
+// Push chunks: one per sort tile of the last tile sort ([first[t], end[t])
+// of the array, ntiles of them, covering the first nsorted particles), then
+// runs of 256 K particles over the rest (appended since); ntiles = nsorted =
+// 0: runs of 256 K over the whole array.
+struct PushChunks {
+  const int *first = nullptr, *end = nullptr;
+  long long ntiles = 0, nsorted = 0;
+  int K = 1;
+};
+// workgroups (and scratch boxes) of a push over n particles
+long long push_grid(const PushChunks &pc, long long n);
 // wide (3D, FP32): deposit rounds over boxes four x1 cells wide instead of
-// two, for species spread over the grid at a few particles per cell
-// blockbox: push_blocks(n, K) scratch boxes, merged into *jbox after the launch
+// two, and cell groups, for species spread over the grid at a few particles
+// per cell; blockbox: push_grid(pc, n) scratch boxes, merged into *jbox
+// after the launch
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
-                         const Particles<Real> &p, const PushParams<Real> &q, int K, bool wide, JBox *blockbox,
-                         int *err, hipStream_t st);
+                         const Particles<Real> &p, const PushParams<Real> &q, const PushChunks &pc, bool wide,
+                         JBox *blockbox, int *err, hipStream_t st);
 // *jbox = union of the nbox per-workgroup boxes (atomic min/max into *jbox)
 void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStream_t st);
 long long push_blocks(long long n, int K);
@@ -90,6 +102,11 @@ bool sort_tiles_fit(const Geo &g);
 template <typename Real>
 void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, const int *id_src, int *id_dst,
                     const unsigned *perm, int ndim, hipStream_t st);
+// index range of each sort tile (key >> shift) among the n alive particles
+// of a tile-sorted key array; first, end: ntiles ints each, cleared by the
+// caller
+void launch_tile_ranges(const unsigned *keys, long long n, int shift, long long ntiles, int *first, int *end,
+                        hipStream_t st);
 // sorted keys: distinct alive cells added to *runs, alive count written to *alive
 void launch_count_runs(const unsigned *keys, long long n, unsigned long long *runs, unsigned long long *alive,
                        hipStream_t st);

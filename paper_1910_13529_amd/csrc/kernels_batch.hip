@@ -96,7 +96,9 @@ __global__ __launch_bounds__(kPushBlock) void k_batch_push(const BatchRun<Real> 
   f.J3 = r.J3;
   f.J1c = r.J1c;
   const HalfB<Real> Bh{r.B[bnew ^ 1][0], r.B[bnew ^ 1][1], r.B[bnew ^ 1][2]};
-  push_chunk<Real, 2>(r.g, f, Bh, pd.p, pd.q, pd.K, c.chunk, chunkbox + blockIdx.x, err, tile_raw, box);
+  const long long c0 = c.chunk * (long long)kPushBlock * pd.K;
+  push_chunk<Real, 2>(r.g, f, Bh, pd.p, pd.q, c0, c0 + (long long)kPushBlock * pd.K, chunkbox + blockIdx.x, err,
+                      tile_raw, box);
 }
 
 // box[run] = union of the run's chunk boxes (one wavefront per run)

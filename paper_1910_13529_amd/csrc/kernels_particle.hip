@@ -22,14 +22,31 @@
 
 namespace relpic {
 
+// Workgroup b takes sort tile b's particles (b < pc.ntiles) or the b -
+// pc.ntiles-th run of 256 K particles after the first pc.nsorted.
 template <typename Real, int DIM, int W>
 __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real> f, HalfB<Real> Bh,
-                                                             Particles<Real> p, PushParams<Real> q, int K,
+                                                             Particles<Real> p, PushParams<Real> q, PushChunks pc,
                                                              JBox *blockbox, int *err) {
   constexpr int TILE = PushTile<Real>::bytes;
   __shared__ __align__(16) unsigned char tile_raw[TILE];
   __shared__ int box[kChunkBoxInts];
-  push_chunk<Real, DIM, W, TILE>(g, f, Bh, p, q, K, blockIdx.x, blockbox + blockIdx.x, err, tile_raw, box);
+  const long long b = blockIdx.x;
+  long long c0, c1;
+  if (b < pc.ntiles) {
+    c0 = pc.first[b];
+    c1 = pc.end[b];
+  } else {
+    const long long per = (long long)kPushBlock * pc.K;
+    c0 = pc.nsorted + (b - pc.ntiles) * per;
+    c1 = c0 + per;
+  }
+  if constexpr (W == 4) {
+    __shared__ GroupLds grp;
+    push_chunk<Real, DIM, W, TILE>(g, f, Bh, p, q, c0, c1, blockbox + b, err, tile_raw, box, &grp);
+  } else {
+    push_chunk<Real, DIM, W, TILE>(g, f, Bh, p, q, c0, c1, blockbox + b, err, tile_raw, box);
+  }
 }
 
 // Box of a set of per-workgroup boxes merged into *out: each workgroup
@@ -84,19 +101,42 @@ long long push_blocks(long long n, int K) {
   return n <= 0 ? 0 : (n + per - 1) / per;
 }
 
+long long push_grid(const PushChunks &pc, long long n) {
+  return n <= 0 ? 0 : pc.ntiles + push_blocks(n - pc.nsorted, pc.K);
+}
+
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
-                         const Particles<Real> &p, const PushParams<Real> &q, int K, bool wide, JBox *blockbox,
-                         int *err, hipStream_t st) {
+                         const Particles<Real> &p, const PushParams<Real> &q, const PushChunks &pc, bool wide,
+                         JBox *blockbox, int *err, hipStream_t st) {
   if (p.n <= 0) return;
-  const unsigned blocks = (unsigned)push_blocks(p.n, K);
+  const unsigned blocks = (unsigned)push_grid(pc, p.n);
   // FP64 keeps the narrow rounds: the wide ones take it from two waves per SIMD to one
   if (ndim == 3 && wide && sizeof(Real) == 4)
-    k_push_deposit<Real, 3, 4><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
+    k_push_deposit<Real, 3, 4><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, pc, blockbox, err);
   else if (ndim == 3)
-    k_push_deposit<Real, 3, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
+    k_push_deposit<Real, 3, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, pc, blockbox, err);
   else
-    k_push_deposit<Real, 2, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, K, blockbox, err);
+    k_push_deposit<Real, 2, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, pc, blockbox, err);
+}
+
+// Particle index range of each sort tile in a tile-sorted array of n alive
+// particles: first[t] at the tile's first particle, end[t] one past its last
+// (tiles without particles keep the zeros the caller cleared).
+__global__ __launch_bounds__(256) void k_tile_ranges(const unsigned *keys, long long n, int shift, long long ntiles,
+                                                     int *first, int *end) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const unsigned t = keys[i] >> shift;
+  if ((long long)t >= ntiles) return;
+  if (i == 0 || (keys[i - 1] >> shift) != t) first[t] = (int)i;
+  if (i + 1 == n || (keys[i + 1] >> shift) != t) end[t] = (int)(i + 1);
+}
+
+void launch_tile_ranges(const unsigned *keys, long long n, int shift, long long ntiles, int *first, int *end,
+                        hipStream_t st) {
+  if (n <= 0) return;
+  k_tile_ranges<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(keys, n, shift, ntiles, first, end);
 }
 
 void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStream_t st) {
@@ -201,8 +241,8 @@ void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, cons
 
 #define RELPIC_INST_PART(Real)                                                                                   \
   template void launch_push_deposit<Real>(int, const Geo &, const Fields<Real> &, const HalfB<Real> &,          \
-                                          const Particles<Real> &, const PushParams<Real> &, int, bool, JBox *,  \
-                                          int *, hipStream_t);                                                   \
+                                          const Particles<Real> &, const PushParams<Real> &, const PushChunks &, \
+                                          bool, JBox *, int *, hipStream_t);                                     \
   template void launch_sort_keys<Real>(const Geo &, const Particles<Real> &, int, unsigned *, unsigned *,        \
                                        hipStream_t);                                                             \
   template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \

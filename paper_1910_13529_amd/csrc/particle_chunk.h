@@ -11,11 +11,13 @@ namespace relpic {
 
 constexpr int kPushBlock = 256;
 constexpr int kTileBytes = 49152;  // LDS tile per workgroup: J (3 components) + E, B (6)
-// The single-run FP64 push runs two waves per SIMD (two workgroups per CU),
-// which leaves room for a larger tile: 768 cells of 9 FP64 words.
+// The single-run FP32 push runs three workgroups per CU in 160 KB of LDS
+// (tile, box words and cell-group tables of each within a third); the FP64
+// push two waves per SIMD (two workgroups per CU), which leaves room for 768
+// cells of 9 FP64 words.
 template <typename Real>
 struct PushTile {
-  static constexpr int bytes = kTileBytes;
+  static constexpr int bytes = 52224;
 };
 template <>
 struct PushTile<double> {
@@ -186,10 +188,14 @@ __device__ __forceinline__ int esirkepov_1d(Real o0, int sh, Real o1, Real S0[4]
 }
 
 // Where deposits go: the workgroup's LDS tile if it covers the point, else
-// J in HBM.  Coordinates are the window x1 index and unwrapped x2, x3.
+// J in HBM.  Coordinates are the window x1 index and unwrapped x2, x3.  An
+// FP32 run accumulates the tile's current in FP64 (tile_d) when the tile has
+// room: LDS atomic adds of FP64 words take a few cycles per wavefront
+// instruction on gfx950, those of FP32 words about three cycles per lane.
 template <typename Real>
 struct Sink {
   Real *tile;        // 3 components x T1 x T2 x T3, or null
+  double *tile_d;    // the same current in FP64 words (FP32 runs), or null
   int t1, t2, t3;    // tile origin
   int T1, T2, T3;    // tile extents
   int tn;            // T1 * T2 * T3
@@ -201,7 +207,11 @@ struct Sink {
     if (tile) {
       const int a = x1 - t1, b = x2 - t2, c = x3 - t3;
       if (a >= 0 && a < T1 && b >= 0 && b < T2 && c >= 0 && c < T3) {
-        lds_add(tile + comp * tn + a + T1 * (b + T2 * c), v);
+        const int id = comp * tn + a + T1 * (b + T2 * c);
+        if (tile_d)
+          lds_add(tile_d + id, (double)v);
+        else
+          lds_add(tile + id, v);
         return;
       }
     }
@@ -498,16 +508,235 @@ __device__ __forceinline__ bool deposit_wave(bool active, const Moved<Real> &m, 
   return active && (pending || !(flat2 && flat3));
 }
 
-// One workgroup's share of the particle phase: chunk `chunk` of K * 256
-// particles.  tile_raw: TILE bytes of LDS, box: kChunkBoxInts ints of LDS; *mybox
-// receives the chunk's deposit box.
+// ---- cell groups (tile-sorted 3D species) ------------------------------------------
+//
+// A sorted plasma holds its particles in runs of one cell each (eight per cell
+// at 8 ppc), but a run can start anywhere in the array, so aligned lanes do
+// not share cells.  A grouped chunk maps each run, cut into pieces of at most
+// eight, onto one 8-lane group of a wavefront: group gi of the chunk takes
+// lanes 8 (gi mod 32) .. + 7 of iteration gi / 32.  All particles of a group
+// then share one cell, and those whose exact supports lie in that cell's
+// frame (node base -1 on every axis, no transverse crossing) are summed over
+// the group by a three-level reduce-scatter (gfx950 DPP: row half-mirror,
+// then lane ^ 1 and lane ^ 2), after which each of the eight lanes adds ten
+// of the frame's 75 points to the LDS tile.
+
+constexpr int kGroupMax = 32 * 9;  // groups of a grouped chunk (<= 2048 particles, <= 9 iterations)
+constexpr int kGroupSlots = 80;    // 8 lanes x 10 points of a group's frame (75 used)
+
+// LDS of a grouped chunk: group starts (chunk positions; start[G] = end), the
+// tile offset of each lane's ten points, scan scratch.
+struct GroupLds {
+  unsigned short start[kGroupMax + 2];
+  int off[kGroupSlots];
+  int scan[8];
+};
+
+// Exclusive scan over the 256 threads of the workgroup (sum, or max with
+// identity -1 for values >= -1); scratch: 4 ints of LDS; *total receives the
+// reduction over all threads.  Contains a barrier; every thread calls it.
+template <bool MAX>
+__device__ __forceinline__ int block_exclusive_scan(int v, int *scratch, int *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x = MAX ? max(x, y) : x + y;
+  }
+  if (lane == 63) scratch[wave] = x;
+  int ex = __shfl_up(x, 1, 64);
+  if (lane == 0) ex = MAX ? -1 : 0;
+  __syncthreads();
+  int pre = MAX ? -1 : 0, tot = MAX ? -1 : 0;
+#pragma unroll
+  for (int w = 0; w < kPushBlock / 64; ++w) {
+    const int s = scratch[w];
+    if (w < wave) pre = MAX ? max(pre, s) : pre + s;
+    tot = MAX ? max(tot, s) : tot + s;
+  }
+  *total = tot;
+  return MAX ? max(pre, ex) : pre + ex;
+}
+
+// Tile offset (relative to the frame origin) of point u of the 10 that lane
+// k of a group holds after the reduction.  Lane k holds, for u = 0..9, pair
+// p = u + 10 ((k >> 1) & 1) + 20 (k & 1), member (k >> 2) & 1 (0: first,
+// 1: second) of the pairs that the first level sums:
+//   p 0..11   J2 at (a = p mod 4, x3 node a3 = p / 4), x2 half point 0 | 1
+//   p 12..23  J3 at (a, x2 node a2), x3 half point 0 | 1
+//   p 24..32  J1 at (a = q mod 3, a2 = q / 3), x3 node 0 | 2
+//   p 33..35  J1 at (a, x3 node 1), x2 node 0 | 2
+//   p 36..38  J1 at (a, 1, 1) | nothing
+// (x1: J1 half points, J2 and J3 nodes, from the frame's first x1 point).
+__device__ __forceinline__ int group_slot_offset(int slot, int T1, int T2, int tn) {
+  const int k = slot / 10, u = slot - 10 * k;
+  const int p = u + 10 * ((k >> 1) & 1) + 20 * (k & 1), h = (k >> 2) & 1;
+  const int T12 = T1 * T2;
+  if (p < 12) return tn + (p & 3) + T1 * h + T12 * (p >> 2);
+  if (p < 24) return 2 * tn + ((p - 12) & 3) + T1 * ((p - 12) >> 2) + T12 * h;
+  if (p < 33) return (p - 24) % 3 + T1 * ((p - 24) / 3) + T12 * (2 * h);
+  if (p < 36) return (p - 33) + T1 * (2 * h) + T12;
+  if (p < 39 && h == 0) return (p - 36) + T1 + T12;
+  return 0;  // padding: its value is zero
+}
+
+// Cut the runs of equal cells of the chunk's P <= 8 * 256 particles (from
+// array index chunk0) into groups of at most 8 and store their starts (chunk
+// positions, one thread per K = ceil(P / 256) consecutive positions) and the
+// lanes' point offsets in *gl.  Returns the number of groups (the table is
+// complete only when it is at most kGroupMax).  Contains barriers; every
+// thread calls it.
+template <typename Real>
+__device__ __forceinline__ int build_groups(const Particles<Real> &p, long long chunk0, int P, int T1, int T2,
+                                            int tn, GroupLds *gl) {
+  const int tid = threadIdx.x;
+  const int K = (P + kPushBlock - 1) / kPushBlock;
+  const int pos0 = tid * K;
+  int prev = INT_MIN;  // no cell has this value (dead particles are -1)
+  if (pos0 > 0 && pos0 - 1 < P) prev = p.cell[chunk0 + pos0 - 1];
+  int cl[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) cl[j] = (j < K && pos0 + j < P) ? p.cell[chunk0 + pos0 + j] : INT_MIN;
+  // last run start among this thread's positions, then the one before them
+  int last = -1;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < K && pos0 + j < P && cl[j] != (j ? cl[j - 1] : prev)) last = pos0 + j;
+  int tot = 0;
+  int rs = block_exclusive_scan<true>(last, gl->scan, &tot);
+  // group starts: run starts and every eighth position inside a run
+  int cnt = 0;
+  unsigned gm = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < K && pos0 + j < P) {
+      if (cl[j] != (j ? cl[j - 1] : prev)) rs = pos0 + j;
+      if (((pos0 + j - rs) & 7) == 0) {
+        gm |= 1u << j;
+        ++cnt;
+      }
+    }
+  int G = 0;
+  int at = block_exclusive_scan<false>(cnt, gl->scan + 4, &G);
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if ((gm >> j) & 1u) {
+      if (at < kGroupMax) gl->start[at] = (unsigned short)(pos0 + j);
+      ++at;
+    }
+  if (tid == 0 && G <= kGroupMax) gl->start[G] = (unsigned short)(P > 0 ? P : 0);
+  if (tid < kGroupSlots) gl->off[tid] = group_slot_offset(tid, T1, T2, tn);
+  __syncthreads();
+  return G;
+}
+
+// Group deposit (every lane of the wavefront calls it, in a grouped chunk):
+// sums the frame-fitting particles of each 8-lane group and adds the totals
+// to the LDS tile.  The first level pairs points whose values differ in one
+// factor (a half-point index or a node), so each lane forms the member it
+// keeps and the member it sends directly and sums them in one DPP add.
+// Returns whether this lane's particle still has to be deposited (by the
+// rounds, then directly).
+template <typename Real>
+__device__ __forceinline__ bool deposit_groups(bool active, const Moved<Real> &m, const PushParams<Real> &q,
+                                               const Sink<Real> &sk, const int *goff) {
+  const int lane = threadIdx.x & 63;
+  const bool fits = active && m.base[0] == -1 && m.base[1] == -1 && m.base[2] == -1 && m.DS[1][3] == Real(0) &&
+                    m.DS[2][3] == Real(0);
+  // frame origin (cell - 1 on every axis) as a tile index, from the group's
+  // first lane (its particle is the run's first; dead runs give -1)
+  int fb = -1;
+  if (active) fb = (m.c[0] - 1 - sk.t1) + sk.T1 * ((m.c[1] - 1 - sk.t2) + sk.T2 * (m.c[2] - 1 - sk.t3));
+  fb = __builtin_amdgcn_ds_swizzle(fb, 0x18);  // lane & ~7 within each 32-lane half
+
+  const Real z = fits ? Real(1) : Real(0);
+  Real c1[3], F2[2], F3[2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c1[a] = z * q.f1 * m.cum[0][a];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    F2[h] = z * q.f2 * m.cum[1][h];
+    F3[h] = z * q.f3 * m.cum[2][h];
+  }
+  Real P2[3], Q2[3], P3[3], Q3[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    P2[k] = m.S0[1][k] + Real(0.5) * m.DS[1][k];
+    Q2[k] = Real(0.5) * m.S0[1][k] + Real(1.0 / 3.0) * m.DS[1][k];
+    P3[k] = m.S0[2][k] + Real(0.5) * m.DS[2][k];
+    Q3[k] = Real(0.5) * m.S0[2][k] + Real(1.0 / 3.0) * m.DS[2][k];
+  }
+  // first level, over the row half-mirror (lane k <-> 7 - k of each group):
+  // lanes 0..3 keep the first members, lanes 4..7 the second
+  const bool up = (lane & 4) != 0;
+  auto hm = [](Real x) { return mirror8(x); };
+  Real r[39];
+  {
+    const Real fk = up ? F2[1] : F2[0], fs = up ? F2[0] : F2[1];
+    const Real gk = up ? F3[1] : F3[0], gs = up ? F3[0] : F3[1];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const Real w2 = m.S0[0][a] * P3[k] + m.DS[0][a] * Q3[k];
+        r[a + 4 * k] = fk * w2 + hm(fs * w2);
+        const Real w3 = m.S0[0][a] * P2[k] + m.DS[0][a] * Q2[k];
+        r[12 + a + 4 * k] = gk * w3 + hm(gs * w3);
+      }
+    }
+  }
+  {
+    const Real Pk = up ? P3[2] : P3[0], Qk = up ? Q3[2] : Q3[0];
+    const Real Ps = up ? P3[0] : P3[2], Qs = up ? Q3[0] : Q3[2];
+#pragma unroll
+    for (int a2 = 0; a2 < 3; ++a2) {
+      const Real wk = m.S0[1][a2] * Pk + m.DS[1][a2] * Qk, ws = m.S0[1][a2] * Ps + m.DS[1][a2] * Qs;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) r[24 + a + 3 * a2] = c1[a] * wk + hm(c1[a] * ws);
+    }
+    const Real Sk = up ? m.S0[1][2] : m.S0[1][0], Dk = up ? m.DS[1][2] : m.DS[1][0];
+    const Real Ss = up ? m.S0[1][0] : m.S0[1][2], Ds = up ? m.DS[1][0] : m.DS[1][2];
+    const Real wk = Sk * P3[1] + Dk * Q3[1], ws = Ss * P3[1] + Ds * Q3[1];
+    const Real w11 = m.S0[1][1] * P3[1] + m.DS[1][1] * Q3[1];
+    const Real w11k = up ? Real(0) : w11, w11s = up ? w11 : Real(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r[33 + a] = c1[a] * wk + hm(c1[a] * ws);
+      r[36 + a] = c1[a] * w11k + hm(c1[a] * w11s);
+    }
+  }
+  // second and third levels: lane ^ 1 (39 -> 20 values), lane ^ 2 (-> 10)
+  int off = 0;
+  rs_level<Real, 39, 1>(r, lane, off);
+  rs_level<Real, 20, 2>(r, lane, off);
+  if (fb >= 0) {
+    double *base = sk.tile_d + fb;
+    const int *lo = goff + (lane & 7) * 10;
+#pragma unroll
+    for (int u = 0; u < 10; ++u) lds_add(base + lo[u], (double)r[u]);
+  }
+  return active && !fits;
+}
+
+// One workgroup's share of the particle phase: the particles at array
+// indices [chunk0, chunk1), K = ceil((chunk1 - chunk0) / 256) per thread.
+// tile_raw: TILE bytes of LDS, box: kChunkBoxInts ints of LDS; *mybox receives
+// the chunk's deposit box.  With W = 4 (tile-sorted 3D species) gl is the LDS
+// of the cell groups: a chunk of at most 2048 particles whose current fits
+// the LDS tile in FP64 and whose runs of equal cells make at most 32 (K + 1)
+// groups of <= 8 particles is walked group by group (ceil(groups / 32)
+// iterations), others 256 particles per iteration in array order.
 template <typename Real, int DIM, int W = 2, int TILE = kTileBytes>
 __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
-                                           const Particles<Real> &p, const PushParams<Real> &q, int K,
-                                           long long chunk, JBox *mybox, int *err, unsigned char *tile_raw,
-                                           int *box) {
+                                           const Particles<Real> &p, const PushParams<Real> &q, long long chunk0,
+                                           long long chunk1, JBox *mybox, int *err, unsigned char *tile_raw,
+                                           int *box, GroupLds *gl = nullptr) {
   Real *tile = reinterpret_cast<Real *>(tile_raw);
-  const long long chunk0 = chunk * kPushBlock * K;
+  if (chunk1 > p.n) chunk1 = p.n;
+  if (chunk0 > chunk1) chunk0 = chunk1;
+  const int P = (int)(chunk1 - chunk0);
+  const int K = (P + kPushBlock - 1) / kPushBlock;
   const int tid = threadIdx.x;
 
   // wave priorities by phase: the box and staging passes (between
@@ -528,7 +757,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const long long i = chunk0 + (long long)(k0 + j) * kPushBlock + tid;
-        cells[j] = (k0 + j < K && i < p.n) ? p.cell[i] : -1;
+        cells[j] = (k0 + j < K && i < chunk1) ? p.cell[i] : -1;
       }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -605,6 +834,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
   sk.J[1] = f.J2;
   sk.J[2] = f.J3;
   sk.tile = nullptr;
+  sk.tile_d = nullptr;
   sk.t1 = box[0] - 2;
   sk.t2 = box[2] - 2;
   sk.t3 = DIM == 3 ? box[4] - 2 : 0;
@@ -613,12 +843,16 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
   if (box[0] != INT_MAX) {
     const long long T1 = (long long)box[1] - box[0] + 5, T2 = (long long)box[3] - box[2] + 5;
     const long long T3 = DIM == 3 ? (long long)box[5] - box[4] + 5 : 1;
-    if (9 * T1 * T2 * T3 * (long long)sizeof(Real) <= TILE) {
+    // FP32 runs: current in FP64 words when they fit
+    const bool j64 = sizeof(Real) == 4 && 12 * T1 * T2 * T3 * (long long)sizeof(Real) <= TILE;
+    if (j64 || 9 * T1 * T2 * T3 * (long long)sizeof(Real) <= TILE) {
       sk.T1 = (int)T1;
       sk.T2 = (int)T2;
       sk.T3 = (int)T3;
       sk.tn = (int)(T1 * T2 * T3);
       sk.tile = tile;
+      if (j64) sk.tile_d = reinterpret_cast<double *>(tile_raw);
+      Real *fE = tile + (j64 ? 6 : 3) * sk.tn;
       // J part cleared; E and B^n staged for the gather (zero outside the
       // window), one tile cell per thread and pass
       const int tn = sk.tn;
@@ -637,24 +871,53 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
           v[4] = Real(0.5) * (f.B2[id] + Bh.B2[id]);
           v[5] = Real(0.5) * (f.B3[id] + Bh.B3[id]);
         }
+        if (j64) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) tile[k * tn + r] = Real(0);
+          for (int k = 0; k < 3; ++k) sk.tile_d[k * tn + r] = 0.0;
+        } else {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) tile[(3 + k) * tn + r] = v[k];
+          for (int k = 0; k < 3; ++k) tile[k * tn + r] = Real(0);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) fE[k * tn + r] = v[k];
       }
     }
   }
   __syncthreads();
   const bool lds_fields = sk.tile != nullptr;
+  // cell groups: the chunk's runs of equal cells in pieces of <= 8
+  int nit = K, G = 0;
+  bool grouped = false;
+  if constexpr (W == 4 && DIM == 3) {
+    if (lds_fields) {
+      if (K <= 8) G = build_groups<Real>(p, chunk0, P, sk.T1, sk.T2, sk.tn, gl);
+      grouped = sk.tile_d != nullptr && K <= 8 && G > 0 && G <= 32 * (K + 1);
+      if (grouped) nit = (G + 31) / 32;
+    }
+  }
+  // array index of this thread's particle in iteration it (-1: none)
+  auto index_of = [&](int it) -> long long {
+    if constexpr (W == 4 && DIM == 3) {
+      if (grouped) {
+        const int gi = it * 32 + (tid >> 3);
+        if (gi >= G) return -1;
+        const int s0 = gl->start[gi], e0 = gl->start[gi + 1], k8 = tid & 7;
+        return s0 + k8 < e0 ? chunk0 + s0 + k8 : -1;
+      }
+    }
+    const long long i = chunk0 + (long long)it * kPushBlock + tid;
+    return i < chunk1 ? i : -1;
+  };
 
   __builtin_amdgcn_s_setprio(0);
-  // ---- gather, push, move and deposit, K particles per thread; the next
-  // particle's state is loaded while the current one is pushed
+  // ---- gather, push, move and deposit, K particles per thread (grouped:
+  // one per group member); the next particle's state is loaded while the
+  // current one is pushed
   int nx_cell = -1;
   Real nx_o[3] = {Real(0), Real(0), Real(0)}, nx_u[3] = {Real(0), Real(0), Real(0)};
   auto load_state = [&](long long j) {
     nx_cell = -1;
-    if (j < p.n) {
+    if (j >= 0 && j < p.n) {
       nx_cell = p.cell[j];
       nx_o[0] = p.o1[j];
       nx_o[1] = p.o2[j];
@@ -664,12 +927,16 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       nx_u[2] = p.u3[j];
     }
   };
-  load_state(chunk0 + tid);
-  for (int k = 0; k < K; ++k) {
-    const long long i = chunk0 + (long long)k * kPushBlock + tid;
+  long long nx_i = index_of(0);
+  load_state(nx_i);
+  for (int k = 0; k < nit; ++k) {
+    const long long i = nx_i;
     const int packed = nx_cell;
     const Real o[3] = {nx_o[0], nx_o[1], nx_o[2]}, u0[3] = {nx_u[0], nx_u[1], nx_u[2]};
-    if (k + 1 < K) load_state(i + kPushBlock);
+    if (k + 1 < nit) {
+      nx_i = index_of(k + 1);
+      load_state(nx_i);
+    }
     const bool active = packed >= 0;
     Moved<Real> m;
 #pragma unroll
@@ -708,7 +975,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
         sl.h1lo = bH[0] < c1;
         sl.h2lo = bH[1] < c2;
         sl.h3lo = DIM == 3 && bH[2] < c3;
-        const Real *ft = tile + 3 * sk.tn;
+        const Real *ft = tile + (sk.tile_d ? 6 : 3) * sk.tn;
         E1 = interp_lds<Real, DIM, true, false, false>(sl, st.wN, st.wH, ft);
         E2 = interp_lds<Real, DIM, false, true, false>(sl, st.wN, st.wH, ft + sk.tn);
         E3 = interp_lds<Real, DIM, false, false, true>(sl, st.wN, st.wH, ft + 2 * sk.tn);
@@ -826,7 +1093,11 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
         p.u3[i] = un3;
       }
     }
-    if (deposit_wave<Real, DIM, W>(active, m, q, sk)) deposit_direct<Real, DIM>(m, q, sk);
+    bool rest = active;
+    if constexpr (W == 4 && DIM == 3) {
+      if (grouped) rest = deposit_groups<Real>(active, m, q, sk, gl->off);
+    }
+    if (deposit_wave<Real, DIM, W>(rest, m, q, sk)) deposit_direct<Real, DIM>(m, q, sk);
   }
 
   __builtin_amdgcn_s_setprio(1);
@@ -835,7 +1106,9 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
     __syncthreads();
     const FastDiv d1{(unsigned)box[6], box[7]}, d2{(unsigned)box[8], box[9]};
     for (int r = tid; r < sk.tn; r += kPushBlock) {
-      const Real v[3] = {tile[r], tile[sk.tn + r], tile[2 * sk.tn + r]};
+      Real v[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[k] = sk.tile_d ? (Real)sk.tile_d[k * sk.tn + r] : tile[k * sk.tn + r];
       if (v[0] == Real(0) && v[1] == Real(0) && v[2] == Real(0)) continue;
       const int q1 = (int)fdiv(d1, (unsigned)r), q2 = (int)fdiv(d2, (unsigned)q1);
       const int col = col_near(g, sk.t1 + r - q1 * sk.T1);

@@ -47,6 +47,19 @@ __device__ __forceinline__ double xor_lane(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// v of lane 7 - k within each aligned group of 8 lanes (lane = 8 j + k): the
+// DPP row half-mirror
+__device__ __forceinline__ float mirror8(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double mirror8(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x141, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x141, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Swap across rows (BIT 16) or halves (BIT 32): afterwards the lanes with the
 // bit clear hold (a, a of lane ^ BIT) and the lanes with it set hold
 // (b of lane ^ BIT, b), as (a, b).  Summing the pair gives the lane's share

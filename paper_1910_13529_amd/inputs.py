@@ -92,6 +92,23 @@ def uniform_particles(seed, npart, n, uth, ndim=3):
     return cell, off, u
 
 
+def cells_with_counts(seed, counts, uth):
+    """counts[i1, i2, (i3)] particles in each cell, uniform inside it; u ~
+    uth * N(0, 1) per component; returned in a random order (not
+    cell-sorted)."""
+    rng = np.random.default_rng(seed)
+    counts = np.asarray(counts, dtype=np.int64)
+    ndim = counts.ndim
+    idx = np.repeat(np.arange(counts.size), counts.ravel())
+    base = np.stack(np.unravel_index(idx, counts.shape), axis=1).astype(np.float64)
+    X = base + rng.uniform(-0.5, 0.5, base.shape)
+    X = np.minimum(X, base + 0.5 - 1e-6)
+    perm = rng.permutation(len(X))
+    cell, off = split_positions(X[perm])
+    u = uth * rng.standard_normal((len(X), 3))
+    return cell[:, :ndim], off[:, :ndim], u
+
+
 def random_fields(seed, shape, scale=1.0, ncomp=6):
     rng = np.random.default_rng(seed)
     return [scale * rng.standard_normal(shape) for _ in range(ncomp)]

@@ -349,3 +349,50 @@ def test_sort_key_order_by_density(ndim, precision, tol, ptol):
         assert alive.all() and float(np.abs(d).max()) < ptol and float(du.max()) < ptol
     g.close()
     o.close()
+
+
+@pytest.mark.parametrize("sort_every", [25, 2])
+def test_grouped_deposit_irregular_runs(sort_every):
+    # FP32 tile-sorted species whose cells hold irregular particle counts
+    # (most 8, some Poisson around 8, some 1-3, some 12-20 (runs cut into
+    # pieces of 8), and a sparse slab of 1-2 per cell at small x3), so push
+    # chunks (1024 particles, K = 4) are walked by cell groups over 4-5
+    # iterations, or in array order where their runs make more than 160
+    # groups; thermal momenta move a share of the particles across x1 and
+    # transverse cell faces each step (their lanes leave the group sums for
+    # the rounds or the direct path), and the steps between re-sorts split
+    # runs further.  Fields and particles against the oracle.
+    n, dx, dt = (64, 32, 32), (0.5, 1.0, 1.0), 0.2
+    rng = np.random.default_rng(31)
+    counts = np.full(n, 8, dtype=np.int64)
+    r = rng.uniform(size=n)
+    pois = rng.poisson(8.0, size=n)
+    few = rng.integers(1, 4, size=n)
+    many = rng.integers(12, 21, size=n)
+    counts = np.where(r < 0.3, np.maximum(pois, 1), counts)
+    counts = np.where((r >= 0.3) & (r < 0.4), few, counts)
+    counts = np.where((r >= 0.4) & (r < 0.5), many, counts)
+    counts[:, :, :6] = rng.integers(1, 3, size=(n[0], n[1], 6))
+    cell, off, u = inputs.cells_with_counts(32, counts, 0.3)
+    sp = (-1e-4, -1.0, cell, off, u, len(cell))
+    log("grouped deposit: %d particles in %d cells, sort every %d" % (len(cell), counts.size, sort_every))
+    g, o, ids = make_pair(3, n, dx, dt, TABLE1, False, [sp], precision="fp32")
+    g.set_sort_interval(sort_every)
+    steps = 5
+    g.step(steps)
+    o.step(steps)
+    errs = field_errors(g, o)
+    log("grouped deposit, sort every %d: fields %s" % (sort_every, errs))
+    assert max(errs.values()) < 1e-5, errs
+    xo, uo, ao = o.particles()
+    assert ao.all()
+    c, of, ug, alive = g.particles(ids[0], len(cell))
+    assert alive.all()
+    nn = np.asarray(n, dtype=np.float64)[None, :]
+    d = (c + of) - xo
+    d = (d + nn / 2) % nn - nn / 2
+    du = np.linalg.norm(ug - uo, axis=1) / np.maximum(np.linalg.norm(uo, axis=1), 1e-300)
+    log("  particles: max |dx| %.3g cells, max |du|/|u| %.3g" % (float(np.abs(d).max()), float(du.max())))
+    assert float(np.abs(d).max()) < 2e-5 and float(du.max()) < 2e-5
+    g.close()
+    o.close()
