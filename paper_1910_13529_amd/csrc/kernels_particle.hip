@@ -148,9 +148,12 @@ void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStr
 // ---- particle sort (cell order) ---------------------------------------------------
 
 // Sort key of a packed cell: with tiles = t > 0, cells are grouped in
-// 2^t x 4 x 4 (2D: 2^t x 4) tiles of storage cells, x1 fastest inside a tile,
-// so that a chunk of consecutive particles covers a compact 3D region (its
-// LDS box stays small when the particles fill the grid, as a plasma does);
+// 2^t x 4 x 4 (2D: 2^t x 4) tiles, x1 fastest inside a tile, so that a chunk
+// of consecutive particles covers a compact 3D region (its LDS box stays
+// small when the particles fill the grid, as a plasma does).  Tiles count x1
+// from the moving window's first cell, not from the ring buffer's first
+// storage column: a tile then never holds both ends of the window (whose
+// box would span it), and after later shifts its cells stay contiguous.
 // tiles = 0: the packed index itself.  Both are one-to-one on cells.
 template <typename Real>
 __global__ void k_sort_keys(Geo g, Particles<Real> p, int tiles, unsigned *keys, unsigned *idx) {
@@ -163,6 +166,8 @@ __global__ void k_sort_keys(Geo g, Particles<Real> p, int tiles, unsigned *keys,
     if (tiles > 0) {
       int s1, c2, c3;
       unpack_cell(g, c, s1, c2, c3);
+      s1 -= g.ws_mod;  // window x1
+      if (s1 < 0) s1 += g.n1;
       const unsigned w1 = 1u << tiles;
       const unsigned nt1 = ((unsigned)g.n1 + w1 - 1) >> tiles, nt2 = (unsigned)(g.n2 + 3) >> 2;
       const unsigned tile = ((unsigned)(c3 >> 2) * nt2 + (unsigned)(c2 >> 2)) * nt1 + ((unsigned)s1 >> tiles);
