@@ -159,7 +159,9 @@ relpic_status relpic_create(const relpic_grid *grid, const relpic_solver *solver
 relpic_status relpic_destroy(relpic_sim *sim);
 
 /* Add a particle species with charge-to-mass ratio q_over_m (electrons: -1),
- * charge Q of one macro-particle and room for `capacity` particles.
+ * charge Q of one macro-particle and room for `capacity` particles (at most
+ * 2^32 bytes per particle array: 2^30 particles in FP32, 2^29 in FP64;
+ * RELPIC_EINVAL beyond).
  * q_over_m = 0 gives a ballistic species: its momenta never change (no
  * force), it still deposits current, and its kinetic energy is not counted
  * in the diagnostics. */

@@ -719,7 +719,9 @@ relpic_status relpic_destroy(relpic_sim *sim) {
 relpic_status relpic_add_species(relpic_sim *s, double q_over_m, double Q, int64_t capacity, int *species_id) {
   return guarded("add_species", [&]() -> relpic_status {
     if (relpic_status r = check_sim(s)) return r;
-    if (!std::isfinite(q_over_m) || !std::isfinite(Q) || capacity < 0 || capacity > (1LL << 31))
+    // at most 2^32 bytes per particle array (the push addresses them with
+    // 32-bit offsets)
+    if (!std::isfinite(q_over_m) || !std::isfinite(Q) || capacity < 0 || capacity > (1LL << 32) / (int64_t)s->esz)
       return fail(RELPIC_EINVAL, "add_species: bad q/m, charge or capacity");
     Species sp;
     sp.qm = q_over_m;

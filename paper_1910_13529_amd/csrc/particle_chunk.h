@@ -41,6 +41,26 @@ __device__ __forceinline__ float lds_ld(const float *p) { return *(const lds_f32
 __device__ __forceinline__ double lds_ld(const double *p) { return *(const lds_f64 *)p; }
 
 
+// 1/sqrt(x) and 1/x for the Boris push: the hardware reciprocal square root
+// and reciprocal in FP32 (about one ulp, against the several instructions of
+// a correctly rounded division or square root), exact operations in FP64.
+template <typename Real>
+__device__ __forceinline__ Real push_rsqrt(Real x) {
+  return Real(1) / sqrt(x);
+}
+template <>
+__device__ __forceinline__ float push_rsqrt<float>(float x) {
+  return __builtin_amdgcn_rsqf(x);
+}
+template <typename Real>
+__device__ __forceinline__ Real push_rcp(Real x) {
+  return Real(1) / x;
+}
+template <>
+__device__ __forceinline__ float push_rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
 // quadratic B-spline weights at nodes -1, 0, +1 for a particle at offset d
 // from node 0 (d in [-1/2, 1/2])
 template <typename Real>
@@ -75,6 +95,14 @@ struct Stagger {
   unsigned rowN2[3], rowH2[3], rowN3[3], rowH3[3];
   Real wN[3][3], wH[3][3];
 };
+
+// Element j of a particle array through a 32-bit byte offset from its base
+// (a species holds at most 2^32 bytes per array), so loads and stores take
+// a scalar base and one vector offset.
+template <typename T>
+__device__ __forceinline__ T &el32(T *base, unsigned j) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + j * (unsigned)sizeof(T));
+}
 
 // Load element `id` through a 32-bit byte offset from the array base.
 template <typename Real>
@@ -918,13 +946,14 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
   auto load_state = [&](long long j) {
     nx_cell = -1;
     if (j >= 0 && j < p.n) {
-      nx_cell = p.cell[j];
-      nx_o[0] = p.o1[j];
-      nx_o[1] = p.o2[j];
-      if (DIM == 3) nx_o[2] = p.o3[j];
-      nx_u[0] = p.u1[j];
-      nx_u[1] = p.u2[j];
-      nx_u[2] = p.u3[j];
+      const unsigned jj = (unsigned)j;
+      nx_cell = el32(p.cell, jj);
+      nx_o[0] = el32(p.o1, jj);
+      nx_o[1] = el32(p.o2, jj);
+      if (DIM == 3) nx_o[2] = el32(p.o3, jj);
+      nx_u[0] = el32(p.u1, jj);
+      nx_u[1] = el32(p.u2, jj);
+      nx_u[2] = el32(p.u3, jj);
     }
   };
   long long nx_i = index_of(0);
@@ -1031,11 +1060,10 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       // relativistic Boris push
       const Real a = q.half_qmdt;
       const Real um1 = u0[0] + a * E1, um2 = u0[1] + a * E2, um3 = u0[2] + a * E3;
-      const Real gm = sqrt(Real(1) + um1 * um1 + um2 * um2 + um3 * um3);
-      const Real ag = a / gm;
+      const Real ag = a * push_rsqrt(Real(1) + um1 * um1 + um2 * um2 + um3 * um3);
       const Real t1 = ag * B1, t2 = ag * B2, t3 = ag * B3;
       const Real t2s = t1 * t1 + t2 * t2 + t3 * t3;
-      const Real f2 = Real(2) / (Real(1) + t2s);
+      const Real f2 = Real(2) * push_rcp(Real(1) + t2s);
       const Real s1v = f2 * t1, s2v = f2 * t2, s3v = f2 * t3;
       const Real up1 = um1 + (um2 * t3 - um3 * t2);
       const Real up2 = um2 + (um3 * t1 - um1 * t3);
@@ -1043,8 +1071,7 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       const Real un1 = um1 + (up2 * s3v - up3 * s2v) + a * E1;
       const Real un2 = um2 + (up3 * s1v - up1 * s3v) + a * E2;
       const Real un3 = um3 + (up1 * s2v - up2 * s1v) + a * E3;
-      const Real gn = sqrt(Real(1) + un1 * un1 + un2 * un2 + un3 * un3);
-      const Real ig = Real(1) / gn;
+      const Real ig = push_rsqrt(Real(1) + un1 * un1 + un2 * un2 + un3 * un3);
       if (!(un1 == un1) || !(un2 == un2) || !(un3 == un3)) atomicOr(err, 2);
 
       // x^{n+1} = x^n + dt u / gamma, in cell units, as cell + offset
@@ -1078,19 +1105,20 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
         const int after = n1c - q.shift;  // window cell after this step's shift
         if (after < 2 || after > g.n1 - 3) alive = false;
       }
+      const unsigned ii = (unsigned)i;
       if (!alive) {
-        p.cell[i] = -1;
+        el32(p.cell, ii) = -1;
       } else {
         const int ns1 = col_of(g, n1c);
         const int ns2 = wrap_near(c2 + sh[1], g.n2);
         const int ns3 = DIM == 3 ? wrap_near(c3 + sh[2], g.n3) : 0;
-        p.cell[i] = ns1 + g.n1 * (ns2 + g.n2 * ns3);
-        p.o1[i] = on[0];
-        p.o2[i] = on[1];
-        if (DIM == 3) p.o3[i] = on[2];
-        p.u1[i] = un1;
-        p.u2[i] = un2;
-        p.u3[i] = un3;
+        el32(p.cell, ii) = ns1 + g.n1 * (ns2 + g.n2 * ns3);
+        el32(p.o1, ii) = on[0];
+        el32(p.o2, ii) = on[1];
+        if (DIM == 3) el32(p.o3, ii) = on[2];
+        el32(p.u1, ii) = un1;
+        el32(p.u2, ii) = un2;
+        el32(p.u3, ii) = un3;
       }
     }
     bool rest = active;
