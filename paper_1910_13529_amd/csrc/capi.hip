@@ -123,6 +123,8 @@ long long window_target(const relpic_sim *s, long long steps_done) {
 // chunks then straddle no tile seams).  Mean particles per occupied cell
 // below kTileBelow switches to tiles, above kRowsAbove back to rows.
 constexpr double kTileBelow = 64.0, kRowsAbove = 128.0;
+// largest key space sorted by counting (4 bytes per bucket)
+constexpr long long kCountingSortMaxKeys = 1LL << 28;
 constexpr long long kMinPushChunks = 512;
 
 // Sort a species by cell (dropped particles last), drop the dropped ones,
@@ -140,14 +142,43 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
   // tile x1 width 2^tx: FP64 tiles are half as wide (LDS holds half the cells)
   const int tx = sizeof(Real) == 8 ? 2 : 3;
   launch_sort_keys<Real>(g, src, tiles ? tx : 0, sp.keys, sp.idx, s->st);
-  size_t need = 0;
-  HIP_OK(sort_pairs(nullptr, need, sp.keys, sp.keys2, sp.idx, sp.idx2, sp.n, s->st));
-  if (need > sp.sort_tmp_bytes) {
-    sp.sort_tmp = dev_alloc(s, need);
-    if (!sp.sort_tmp) return fail(RELPIC_ENOMEM, "sort: temporary storage allocation failed");
-    sp.sort_tmp_bytes = need;
+  unsigned long long *cnt = (unsigned long long *)(s->dbuf + 6);
+  unsigned long long *runs = (unsigned long long *)(s->dbuf + 7);
+  HIP_OK(hipMemsetAsync(s->dbuf + 6, 0, 2 * sizeof(double), s->st));
+  // key space: the cells in tile order, or the packed cell index
+  long long nkeys = g.N;
+  if (tiles) {
+    const long long nt1 = (g.n1 + (1 << tx) - 1) >> tx, nt2 = (g.n2 + 3) / 4, nt3 = g.n3 > 1 ? (g.n3 + 3) / 4 : 1;
+    nkeys = nt1 * nt2 * nt3 * ((long long)(g.n3 > 1 ? 16 : 4) << tx);
   }
-  HIP_OK(sort_pairs(sp.sort_tmp, need, sp.keys, sp.keys2, sp.idx, sp.idx2, sp.n, s->st));
+  // counting sort (hand-written, two passes over the keys) when the buckets
+  // fit; radix sort of the whole key otherwise
+  const bool counting = nkeys <= kCountingSortMaxKeys;
+  if (counting) {
+    const long long nb = key_scan_blocks((unsigned)nkeys);
+    if (nkeys > s->kcount_cap) {
+      s->kcount = (unsigned *)dev_alloc(s, sizeof(unsigned) * (size_t)nkeys);
+      if (!s->kcount) return fail(RELPIC_ENOMEM, "sort: bucket allocation failed");
+      s->kcount_cap = nkeys;
+    }
+    if (nb > s->kblocks_cap) {
+      s->kbsum = (unsigned long long *)dev_alloc(s, sizeof(unsigned long long) * (size_t)nb);
+      s->kbocc = (unsigned *)dev_alloc(s, sizeof(unsigned) * (size_t)nb);
+      if (!s->kbsum || !s->kbocc) return fail(RELPIC_ENOMEM, "sort: scan scratch allocation failed");
+      s->kblocks_cap = nb;
+    }
+    HIP_OK(hipMemsetAsync(s->kcount, 0, sizeof(unsigned) * (size_t)nkeys, s->st));
+    launch_key_sort(sp.keys, sp.n, (unsigned)nkeys, s->kcount, s->kbsum, s->kbocc, cnt, sp.keys2, sp.idx2, s->st);
+  } else {
+    size_t need = 0;
+    HIP_OK(sort_pairs(nullptr, need, sp.keys, sp.keys2, sp.idx, sp.idx2, sp.n, s->st));
+    if (need > sp.sort_tmp_bytes) {
+      sp.sort_tmp = dev_alloc(s, need);
+      if (!sp.sort_tmp) return fail(RELPIC_ENOMEM, "sort: temporary storage allocation failed");
+      sp.sort_tmp_bytes = need;
+    }
+    HIP_OK(sort_pairs(sp.sort_tmp, need, sp.keys, sp.keys2, sp.idx, sp.idx2, sp.n, s->st));
+  }
   Particles<Real> dst = src;
   dst.cell = sp.cell2;
   dst.o1 = (Real *)sp.o2[0];
@@ -156,11 +187,10 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
   dst.u1 = (Real *)sp.u2[0];
   dst.u2 = (Real *)sp.u2[1];
   dst.u3 = (Real *)sp.u2[2];
-  unsigned long long *cnt = (unsigned long long *)(s->dbuf + 6);
-  unsigned long long *runs = (unsigned long long *)(s->dbuf + 7);
-  HIP_OK(hipMemsetAsync(s->dbuf + 6, 0, 2 * sizeof(double), s->st));
-  launch_permute<Real>(src, dst, sp.id, sp.id2, sp.idx2, s->ndim, s->st);
-  launch_count_runs(sp.keys2, sp.n, runs, cnt, s->st);
+  // the counting sort leaves the alive count in cnt[0] and the distinct
+  // cells in cnt[1]; the radix sort keeps the dropped particles (last)
+  launch_permute<Real>(src, dst, sp.id, sp.id2, sp.idx2, s->ndim, s->st, counting ? cnt : nullptr);
+  if (!counting) launch_count_runs(sp.keys2, sp.n, runs, cnt, s->st);
   unsigned long long h[2] = {0, 0};
   HIP_OK(hipMemcpyAsync(h, s->dbuf + 6, sizeof(h), hipMemcpyDeviceToHost, s->st));
   HIP_OK(hipStreamSynchronize(s->st));

@@ -99,6 +99,11 @@ struct relpic_sim {
   long long sort_interval = 25;  // re-sort every this many steps (0: only after loads)
   int *err = nullptr;
   double *dbuf = nullptr;      // diagnostics accumulators (8 doubles)
+  // counting sort of the particle keys: bucket counts and scan scratch
+  unsigned *kcount = nullptr;
+  unsigned long long *kbsum = nullptr;
+  unsigned *kbocc = nullptr;
+  long long kcount_cap = 0, kblocks_cap = 0;
   double *rho = nullptr;       // FP64 scratch for the Gauss diagnostic
   double *rho_bg = nullptr;    // background charge, storage layout
   double *gather_buf = nullptr;  // FP64 staging of fields gathered at particles (diagnostic)

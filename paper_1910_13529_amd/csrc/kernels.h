@@ -99,14 +99,25 @@ void launch_sort_keys(const Geo &g, const Particles<Real> &p, int tiles, unsigne
                       hipStream_t st);
 // whether the tiled sort keys (any t <= 3) fit in 32 bits on this grid
 bool sort_tiles_fit(const Geo &g);
+// dst[j] = src[perm[j]] for j below src.n and, when count is given, below
+// *count (device word)
 template <typename Real>
 void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, const int *id_src, int *id_dst,
-                    const unsigned *perm, int ndim, hipStream_t st);
+                    const unsigned *perm, int ndim, hipStream_t st, const unsigned long long *count = nullptr);
 // index range of each sort tile (key >> shift) among the n alive particles
 // of a tile-sorted key array; first, end: ntiles ints each, cleared by the
 // caller
 void launch_tile_ranges(const unsigned *keys, long long n, int shift, long long ntiles, int *first, int *end,
                         hipStream_t st);
+// Counting sort of (key, index) pairs with keys below nkeys (others, the
+// dropped particles, left out): keys_out / idx_out receive the totals[0]
+// alive pairs in key order (unordered inside a key), totals[1] = distinct
+// keys.  count: nkeys words cleared by the caller (left holding the bucket
+// ends); bsum, bocc: key_scan_blocks(nkeys) entries of scratch.
+long long key_scan_blocks(unsigned nkeys);
+void launch_key_sort(const unsigned *keys, long long n, unsigned nkeys, unsigned *count, unsigned long long *bsum,
+                     unsigned *bocc, unsigned long long *totals, unsigned *keys_out, unsigned *idx_out,
+                     hipStream_t st);
 // sorted keys: distinct alive cells added to *runs, alive count written to *alive
 void launch_count_runs(const unsigned *keys, long long n, unsigned long long *runs, unsigned long long *alive,
                        hipStream_t st);

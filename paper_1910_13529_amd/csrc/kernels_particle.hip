@@ -147,6 +147,185 @@ void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStr
 
 // ---- particle sort (cell order) ---------------------------------------------------
 
+// Counting sort of the particles by cell key (keys below nkeys; dropped
+// particles carry 0xFFFFFFFF and are left out): a histogram of the keys, an
+// exclusive scan of it (bucket starts, the alive count and the occupied
+// cells), and a scatter of each particle index to its bucket.  The array is
+// mostly in order already (re-sorted every few steps), so a wavefront's
+// lanes come in runs of equal keys: the first lane of a run adds the run's
+// length to the histogram and claims its slots in one atomic each.  Order
+// inside a bucket follows the atomics (not stable).
+
+// Runs of equal valid keys in the wavefront: bit l of *heads marks a lane
+// that starts a run; returns the run length for such a lane.
+__device__ __forceinline__ int wave_run(unsigned k, bool valid, unsigned long long *heads) {
+  const int lane = threadIdx.x & 63;
+  const unsigned prev = __shfl_up(k, 1, 64);
+  const bool prev_valid = __shfl_up(valid ? 1 : 0, 1, 64) != 0;
+  const bool head = valid && (lane == 0 || !prev_valid || prev != k);
+  const unsigned long long hm = __ballot(head), invalid = __ballot(!valid);
+  *heads = hm;
+  // the run ends at the next head or invalid lane above this one
+  const unsigned long long above = (hm | invalid) & (lane == 63 ? 0ULL : (~0ULL << (lane + 1)));
+  return above ? (__ffsll((long long)above) - 1 - lane) : (64 - lane);
+}
+
+__global__ __launch_bounds__(256) void k_key_hist(const unsigned *keys, long long n, unsigned nkeys,
+                                                  unsigned *count) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  const unsigned k = i < n ? keys[i] : 0xFFFFFFFFu;
+  const bool valid = k < nkeys;
+  unsigned long long heads;
+  const int len = wave_run(k, valid, &heads);
+  if (valid && ((heads >> (threadIdx.x & 63)) & 1ULL)) atomicAdd(count + k, (unsigned)len);
+}
+
+// Scan, phase 1: sums and occupied buckets of each 4096-bucket block.
+constexpr int kScanPer = 16;                 // buckets per thread
+constexpr int kScanBlock = 256 * kScanPer;   // buckets per workgroup
+
+__global__ __launch_bounds__(256) void k_key_scan_blocks(const unsigned *count, unsigned nkeys,
+                                                         unsigned long long *bsum, unsigned *bocc) {
+  __shared__ unsigned long long ps[4];
+  __shared__ unsigned po[4];
+  const long long k0 = blockIdx.x * (long long)kScanBlock + threadIdx.x * (long long)kScanPer;
+  unsigned long long sum = 0;
+  unsigned occ = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    const unsigned c = k0 + j < nkeys ? count[k0 + j] : 0u;
+    sum += c;
+    occ += c != 0u;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sum += __shfl_xor(sum, o, 64);
+    occ += __shfl_xor(occ, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    ps[threadIdx.x >> 6] = sum;
+    po[threadIdx.x >> 6] = occ;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.x] = ps[0] + ps[1] + ps[2] + ps[3];
+    bocc[blockIdx.x] = po[0] + po[1] + po[2] + po[3];
+  }
+}
+
+// Scan, phase 2 (one workgroup of 1024 threads): exclusive prefix of the
+// block sums in place; totals[0] = alive particles, totals[1] = occupied
+// buckets.
+__global__ __launch_bounds__(1024) void k_key_scan_top(unsigned long long *bsum, const unsigned *bocc,
+                                                       long long nb, unsigned long long *totals) {
+  __shared__ unsigned long long wsum[16];
+  __shared__ unsigned long long wocc[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const long long per = (nb + 1023) / 1024;
+  const long long b0 = t * per;
+  unsigned long long s = 0, occ = 0;
+  for (long long j = 0; j < per; ++j)
+    if (b0 + j < nb) {
+      s += bsum[b0 + j];
+      occ += bocc[b0 + j];
+    }
+  // inclusive scan of s over the workgroup
+  unsigned long long x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  unsigned long long oc = occ;
+  for (int o = 32; o > 0; o >>= 1) oc += __shfl_xor(oc, o, 64);
+  if (lane == 63) wsum[w] = x;
+  if (lane == 0) wocc[w] = oc;
+  __syncthreads();
+  unsigned long long pre = 0, tot = 0, totocc = 0;
+  for (int j = 0; j < 16; ++j) {
+    if (j < w) pre += wsum[j];
+    tot += wsum[j];
+    totocc += wocc[j];
+  }
+  unsigned long long run = pre + x - s;  // exclusive prefix of this thread's first block
+  for (long long j = 0; j < per; ++j)
+    if (b0 + j < nb) {
+      const unsigned long long v = bsum[b0 + j];
+      bsum[b0 + j] = run;
+      run += v;
+    }
+  if (t == 0) {
+    totals[0] = tot;
+    totals[1] = totocc;
+  }
+}
+
+// Scan, phase 3: bucket starts (exclusive prefix) written over the counts.
+__global__ __launch_bounds__(256) void k_key_scan_apply(unsigned *count, unsigned nkeys,
+                                                        const unsigned long long *bsum) {
+  __shared__ unsigned ws[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const long long k0 = blockIdx.x * (long long)kScanBlock + t * (long long)kScanPer;
+  unsigned c[kScanPer], s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    c[j] = k0 + j < nkeys ? count[k0 + j] : 0u;
+    s += c[j];
+  }
+  unsigned x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) ws[w] = x;
+  __syncthreads();
+  unsigned pre = 0;
+  for (int j = 0; j < w; ++j) pre += ws[j];
+  unsigned run = (unsigned)bsum[blockIdx.x] + pre + x - s;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j)
+    if (k0 + j < nkeys) {
+      count[k0 + j] = run;
+      run += c[j];
+    }
+}
+
+// Scatter: particle i to the next free slot of its bucket; sorted keys and
+// indices out.
+__global__ __launch_bounds__(256) void k_key_scatter(const unsigned *keys, long long n, unsigned nkeys,
+                                                     unsigned *cursor, unsigned *keys_out, unsigned *idx_out) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  const unsigned k = i < n ? keys[i] : 0xFFFFFFFFu;
+  const bool valid = k < nkeys;
+  unsigned long long heads;
+  const int len = wave_run(k, valid, &heads);
+  const int lane = threadIdx.x & 63;
+  unsigned base = 0;
+  if (valid && ((heads >> lane) & 1ULL)) base = atomicAdd(cursor + k, (unsigned)len);
+  // the run's first lane: the highest head at or below this lane
+  const unsigned long long below = heads & (lane == 63 ? ~0ULL : ((2ULL << lane) - 1));
+  const int hl = below ? 63 - __clzll((long long)below) : lane;
+  base = __shfl(base, hl, 64);
+  if (valid) {
+    const unsigned dst = base + (unsigned)(lane - hl);
+    keys_out[dst] = k;
+    idx_out[dst] = (unsigned)i;
+  }
+}
+
+long long key_scan_blocks(unsigned nkeys) { return ((long long)nkeys + kScanBlock - 1) / kScanBlock; }
+
+void launch_key_sort(const unsigned *keys, long long n, unsigned nkeys, unsigned *count, unsigned long long *bsum,
+                     unsigned *bocc, unsigned long long *totals, unsigned *keys_out, unsigned *idx_out,
+                     hipStream_t st) {
+  const long long nb = key_scan_blocks(nkeys);
+  const unsigned pgrid = (unsigned)((n + 255) / 256);
+  if (n > 0) k_key_hist<<<pgrid, 256, 0, st>>>(keys, n, nkeys, count);
+  k_key_scan_blocks<<<(unsigned)nb, 256, 0, st>>>(count, nkeys, bsum, bocc);
+  k_key_scan_top<<<1, 1024, 0, st>>>(bsum, bocc, nb, totals);
+  k_key_scan_apply<<<(unsigned)nb, 256, 0, st>>>(count, nkeys, bsum);
+  if (n > 0) k_key_scatter<<<pgrid, 256, 0, st>>>(keys, n, nkeys, count, keys_out, idx_out);
+}
+
+
 // Sort key of a packed cell: with tiles = t > 0, cells are grouped in
 // 2^t x 4 x 4 (2D: 2^t x 4) tiles, x1 fastest inside a tile, so that a chunk
 // of consecutive particles covers a compact 3D region (its LDS box stays
@@ -181,9 +360,9 @@ __global__ void k_sort_keys(Geo g, Particles<Real> p, int tiles, unsigned *keys,
 
 template <typename Real>
 __global__ void k_permute(Particles<Real> src, Particles<Real> dst, const int *id_src, int *id_dst,
-                          const unsigned *perm, int ndim) {
+                          const unsigned *perm, int ndim, const unsigned long long *count) {
   const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (j >= src.n) return;
+  if (j >= src.n || (count && (unsigned long long)j >= *count)) return;
   const long long i = perm[j];
   const int c = src.cell[i];
   dst.cell[j] = c;
@@ -240,9 +419,9 @@ void launch_sort_keys(const Geo &g, const Particles<Real> &p, int tiles, unsigne
 
 template <typename Real>
 void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, const int *id_src, int *id_dst,
-                    const unsigned *perm, int ndim, hipStream_t st) {
+                    const unsigned *perm, int ndim, hipStream_t st, const unsigned long long *count) {
   if (src.n <= 0) return;
-  k_permute<Real><<<(unsigned)((src.n + 255) / 256), 256, 0, st>>>(src, dst, id_src, id_dst, perm, ndim);
+  k_permute<Real><<<(unsigned)((src.n + 255) / 256), 256, 0, st>>>(src, dst, id_src, id_dst, perm, ndim, count);
 }
 
 #define RELPIC_INST_PART(Real)                                                                                   \
@@ -252,7 +431,7 @@ void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, cons
   template void launch_sort_keys<Real>(const Geo &, const Particles<Real> &, int, unsigned *, unsigned *,        \
                                        hipStream_t);                                                             \
   template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \
-                                     const unsigned *, int, hipStream_t);
+                                     const unsigned *, int, hipStream_t, const unsigned long long *);
 
 RELPIC_INST_PART(float)
 RELPIC_INST_PART(double)
