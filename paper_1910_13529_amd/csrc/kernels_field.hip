@@ -316,13 +316,28 @@ __global__ __launch_bounds__(256) void k_jcorr_rows(Geo g, const Real *J1, Real 
   for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
     const int i2 = b.lo[1] + (int)(r % w2), i3 = b.lo[2] + (int)(r / w2);
     const long long row = (long long)g.n1 * (i2 + (long long)g.n2 * i3);
-    for (int t = threadIdx.x; t < W + 2 * ng; t += blockDim.x) line[t] = ldc(J1, row, col_of(g, lo1 - ng + t));
+    // one cell past the last tap of the last output: an odd W's second
+    // output of the last pair reads it (and is not stored)
+    for (int t = threadIdx.x; t < W + 2 * ng + 1; t += blockDim.x) line[t] = ldc(J1, row, col_of(g, lo1 - ng + t));
     __syncthreads();
-    for (int t = threadIdx.x; t < W; t += blockDim.x) {
+    // two neighbouring outputs j, j + 1 per thread: per tap m the pair reads
+    // c[j - m] and c[j + 1 + m] and takes c[j + m], c[j + 1 - m] from the
+    // previous tap, so each LDS word read serves both outputs
+    for (int t = 2 * threadIdx.x; t < W; t += 2 * blockDim.x) {
       const Real *c = line + ng + t;
-      Real acc = taps[0] * c[0];
-      for (int m = 1; m <= ng; ++m) acc += taps[m] * (c[-m] + c[m]);
-      J1c[row + col_of(g, lo1 + t)] = acc;
+      Real a0 = taps[0] * c[0], a1 = taps[0] * c[1];
+      Real lprev = c[0], rprev = c[1];
+#pragma unroll 4
+      for (int m = 1; m <= ng; ++m) {
+        const Real l = c[-m], r = c[1 + m];
+        const Real tm = taps[m];
+        a0 += tm * (l + rprev);
+        a1 += tm * (lprev + r);
+        lprev = l;
+        rprev = r;
+      }
+      J1c[row + col_of(g, lo1 + t)] = a0;
+      if (t + 1 < W) J1c[row + col_of(g, lo1 + t + 1)] = a1;
     }
     __syncthreads();
   }
@@ -611,7 +626,7 @@ void launch_jcorr(const Geo &g, const Real *J1, Real *J1c, const Real *taps, int
                   hipStream_t st) {
   // a whole x1 line and its taps in LDS when they fit (the box's x1 range
   // is at most n1 after widening)
-  const size_t lds = sizeof(Real) * (size_t)(g.n1 + 2 * ng);
+  const size_t lds = sizeof(Real) * (size_t)(g.n1 + 2 * ng + 1);
   if (lds <= 32768)
     k_jcorr_rows<Real><<<4096, 256, lds, st>>>(g, J1, J1c, taps, ng, box);
   else
