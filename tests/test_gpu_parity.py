@@ -351,6 +351,18 @@ def test_sort_key_order_by_density(ndim, precision, tol, ptol):
     o.close()
 
 
+@pytest.mark.parametrize("precision,limit", [("fp32", 1 << 30), ("fp64", 1 << 29)])
+def test_species_capacity_limit(precision, limit):
+    # the push addresses each particle array with 32-bit byte offsets, so a
+    # species holds at most 2^32 bytes per array; the check happens before
+    # any allocation (the limit itself is not allocated here)
+    from paper_1910_13529_amd.relpic import RelpicError, Sim
+    g = Sim(dict(ndim=3, n=(16, 8, 8), dx=(1.0, 1.0, 1.0), dt=0.3), precision=precision)
+    with pytest.raises(RelpicError):
+        g.add_species(-1.0, -1e-3, limit + 1)
+    g.add_species(-1.0, -1e-3, 1024)
+    g.close()
+
 @pytest.mark.parametrize("sort_every", [25, 2])
 def test_grouped_deposit_irregular_runs(sort_every):
     # FP32 tile-sorted species whose cells hold irregular particle counts
