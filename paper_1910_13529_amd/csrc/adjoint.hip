@@ -157,8 +157,8 @@ struct Ctx {
       }
       const Fields<Real> f = fields_with(E, bn);
       const HalfB<Real> Bh{bc[0], bc[1], bc[2]};
-      launch_push_deposit<Real>(2, g, f, Bh, parts<Real>(sp), push_params<Real>(s, sp, 0), pc, false, s->blockbox,
-                                s->err, s->st);
+      launch_push_deposit<Real>(2, g, f, Bh, parts<Real>(sp), push_params<Real>(s, sp, 0), pc, false, false,
+                                s->blockbox, s->err, s->st);
       launch_merge_boxes(s->blockbox, nb, box, s->st);
     }
     const Fields<Real> f = fields_with(E, bn);

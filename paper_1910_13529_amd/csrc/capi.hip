@@ -123,6 +123,9 @@ long long window_target(const relpic_sim *s, long long steps_done) {
 // chunks then straddle no tile seams).  Mean particles per occupied cell
 // below kTileBelow switches to tiles, above kRowsAbove back to rows.
 constexpr double kTileBelow = 64.0, kRowsAbove = 128.0;
+// particles per occupied cell from which a tile-sorted FP32 species pushes
+// without the wavefront rounds (runs of 6 and more fill most of a cell group)
+constexpr double kLongRunsPpc = 6.0;
 // largest key space sorted by counting (4 bytes per bucket)
 constexpr long long kCountingSortMaxKeys = 1LL << 28;
 constexpr long long kMinPushChunks = 512;
@@ -135,6 +138,7 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
   sp.dirty = false;
   sp.sorted_at = s->step;
   sp.ntiles = sp.n_tiled = 0;
+  sp.long_runs = false;
   if (sp.n <= 1) return RELPIC_OK;
   Particles<Real> src = parts<Real>(sp);
   const Geo g = make_geo(s);
@@ -212,6 +216,9 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
     return do_sort<Real>(s, sp);
   }
   sp.ntiles = sp.n_tiled = 0;
+  // cells holding runs of several particles (a plasma at a few per cell):
+  // the cell groups take nearly every lane, the rest deposit directly
+  sp.long_runs = tiles && ppc >= kLongRunsPpc;
   if (tiles) {
     // chunks of 256 K particles, at most one tile's worth: a chunk then spans
     // parts of at most two x1-neighbouring tiles, whose cells with the
@@ -333,8 +340,8 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
       }
       {
         ProfScope ps(s, 0 + 64 * (int)(si + 1));
-        launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, pc, sp.tile_keys, s->blockbox, s->err,
-                                  s->st);
+        launch_push_deposit<Real>(s->ndim, g, f, Bh, parts<Real>(sp), q, pc, sp.tile_keys, sp.long_runs, s->blockbox,
+                                  s->err, s->st);
       }
       ProfScope ps(s, 6);
       launch_merge_boxes(s->blockbox, nb, box, s->st);

@@ -34,6 +34,7 @@ struct Species {
   long long sorted_at = 0;  // step of the last sort
   int K = 1;           // particles per thread in the push kernel
   bool tile_keys = false;  // sort key order: 3D tiles (sparse) or rows (dense)
+  bool long_runs = false;  // tile order and runs of several particles per cell
   // index ranges of the sort tiles after the last tile sort (push chunks)
   int *tile_first = nullptr, *tile_end = nullptr;
   long long tiles_cap = 0, ntiles = 0, n_tiled = 0;

@@ -80,12 +80,14 @@ struct PushChunks {
 long long push_grid(const PushChunks &pc, long long n);
 // wide (3D, FP32): deposit rounds over boxes four x1 cells wide instead of
 // two, and cell groups, for species spread over the grid at a few particles
-// per cell; blockbox: push_grid(pc, n) scratch boxes, merged into *jbox
-// after the launch
+// per cell; long_runs (with wide): the cells hold runs of several particles,
+// so lanes outside the cell groups deposit directly instead of in rounds;
+// blockbox: push_grid(pc, n) scratch boxes, merged into *jbox after the
+// launch
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
                          const Particles<Real> &p, const PushParams<Real> &q, const PushChunks &pc, bool wide,
-                         JBox *blockbox, int *err, hipStream_t st);
+                         bool long_runs, JBox *blockbox, int *err, hipStream_t st);
 // *jbox = union of the nbox per-workgroup boxes (atomic min/max into *jbox)
 void launch_merge_boxes(const JBox *blockbox, long long nbox, JBox *jbox, hipStream_t st);
 long long push_blocks(long long n, int K);

@@ -24,7 +24,7 @@ namespace relpic {
 
 // Workgroup b takes sort tile b's particles (b < pc.ntiles) or the b -
 // pc.ntiles-th run of 256 K particles after the first pc.nsorted.
-template <typename Real, int DIM, int W>
+template <typename Real, int DIM, int W, bool ROUNDS = true>
 __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real> f, HalfB<Real> Bh,
                                                              Particles<Real> p, PushParams<Real> q, PushChunks pc,
                                                              JBox *blockbox, int *err) {
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kPushBlock) void k_push_deposit(Geo g, Fields<Real>
   }
   if constexpr (W == 4) {
     __shared__ GroupLds grp;
-    push_chunk<Real, DIM, W, TILE>(g, f, Bh, p, q, c0, c1, blockbox + b, err, tile_raw, box, &grp);
+    push_chunk<Real, DIM, W, TILE, ROUNDS>(g, f, Bh, p, q, c0, c1, blockbox + b, err, tile_raw, box, &grp);
   } else {
     push_chunk<Real, DIM, W, TILE>(g, f, Bh, p, q, c0, c1, blockbox + b, err, tile_raw, box);
   }
@@ -108,11 +108,13 @@ long long push_grid(const PushChunks &pc, long long n) {
 template <typename Real>
 void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
                          const Particles<Real> &p, const PushParams<Real> &q, const PushChunks &pc, bool wide,
-                         JBox *blockbox, int *err, hipStream_t st) {
+                         bool long_runs, JBox *blockbox, int *err, hipStream_t st) {
   if (p.n <= 0) return;
   const unsigned blocks = (unsigned)push_grid(pc, p.n);
   // FP64 keeps the narrow rounds: the wide ones take it from two waves per SIMD to one
-  if (ndim == 3 && wide && sizeof(Real) == 4)
+  if (ndim == 3 && wide && sizeof(Real) == 4 && long_runs)
+    k_push_deposit<Real, 3, 4, false><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, pc, blockbox, err);
+  else if (ndim == 3 && wide && sizeof(Real) == 4)
     k_push_deposit<Real, 3, 4><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, pc, blockbox, err);
   else if (ndim == 3)
     k_push_deposit<Real, 3, 2><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, pc, blockbox, err);
@@ -427,7 +429,7 @@ void launch_permute(const Particles<Real> &src, const Particles<Real> &dst, cons
 #define RELPIC_INST_PART(Real)                                                                                   \
   template void launch_push_deposit<Real>(int, const Geo &, const Fields<Real> &, const HalfB<Real> &,          \
                                           const Particles<Real> &, const PushParams<Real> &, const PushChunks &, \
-                                          bool, JBox *, int *, hipStream_t);                                     \
+                                          bool, bool, JBox *, int *, hipStream_t);                               \
   template void launch_sort_keys<Real>(const Geo &, const Particles<Real> &, int, unsigned *, unsigned *,        \
                                        hipStream_t);                                                             \
   template void launch_permute<Real>(const Particles<Real> &, const Particles<Real> &, const int *, int *,      \

@@ -754,8 +754,11 @@ __device__ __forceinline__ bool deposit_groups(bool active, const Moved<Real> &m
 // of the cell groups: a chunk of at most 2048 particles whose current fits
 // the LDS tile in FP64 and whose runs of equal cells make at most 32 (K + 1)
 // groups of <= 8 particles is walked group by group (ceil(groups / 32)
-// iterations), others 256 particles per iteration in array order.
-template <typename Real, int DIM, int W = 2, int TILE = kTileBytes>
+// iterations), others 256 particles per iteration in array order.  ROUNDS
+// = false (species whose cells hold long runs): lanes that leave the group
+// sums deposit directly, without the wavefront rounds, whose code alone
+// costs the loop registers (SGPR spills reloaded every iteration).
+template <typename Real, int DIM, int W = 2, int TILE = kTileBytes, bool ROUNDS = true>
 __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, const HalfB<Real> &Bh,
                                            const Particles<Real> &p, const PushParams<Real> &q, long long chunk0,
                                            long long chunk1, JBox *mybox, int *err, unsigned char *tile_raw,
@@ -1125,7 +1128,11 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
     if constexpr (W == 4 && DIM == 3) {
       if (grouped) rest = deposit_groups<Real>(active, m, q, sk, gl->off);
     }
-    if (deposit_wave<Real, DIM, W>(rest, m, q, sk)) deposit_direct<Real, DIM>(m, q, sk);
+    if constexpr (W == 4 && DIM == 3 && !ROUNDS) {
+      if (rest) deposit_direct<Real, DIM>(m, q, sk);
+    } else {
+      if (deposit_wave<Real, DIM, W>(rest, m, q, sk)) deposit_direct<Real, DIM>(m, q, sk);
+    }
   }
 
   __builtin_amdgcn_s_setprio(1);
