@@ -318,7 +318,9 @@ def adjoint_main(args):
     print(json.dumps(out), flush=True)
 
 
-PUSH_PLASMA_KERNEL = "relpic::k_push_deposit<float, 3, 4>"  # the plasma's launch (tile-sorted, wide rounds)
+# the plasma's launch: tile-sorted, 8 particles per cell, so the wide kernel
+# with cell groups and without the wavefront rounds
+PUSH_PLASMA_KERNEL = "relpic::k_push_deposit<float, 3, 4, false>"
 TRAFFIC_FILE_PLASMA = os.path.join(ROOT, "profiles", "traffic_plasma3d_fp32.json")
 
 
