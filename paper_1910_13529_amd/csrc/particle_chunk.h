@@ -75,12 +75,11 @@ __device__ __forceinline__ void qw(Real d, Real w[3]) {
 // j of the middle point and its weights.
 template <typename Real>
 __device__ __forceinline__ int qw_half(int c, Real o, Real w[3]) {
-  if (o >= Real(0)) {
-    qw(o - Real(0.5), w);
-    return c;
-  }
-  qw(o + Real(0.5), w);
-  return c - 1;
+  // the offset from the nearer half point is selected first, so one set of
+  // weights is evaluated (not both branches and a select of each weight)
+  const bool up = o >= Real(0);
+  qw(up ? o - Real(0.5) : o + Real(0.5), w);
+  return up ? c : c - 1;
 }
 
 // Gather stencils of one particle: element offsets of the x1 columns and of
