@@ -112,7 +112,7 @@ void launch_push_deposit(int ndim, const Geo &g, const Fields<Real> &f, const Ha
   if (p.n <= 0) return;
   const unsigned blocks = (unsigned)push_grid(pc, p.n);
   // FP64 keeps the narrow rounds: the wide ones take it from two waves per SIMD to one
-  if (ndim == 3 && wide && sizeof(Real) == 4 && long_runs)
+  if (ndim == 3 && wide && long_runs)
     k_push_deposit<Real, 3, 4, false><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, pc, blockbox, err);
   else if (ndim == 3 && wide && sizeof(Real) == 4)
     k_push_deposit<Real, 3, 4><<<blocks, kPushBlock, 0, st>>>(g, f, Bh, p, q, pc, blockbox, err);

@@ -222,7 +222,7 @@ __device__ __forceinline__ int esirkepov_1d(Real o0, int sh, Real o1, Real S0[4]
 template <typename Real>
 struct Sink {
   Real *tile;        // 3 components x T1 x T2 x T3, or null
-  double *tile_d;    // the same current in FP64 words (FP32 runs), or null
+  double *tile_d;    // the current as FP64 words (an FP32 run that fits them; an FP64 run: tile), or null
   int t1, t2, t3;    // tile origin
   int T1, T2, T3;    // tile extents
   int tn;            // T1 * T2 * T3
@@ -881,7 +881,8 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       sk.T3 = (int)T3;
       sk.tn = (int)(T1 * T2 * T3);
       sk.tile = tile;
-      if (j64) sk.tile_d = reinterpret_cast<double *>(tile_raw);
+      // FP64 current words: the tile's own in an FP64 run
+      if (j64 || sizeof(Real) == 8) sk.tile_d = reinterpret_cast<double *>(tile_raw);
       Real *fE = tile + (j64 ? 6 : 3) * sk.tn;
       // J part cleared; E and B^n staged for the gather (zero outside the
       // window), one tile cell per thread and pass
@@ -1006,7 +1007,9 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
         sl.h1lo = bH[0] < c1;
         sl.h2lo = bH[1] < c2;
         sl.h3lo = DIM == 3 && bH[2] < c3;
-        const Real *ft = tile + (sk.tile_d ? 6 : 3) * sk.tn;
+        // E and B follow the current: 3 words per cell in its own precision,
+        // 6 when an FP32 run holds it in FP64
+        const Real *ft = tile + ((sizeof(Real) == 4 && sk.tile_d) ? 6 : 3) * sk.tn;
         E1 = interp_lds<Real, DIM, true, false, false>(sl, st.wN, st.wH, ft);
         E2 = interp_lds<Real, DIM, false, true, false>(sl, st.wN, st.wH, ft + sk.tn);
         E3 = interp_lds<Real, DIM, false, false, true>(sl, st.wN, st.wH, ft + 2 * sk.tn);
