@@ -220,12 +220,17 @@ relpic_status do_sort(relpic_sim *s, Species &sp) {
   // the cell groups take nearly every lane, the rest deposit directly
   sp.long_runs = tiles && ppc >= kLongRunsPpc;
   if (tiles) {
-    // chunks of 256 K particles, at most one tile's worth: a chunk then spans
-    // parts of at most two x1-neighbouring tiles, whose cells with the
-    // deposit halo (3D FP32: 20 x 8 x 8, FP64: 12 x 8 x 8) fit the push's
-    // LDS tile; used for particles appended after this sort
-    const double per_tile = ppc * (double)((s->ndim == 3 ? 16 : 4) << tx);
-    sp.K = per_tile >= 2048.0 ? 8 : (per_tile >= 1024.0 ? 4 : (per_tile >= 512.0 ? 2 : 1));
+    // chunks of 256 K particles.  2D: at most one tile's worth, so a chunk
+    // spans parts of at most two x1-neighbouring tiles, whose cells with the
+    // deposit halo fit the push's LDS tile.  3D (the sorted particles go one
+    // sort tile per workgroup below): chunks for the particles appended after
+    // this sort, at most one injected transverse block's worth, whose one x1
+    // cell with the halo (5 x 12 x 12 cells) fits the LDS tile with the
+    // current in FP64 words; a 1024-particle chunk of an 8-per-cell slab
+    // (5 x 12 x 20) does not
+    const double per_chunk =
+        s->ndim == 3 ? ppc * (double)(kInjBlock * kInjBlock) : ppc * (double)(4 << tx);
+    sp.K = per_chunk >= 2048.0 ? 8 : (per_chunk >= 1024.0 ? 4 : (per_chunk >= 512.0 ? 2 : 1));
     // the sorted particles are pushed one sort tile per workgroup: the
     // chunk's cells are exactly one tile (plus the particles' drift since)
     if (s->ndim == 3 && sp.n > 0) {
@@ -420,7 +425,7 @@ relpic_status do_steps(relpic_sim *s, long long nsteps) {
           break;
         }
         launch_inject_slab<Real>(s->ndim, g2, parts<Real>(sp), sp.id, sp.n, s->n[0] - 3, sp.ppc[0], sp.ppc[1],
-                                 sp.ppc[2], sp.uth, sp.seed, sp.inj_count, sp.next_id, sp.tile_keys, s->st);
+                                 sp.ppc[2], sp.uth, sp.seed, sp.inj_count, sp.next_id, s->st);
         sp.n += nnew;
         sp.next_id += nnew;
         sp.inj_count += (unsigned long long)nnew;

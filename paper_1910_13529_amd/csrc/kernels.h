@@ -152,11 +152,12 @@ void launch_gather_at_particles(int ndim, const Geo &g, const Fields<Real> &f, c
                                 long long first, long long count, double *out, hipStream_t st);
 
 // ---- plasma injection ------------------------------------------------------------
-// tile_order: store the slab's cells in tile-key order (3D, n2 and n3
-// multiples of 4); ids and momenta follow the row order either way
+// 3D stores the slab's cells in kInjBlock x kInjBlock transverse blocks, 2D
+// in row order; ids and momenta follow the row order either way
+constexpr int kInjBlock = 8;
 template <typename Real>
 void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, int *id, long long first, int win_cell, int ppc1,
                         int ppc2, int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
-                        long long id0, bool tile_order, hipStream_t st);
+                        long long id0, hipStream_t st);
 
 }  // namespace relpic

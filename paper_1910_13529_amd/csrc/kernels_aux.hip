@@ -240,15 +240,15 @@ __device__ __forceinline__ double normal_k(unsigned long long seed, unsigned lon
 // A slab of ppc1 x ppc2 x ppc3 particles per cell in window cell win_cell.
 // Particle r of the slab in row order (cell index i2 + n2 i3, then the
 // sub-lattice point) carries id id0 + r and the thermal momenta of counter
-// counter0 + r.  tiles = 0 stores them in that order; tiles = 1 (3D, n2 and
-// n3 multiples of 4) stores the cells in the order of the tile sort key
-// (4 x 4 transverse blocks, x3 block major; x3 major inside a block), so a
-// push chunk of freshly injected particles covers a compact box before the
-// next re-sort instead of a long x2 row.
+// counter0 + r.  2D stores them in that order; 3D stores the cells in
+// kInjBlock x kInjBlock transverse blocks (narrower at the x2 and x3 ends;
+// x2 blocks fastest, x2 fastest inside a block), so that a push chunk of one
+// block's particles covers a 5 x 12 x 12 deposit box, which the push holds
+// in LDS, instead of a long x2 row.
 template <typename Real>
 __global__ void k_inject(int ndim, Geo g, Particles<Real> p, int *id, long long first, int win_cell, int ppc1,
                          int ppc2, int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
-                         long long id0, int tiles) {
+                         long long id0) {
   const long long per = (long long)ppc1 * ppc2 * ppc3;
   const long long total = per * g.n2 * g.n3;
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -256,11 +256,17 @@ __global__ void k_inject(int ndim, Geo g, Particles<Real> p, int *id, long long 
   const long long q = t % per;
   const long long rc = t / per;  // the cell's place in storage order
   int i2, i3;
-  if (tiles) {
-    const long long T = rc >> 4;
-    const int L = (int)(rc & 15), nt2 = g.n2 >> 2;
-    i2 = (int)(T % nt2) * 4 + (L & 3);
-    i3 = (int)(T / nt2) * 4 + (L >> 2);
+  if (ndim == 3) {
+    // block row b3 (h3 rows of cells), then block b2 (w2 x h3 cells) in it
+    const long long rowcells = (long long)kInjBlock * g.n2;
+    const int b3 = (int)(rc / rowcells);
+    const int h3 = min(kInjBlock, g.n3 - kInjBlock * b3);
+    const long long rr = rc - (long long)b3 * rowcells;
+    const int b2 = (int)(rr / (kInjBlock * h3));
+    const int w2 = min(kInjBlock, g.n2 - kInjBlock * b2);
+    const int sb = (int)(rr - (long long)b2 * kInjBlock * h3);
+    i2 = kInjBlock * b2 + sb % w2;
+    i3 = kInjBlock * b3 + sb / w2;
   } else {
     i2 = (int)(rc % g.n2);
     i3 = (int)(rc / g.n2);
@@ -324,11 +330,10 @@ void launch_diag_gauss(int ndim, const Geo &g, const Fields<Real> &f, const Axia
 template <typename Real>
 void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, int *id, long long first, int win_cell, int ppc1,
                         int ppc2, int ppc3, double uth, unsigned long long seed, unsigned long long counter0,
-                        long long id0, bool tile_order, hipStream_t st) {
+                        long long id0, hipStream_t st) {
   const long long total = (long long)ppc1 * ppc2 * ppc3 * g.n2 * g.n3;
-  const int tiles = tile_order && ndim == 3 && g.n2 % 4 == 0 && g.n3 % 4 == 0 ? 1 : 0;
   k_inject<Real><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(ndim, g, p, id, first, win_cell, ppc1, ppc2, ppc3,
-                                                                    uth, seed, counter0, id0, tiles);
+                                                                    uth, seed, counter0, id0);
 }
 
 #define RELPIC_INST_AUX(Real)                                                                                      \
@@ -339,7 +344,7 @@ void launch_inject_slab(int ndim, const Geo &g, Particles<Real> p, int *id, long
   template void launch_diag_gauss<Real>(int, const Geo &, const Fields<Real> &, const Axial<double> &, double,      \
                                         double, const double *, const double *, int, double *, hipStream_t);       \
   template void launch_inject_slab<Real>(int, const Geo &, Particles<Real>, int *, long long, int, int, int, int,   \
-                                         double, unsigned long long, unsigned long long, long long, bool, hipStream_t);
+                                         double, unsigned long long, unsigned long long, long long, hipStream_t);
 
 RELPIC_INST_AUX(float)
 RELPIC_INST_AUX(double)

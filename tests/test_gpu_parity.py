@@ -211,15 +211,19 @@ def test_fused_field_update_availability():
         g3b.set_fused_fields(True)
 
 
-@pytest.mark.parametrize("precision,tol,xtol,utol,steps,sort_every", [
-    ("fp64", 1e-12, 1e-12, 1e-13, 13, 0), ("fp64", 1e-12, 1e-12, 1e-13, 30, 5), ("fp32", 1e-5, 2e-5, 2e-5, 30, 5)])
-def test_plasma_injection_window(precision, tol, xtol, utol, steps, sort_every):
+@pytest.mark.parametrize("precision,tol,xtol,utol,steps,sort_every,n", [
+    ("fp64", 1e-12, 1e-12, 1e-13, 13, 0, (40, 8, 8)), ("fp64", 1e-12, 1e-12, 1e-13, 30, 5, (40, 8, 8)),
+    ("fp32", 1e-5, 2e-5, 2e-5, 30, 5, (40, 8, 8)), ("fp64", 1e-12, 1e-12, 1e-13, 13, 0, (40, 12, 10)),
+    ("fp32", 1e-5, 2e-5, 2e-5, 30, 5, (40, 20, 13))])
+def test_plasma_injection_window(precision, tol, xtol, utol, steps, sort_every, n):
     # cold plasma ahead of a beam in the moving window: the window injects a
     # slab of 2x2x2 particles per cell at each shift, momenta from the shared
-    # counter-based generator.  With re-sorts every few steps the plasma is
-    # sorted by tiles of storage cells after the window has moved (ring
-    # buffer offset), and in FP32 deposits with the wide rounds.
-    n, dx, dt = (40, 8, 8), (0.02, 0.05, 0.05), 0.005
+    # counter-based generator, its cells stored in 8x8 transverse blocks
+    # (narrower at the ends on the ragged grids).  With re-sorts every few
+    # steps the plasma is sorted by tiles of storage cells after the window
+    # has moved (ring buffer offset), and in FP32 deposits with the wide
+    # rounds.
+    dx, dt = (0.02, 0.05, 0.05), 0.005
     cellp, offp, up = inputs.plasma_lattice(4, (2, 0, 0), (n[0] - 2, n[1], n[2]), (2, 2, 2), 1e-4)
     keep = cellp[:, 0] <= n[0] - 3
     cellp, offp, up = cellp[keep], offp[keep], up[keep]
