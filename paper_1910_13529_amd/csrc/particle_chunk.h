@@ -739,9 +739,14 @@ __device__ __forceinline__ bool deposit_groups(bool active, const Moved<Real> &m
   rs_level<Real, 20, 2>(r, lane, off);
   if (fb >= 0) {
     double *base = sk.tile_d + fb;
+    // all ten offsets are read before the first add: the adds could alias
+    // the table, so a read placed after an add would wait for it
     const int *lo = goff + (lane & 7) * 10;
+    int o[10];
 #pragma unroll
-    for (int u = 0; u < 10; ++u) lds_add(base + lo[u], (double)r[u]);
+    for (int u = 0; u < 10; ++u) o[u] = lo[u];
+#pragma unroll
+    for (int u = 0; u < 10; ++u) lds_add(base + o[u], (double)r[u]);
   }
   return active && !fits;
 }
