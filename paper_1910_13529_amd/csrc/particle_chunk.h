@@ -895,17 +895,22 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       const FastDiv d1{(unsigned)box[6], box[7]}, d2{(unsigned)box[8], box[9]};
       for (int r = tid; r < tn; r += kPushBlock) {
         const int q1 = (int)fdiv(d1, (unsigned)r), q2 = (int)fdiv(d2, (unsigned)q1);
-        const int col = col_of(g, sk.t1 + r - q1 * sk.T1);
+        const int a1 = r - q1 * sk.T1, a2 = q1 - q2 * sk.T2;
+        // the gather reads cells c - 2 .. c + 1 of each axis, so the box's
+        // last layer on each axis (old cells + 2) holds current only
+        const bool used = a1 < sk.T1 - 1 && a2 < sk.T2 - 1 && (DIM == 2 || q2 < sk.T3 - 1);
+        const int col = used ? col_of(g, sk.t1 + a1) : -1;
         Real v[6] = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0)};
         if (col >= 0) {
-          const long long id = (long long)g.n1 * (wrap_near(sk.t2 + q1 - q2 * sk.T2, g.n2) +
-                                                  (long long)g.n2 * wrap_near(sk.t3 + q2, g.n3)) + col;
-          v[0] = f.E1[id];
-          v[1] = f.E2[id];
-          v[2] = f.E3[id];
-          v[3] = Real(0.5) * (f.B1[id] + Bh.B1[id]);
-          v[4] = Real(0.5) * (f.B2[id] + Bh.B2[id]);
-          v[5] = Real(0.5) * (f.B3[id] + Bh.B3[id]);
+          const unsigned id =
+              (unsigned)g.n1 * (unsigned)(wrap_near(sk.t2 + a2, g.n2) + g.n2 * wrap_near(sk.t3 + q2, g.n3)) +
+              (unsigned)col;
+          v[0] = ld32(f.E1, id);
+          v[1] = ld32(f.E2, id);
+          v[2] = ld32(f.E3, id);
+          v[3] = Real(0.5) * (ld32(f.B1, id) + ld32(Bh.B1, id));
+          v[4] = Real(0.5) * (ld32(f.B2, id) + ld32(Bh.B2, id));
+          v[5] = Real(0.5) * (ld32(f.B3, id) + ld32(Bh.B3, id));
         }
         if (j64) {
 #pragma unroll
@@ -914,8 +919,10 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
 #pragma unroll
           for (int k = 0; k < 3; ++k) tile[k * tn + r] = Real(0);
         }
+        if (used) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) fE[k * tn + r] = v[k];
+          for (int k = 0; k < 6; ++k) fE[k * tn + r] = v[k];
+        }
       }
     }
   }
@@ -1155,11 +1162,11 @@ __device__ __forceinline__ void push_chunk(const Geo &g, const Fields<Real> &f, 
       const int q1 = (int)fdiv(d1, (unsigned)r), q2 = (int)fdiv(d2, (unsigned)q1);
       const int col = col_near(g, sk.t1 + r - q1 * sk.T1);
       if (col < 0) continue;
-      const long long id = (long long)g.n1 * (wrap_near(sk.t2 + q1 - q2 * sk.T2, g.n2) +
-                                              (long long)g.n2 * wrap_near(sk.t3 + q2, g.n3)) + col;
+      const unsigned id = (unsigned)g.n1 * (unsigned)(wrap_near(sk.t2 + q1 - q2 * sk.T2, g.n2) +
+                                                       g.n2 * wrap_near(sk.t3 + q2, g.n3)) + (unsigned)col;
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        if (v[k] != Real(0)) atomicAdd(sk.J[k] + id, v[k]);
+        if (v[k] != Real(0)) atomicAdd(&el32(sk.J[k], id), v[k]);
     }
   }
 }
