@@ -169,13 +169,16 @@ __device__ __forceinline__ Real interp_lds(const StaggerL &s, const Real wN[3][3
   const int dy = s.x2[1] - s.x2[0];
   const int z0 = DIM == 3 ? ((H3 && s.h3lo) ? s.x3[0] : s.x3[1]) : 0;
   const int dz = DIM == 3 ? s.x3[1] - s.x3[0] : 0;
+  // one lane pointer per component; the row and plane steps are the same
+  // for every component, so they stay a few uniform offsets
+  const Real *p0 = ft + (x0 + y0 + z0);
   Real acc = 0;
 #pragma unroll
   for (int c = 0; c < (DIM == 3 ? 3 : 1); ++c) {
     Real rc = 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const Real *row = ft + (x0 + y0 + b * dy + z0 + c * dz);
+      const Real *row = p0 + (b * dy + c * dz);
       Real r = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) r += (H1 ? wH[0][a] : wN[0][a]) * lds_ld(row + a);
